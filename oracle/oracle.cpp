@@ -1,0 +1,685 @@
+// FP64 CPU oracle of the null-collision electron-swarm method of
+// "Betaboltz: a Monte-Carlo simulation tool for gas scattering processes"
+// (Renda, Ciubotaru, Banu; arXiv 1901.08140).
+//
+// TEST INFRASTRUCTURE ONLY.  This file is the plain, slow reference that the HIP path is
+// checked against.  Only tests, the smoke check and the benchmark's CPU-baseline leg load
+// it; the product library never includes, links or calls it, and it shares no source with
+// the HIP path (its own Philox, table extension, grid, mover, kinematics and bookkeeping).
+//
+// Everything is IEEE binary64, built with -ffp-contract=off, one electron at a time, in
+// the order the paper describes the steps.  Where the paper is silent the reading used is
+// stated next to the code (the same readings are listed in the design notes).
+//
+// Parity pins (see tests/test_oracle_*.py): Philox known-answer vectors; closed-form
+// free-flight motion (E, E x B, cyclotron); energy conservation in free flight; the
+// elastic/inelastic energy formulas against exact two-body kinematics; the table
+// extension on power laws; the Maxwell-gas drift velocity eE/(m nu) and mean energy;
+// Drude drift with crossed B; diffusion and alpha/eta closed forms for constant rates;
+// channel-selection frequencies; the worked example's report identities.
+// Parity unpinned by a closed form: diffusion magnitudes (sigma, sigma_L, sigma_T) and
+// tallies for the synthetic argon/CO2 tables; those rest on GPU-vs-oracle parity.
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+namespace {
+
+// CODATA 2018 exact/recommended values.
+constexpr double kQe = 1.602176634e-19;     // C
+constexpr double kMe = 9.1093837015e-31;    // kg
+constexpr double kAmu = 1.66053906660e-27;  // kg
+constexpr double kPi = 3.14159265358979323846;
+
+enum Kind { ELASTIC = 0, EXCITATION = 1, IONIZATION = 2, ATTACHMENT = 3 };
+
+// ---------------------------------------------------------------------------------------
+// Philox4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw, SC'11).  A round maps
+// the counter (c0,c1,c2,c3) with key (k0,k1) to
+//   (hi(M1*c2) ^ c1 ^ k0, lo(M1*c2), hi(M0*c0) ^ c3 ^ k1, lo(M0*c0)),
+// with M0 = 0xD2511F53, M1 = 0xCD9E8D57; the key is advanced by the Weyl constants
+// (0x9E3779B9, 0xBB67AE85) between rounds.  Ten rounds.
+// ---------------------------------------------------------------------------------------
+struct Words { uint32_t w[4]; };
+
+Words philox4x32_10(const uint32_t ctr[4], const uint32_t key[2]) {
+  uint32_t c[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c[0];
+    const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c[2];
+    const uint32_t hi0 = static_cast<uint32_t>(p0 >> 32), lo0 = static_cast<uint32_t>(p0);
+    const uint32_t hi1 = static_cast<uint32_t>(p1 >> 32), lo1 = static_cast<uint32_t>(p1);
+    const uint32_t n0 = hi1 ^ c[1] ^ k0;
+    const uint32_t n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+  }
+  Words out;
+  for (int i = 0; i < 4; ++i) out.w[i] = c[i];
+  return out;
+}
+
+// Stream layout: key = (lo32(seed), hi32(seed)); counter = (block, tag, lo32(id), hi32(id)).
+enum Tag : uint32_t { TRIAL_HI = 0, TRIAL_LO = 1, SCAT_HI = 2, SCAT_LO = 3, INIT_HI = 4,
+                      INIT_LO = 5, CHILD_ID = 6 };
+
+Words stream_block(uint64_t seed, uint64_t id, uint32_t tag, uint32_t block) {
+  const uint32_t ctr[4] = {block, tag, static_cast<uint32_t>(id), static_cast<uint32_t>(id >> 32)};
+  const uint32_t key[2] = {static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32)};
+  return philox4x32_10(ctr, key);
+}
+
+// A uniform in [0,1) with 53 random bits: the 32 bits of the HI word on top of the upper
+// 21 bits of the LO word.  (Its top 24 bits are the single-precision uniform hi >> 8.)
+double uniform53(uint32_t hi, uint32_t lo) {
+  const uint64_t m = (static_cast<uint64_t>(hi) << 21) | static_cast<uint64_t>(lo >> 11);
+  return static_cast<double>(m) * 0x1.0p-53;
+}
+
+struct Vec3 { double x, y, z; };
+Vec3 add(Vec3 a, Vec3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+Vec3 sub(Vec3 a, Vec3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+Vec3 scale(Vec3 a, double s) { return {a.x * s, a.y * s, a.z * s}; }
+double dot(Vec3 a, Vec3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+Vec3 cross(Vec3 a, Vec3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+
+// Isotropic unit vector from two uniforms: cos(Theta) = 1 - 2u, Phi = 2 pi u'.
+Vec3 iso_direction(double u_cos, double u_phi) {
+  const double ct = 1.0 - 2.0 * u_cos;
+  const double st = std::sqrt(std::max(0.0, (1.0 - ct) * (1.0 + ct)));
+  const double ph = 2.0 * kPi * u_phi;
+  return {st * std::cos(ph), st * std::sin(ph), ct};
+}
+
+// ---------------------------------------------------------------------------------------
+// Gas model.
+// ---------------------------------------------------------------------------------------
+struct Channel {
+  int kind;
+  double threshold_eV;
+  std::vector<double> e, s;   // raw table points (eV, m^2)
+  int component;
+  double mass_kg;             // target mass M
+  double density;             // n_k = fraction_k * N
+};
+
+// Raw cross-section with the paper's table extension (section "Extension of the
+// cross-section tables"):
+//  * elastic, left of the first point: the first point's value (constant);
+//  * inelastic: zero below the threshold; if the table starts above the threshold, the
+//    point (threshold, 0) is put in front of it (reading of the truncation rule);
+//  * right of the last point: the power law A eps^K through the last two points,
+//    K = ln(s2/s1)/ln(e2/e1), A = s2/e2^K (zero if either value is zero);
+//  * inside the table: linear interpolation in (eps, sigma).
+double sigma_raw(const Channel& ch, double eps) {
+  std::vector<double> e = ch.e, s = ch.s;
+  if (ch.kind != ELASTIC) {
+    if (eps < ch.threshold_eV) return 0.0;
+    if (e.front() > ch.threshold_eV) {
+      e.insert(e.begin(), ch.threshold_eV);
+      s.insert(s.begin(), 0.0);
+    }
+  }
+  const size_t n = e.size();
+  if (eps <= e[0]) return s[0];
+  if (eps > e[n - 1]) {
+    const double e1 = e[n - 2], e2 = e[n - 1], s1 = s[n - 2], s2 = s[n - 1];
+    if (!(s1 > 0.0) || !(s2 > 0.0)) return 0.0;
+    const double K = std::log(s2 / s1) / std::log(e2 / e1);
+    const double A = s2 / std::pow(e2, K);
+    return A * std::pow(eps, K);
+  }
+  // first index i with e[i] >= eps; the segment is [i-1, i]
+  size_t i = 1;
+  while (e[i] < eps) ++i;
+  const double t = (eps - e[i - 1]) / (e[i] - e[i - 1]);
+  return s[i - 1] + (s[i] - s[i - 1]) * t;
+}
+
+// Rate of one channel, the summand of the paper's eq. (frequency):
+// nu_c(eps) = n_k sigma_c(eps) sqrt(2 eps / m), eps converted from eV to joule.
+double rate_raw(const Channel& ch, double eps) {
+  return ch.density * sigma_raw(ch, eps) * std::sqrt(2.0 * eps * kQe / kMe);
+}
+
+struct Params {
+  double E, B, B_angle, N, T, eps0;
+  int secondaries;  // 0 dummy (counted only), 1 real (children created / electrons removed)
+  int grid_P, grid_emin, grid_emax;
+  double user_majorant;
+};
+
+struct Model {
+  Params p;
+  std::vector<Channel> ch;
+  int G;
+  std::vector<double> nodes;   // G node energies (eV)
+  std::vector<double> C;       // cumulative rate, channel-major: C[c*G + g]
+  double majorant;
+  double node_min, node_max;   // 2^emin, 2^emax
+  // field frame
+  double omega;                // e B / m
+  Vec3 a, bhat, vD;
+};
+
+// Octave grid node g = o*P + i has energy 2^(emin+o) * (1 + i/P); node G-1 = 2^emax.
+double node_energy(const Params& p, int g) {
+  const int o = g / p.grid_P, i = g % p.grid_P;
+  return std::ldexp(1.0 + static_cast<double>(i) / p.grid_P, p.grid_emin + o);
+}
+
+// Linear interpolation of a node array at eps (the reading of the paper's per-collision
+// "linear interpolation" after resampling on the octave grid).  Split eps = 2^(ex-1) (1+f)
+// exactly with frexp; i = floor(f P), w = f P - i, g = (ex-1-emin) P + i.
+// Below the grid: F[0].  At or above the top node: F[G-1] (counted as over the cap).
+double interp(const Model& m, const double* F, double eps, bool* over) {
+  if (over) *over = false;
+  if (eps < m.node_min) return F[0];
+  if (eps >= m.node_max) {
+    if (over) *over = true;
+    return F[m.G - 1];
+  }
+  int ex = 0;
+  const double mant = std::frexp(eps, &ex);        // eps = mant * 2^ex, mant in [0.5, 1)
+  const double f = 2.0 * mant - 1.0;               // in [0, 1), exact
+  const double fP = f * m.p.grid_P;                // exact (P is a power of two)
+  const double fi = std::floor(fP);
+  const double w = fP - fi;                        // exact
+  const int g = (ex - 1 - m.p.grid_emin) * m.p.grid_P + static_cast<int>(fi);
+  return F[g] + w * (F[g + 1] - F[g]);
+}
+
+double nu_total(const Model& m, double eps, bool* over = nullptr) {
+  const int nc = static_cast<int>(m.ch.size());
+  return interp(m, &m.C[static_cast<size_t>(nc - 1) * m.G], eps, over);
+}
+
+// Free flight in uniform static E and B (classical motion; the paper's
+// UniformFieldClassic).  E-frame: z along E, B = |B| (sin th, 0, cos th).  The electron
+// charge is -e, so a = -(e/m) E z^ and the velocity rotates as dv/dt = a + omega b^ x v.
+//   v(T) = v_par0 + a_par T + vD + u0 cos(wT) + (b^ x u0) sin(wT)
+//   r(T) = r0 + (v_par0 + vD) T + a_par T^2/2 + [u0 sin(wT) + (b^ x u0)(1 - cos wT)]/w
+// with vD = E x B / B^2 and u0 = v0 - v_par0 - vD;  1 - cos(wT) is taken as 2 sin^2(wT/2).
+void move(const Model& m, Vec3 r0, Vec3 v0, double T, Vec3* r, Vec3* v) {
+  if (m.p.B == 0.0) {
+    if (v) *v = add(v0, scale(m.a, T));
+    if (r) *r = add(add(r0, scale(v0, T)), scale(m.a, 0.5 * T * T));
+    return;
+  }
+  const Vec3 b = m.bhat;
+  const Vec3 vpar0 = scale(b, dot(v0, b));
+  const Vec3 apar = scale(b, dot(m.a, b));
+  const Vec3 u0 = sub(sub(v0, vpar0), m.vD);
+  const Vec3 bxu = cross(b, u0);
+  const double wt = m.omega * T;
+  const double c = std::cos(wt), s = std::sin(wt);
+  if (v) *v = add(add(add(vpar0, scale(apar, T)), m.vD), add(scale(u0, c), scale(bxu, s)));
+  if (r) {
+    const double sh = std::sin(0.5 * wt);
+    const double one_minus_c = 2.0 * sh * sh;
+    Vec3 rr = add(r0, scale(add(vpar0, m.vD), T));
+    rr = add(rr, scale(apar, 0.5 * T * T));
+    rr = add(rr, scale(add(scale(u0, s), scale(bxu, one_minus_c)), 1.0 / m.omega));
+    *r = rr;
+  }
+}
+
+double energy_eV(Vec3 v) { return 0.5 * kMe * dot(v, v) / kQe; }
+double speed_from_energy(double eps) { return std::sqrt(2.0 * eps * kQe / kMe); }
+
+// Energy after an elastic collision (Fraser-Mathieson, the paper's eq. delta_energy_ela).
+double energy_after_elastic(double eps, double cos_t, double M) {
+  const double m = kMe;
+  return eps * (1.0 - 2.0 * m * M * (1.0 - cos_t) / ((m + M) * (m + M)));
+}
+
+// Energy after an inelastic collision with threshold eps_k (eq. delta_energy_ine).
+// The square-root argument is clamped at zero; the caller has already rejected events
+// below the kinematic onset eps_k (m+M)/M.
+double energy_after_inelastic(double eps, double eps_k, double cos_t, double M) {
+  const double m = kMe;
+  const double ratio = eps_k / eps;
+  const double root = std::sqrt(std::max(0.0, 1.0 - (m + M) / M * ratio));
+  return eps * (1.0 - M / (m + M) * ratio + 2.0 * m * M / ((m + M) * (m + M)) * (root * cos_t - 1.0));
+}
+
+// ---------------------------------------------------------------------------------------
+// Per-electron simulation.
+// ---------------------------------------------------------------------------------------
+constexpr uint32_t FLAG_FINISHED = 1, FLAG_ATTACHED = 2, FLAG_STUCK = 4;
+constexpr uint64_t kMaxBlocks = 0x7fffffffull;   // per-electron cap on trial blocks
+constexpr int EV_REAL = 1, EV_FORBIDDEN = 2;
+
+struct Record {
+  uint64_t id;
+  uint32_t flags, k_start, k_end, G, D, n_forbidden, n_over, pad;
+  uint64_t n_null, blocks;
+  double r[3], t, sum_eps, sum_epsp;
+};
+
+struct Event {
+  uint64_t id;
+  int32_t type, channel;
+  uint32_t k, block, sub, pad;
+  double eps, epsp, t, r[3];
+};
+
+struct Electron {
+  uint64_t id;
+  Vec3 r, v;
+  double t;
+  uint32_t k;
+};
+
+struct RunCtx {
+  const Model* m;
+  uint64_t seed;
+  uint32_t n_coll;
+  std::vector<uint64_t> trace_ids;
+  int max_events;
+  std::atomic<int64_t>* created;
+  int64_t capacity;
+  std::atomic<int>* capacity_error;
+};
+
+bool traced(const RunCtx& cx, uint64_t id) {
+  return std::find(cx.trace_ids.begin(), cx.trace_ids.end(), id) != cx.trace_ids.end();
+}
+
+// One electron from its birth state until it has made n_coll real collisions (counting
+// the ones inherited from its lineage), is attached (real secondaries mode) or exceeds the
+// block cap.  Children (real secondaries mode) are appended to `children`.
+Record simulate(const RunCtx& cx, const Electron& e0, std::vector<Electron>& children,
+                std::vector<Event>& events) {
+  const Model& m = *cx.m;
+  const int nc = static_cast<int>(m.ch.size());
+  const double nup = m.majorant;
+  Record rec{};
+  rec.id = e0.id;
+  rec.k_start = e0.k;
+  Vec3 r = e0.r, v = e0.v;   // anchor: state right after the last real collision
+  double t = e0.t;
+  double T = 0.0;            // flight time since the anchor
+  uint32_t k = e0.k;
+  uint64_t block = 0;
+  const bool tr = !cx.trace_ids.empty() && traced(cx, e0.id);
+  int n_ev = 0;
+  bool alive = true;
+
+  while (alive && k < cx.n_coll) {
+    if (block >= kMaxBlocks) { rec.flags |= FLAG_STUCK; break; }
+    const uint32_t blk = static_cast<uint32_t>(block);
+    const Words hi = stream_block(cx.seed, e0.id, TRIAL_HI, blk);
+    const Words lo = stream_block(cx.seed, e0.id, TRIAL_LO, blk);
+    ++block;
+    ++rec.blocks;
+    // A block holds two candidate trials; a non-null outcome (real or forbidden) of the
+    // first ends the block and its second trial is not used.
+    for (int sub = 0; sub < 2; ++sub) {
+      const double u_f = uniform53(hi.w[2 * sub], lo.w[2 * sub]);
+      const double u_r = uniform53(hi.w[2 * sub + 1], lo.w[2 * sub + 1]);
+      // Flight time against the constant trial frequency nu' (eq. random_time).
+      T += -std::log(1.0 - u_f) / nup;
+      Vec3 vT;
+      move(m, r, v, T, nullptr, &vT);
+      const double eps = energy_eV(vT);
+      // Null test (eq. null_fraction): null when R > nu(eps)/nu'; here real iff
+      // R nu' < nu(eps) (strict), with the same R choosing the channel below.
+      const double x = u_r * nup;
+      bool over = false;
+      const double nu = nu_total(m, eps, &over);
+      if (!(x < nu)) { ++rec.n_null; continue; }
+      int c = 0;
+      while (c < nc - 1 && !(x < interp(m, &m.C[static_cast<size_t>(c) * m.G], eps, nullptr))) ++c;
+      const Channel& chn = m.ch[c];
+      const double M = chn.mass_kg;
+      if ((chn.kind == EXCITATION || chn.kind == IONIZATION) &&
+          eps < chn.threshold_eV * ((kMe + M) / M)) {
+        // Kinematically forbidden just above threshold (grid smearing): treated as null.
+        ++rec.n_forbidden;
+        if (tr && n_ev < cx.max_events) {
+          Event ev{};
+          ev.id = e0.id; ev.type = EV_FORBIDDEN; ev.channel = c; ev.k = k;
+          ev.block = blk; ev.sub = sub; ev.eps = eps; ev.epsp = eps;
+          ev.t = t + T; ev.r[0] = r.x; ev.r[1] = r.y; ev.r[2] = r.z;
+          events.push_back(ev);
+        }
+        break;
+      }
+      // Real collision.
+      if (over) ++rec.n_over;
+      Vec3 rT;
+      move(m, r, v, T, &rT, nullptr);
+      const Words sh = stream_block(cx.seed, e0.id, SCAT_HI, k);
+      const Words sl = stream_block(cx.seed, e0.id, SCAT_LO, k);
+      const Vec3 n = iso_direction(uniform53(sh.w[0], sl.w[0]), uniform53(sh.w[1], sl.w[1]));
+      const double v2 = dot(vT, vT);
+      const double cos_t = v2 > 0.0 ? dot(n, vT) / std::sqrt(v2) : 0.0;
+      double epsp;
+      if (chn.kind == ELASTIC) {
+        epsp = energy_after_elastic(eps, cos_t, M);
+      } else if (chn.kind == ATTACHMENT) {
+        epsp = 0.0;   // plastic collision: all the energy is transferred
+      } else {
+        epsp = energy_after_inelastic(eps, chn.threshold_eV, cos_t, M);
+      }
+      epsp = std::max(epsp, 0.0);
+      rec.sum_eps += eps;
+      if (chn.kind == IONIZATION) {
+        epsp *= 0.5;   // equal sharing with the ejected electron
+        ++rec.G;
+        if (m.p.secondaries == 1) {
+          const Words cw = stream_block(cx.seed, e0.id, CHILD_ID, k);
+          Electron child;
+          child.id = (static_cast<uint64_t>(cw.w[0]) | (static_cast<uint64_t>(cw.w[1]) << 32)) |
+                     (1ull << 63);
+          child.r = rT;
+          child.t = t + T;
+          child.k = k + 1;
+          child.v = scale(iso_direction(uniform53(sh.w[2], sl.w[2]), uniform53(sh.w[3], sl.w[3])),
+                          speed_from_energy(epsp));
+          const int64_t n_created = cx.created->fetch_add(1) + 1;
+          if (n_created > cx.capacity) {
+            cx.capacity_error->store(1);
+          } else {
+            children.push_back(child);
+          }
+        }
+      } else if (chn.kind == ATTACHMENT) {
+        ++rec.D;
+        if (m.p.secondaries == 1) alive = false;
+      }
+      rec.sum_epsp += epsp;
+      if (tr && n_ev < cx.max_events) {
+        Event ev{};
+        ev.id = e0.id; ev.type = EV_REAL; ev.channel = c; ev.k = k;
+        ev.block = blk; ev.sub = sub; ev.eps = eps; ev.epsp = epsp;
+        ev.t = t + T; ev.r[0] = rT.x; ev.r[1] = rT.y; ev.r[2] = rT.z;
+        events.push_back(ev);
+        ++n_ev;
+      }
+      ++k;
+      r = rT;
+      t += T;
+      T = 0.0;
+      v = scale(n, speed_from_energy(epsp));
+      break;
+    }
+  }
+  rec.k_end = k;
+  if (!alive) rec.flags |= FLAG_ATTACHED;
+  else if (k >= cx.n_coll) rec.flags |= FLAG_FINISHED;
+  rec.r[0] = r.x; rec.r[1] = r.y; rec.r[2] = r.z;
+  rec.t = t;
+  return rec;
+}
+
+Electron primary(const Model& m, uint64_t seed, uint64_t id) {
+  const Words hi = stream_block(seed, id, INIT_HI, 0);
+  const Words lo = stream_block(seed, id, INIT_LO, 0);
+  Electron e;
+  e.id = id;
+  e.r = {0.0, 0.0, 0.0};
+  e.t = 0.0;
+  e.k = 0;
+  e.v = scale(iso_direction(uniform53(hi.w[0], lo.w[0]), uniform53(hi.w[1], lo.w[1])),
+              speed_from_energy(m.p.eps0));
+  return e;
+}
+
+struct RunResult {
+  std::vector<Record> records;
+  std::vector<Event> events;
+  int status;
+};
+
+}  // namespace
+
+// =======================================================================================
+// C ABI used by the Python wrapper (oracle/__init__.py).
+// =======================================================================================
+extern "C" {
+
+struct or_channel { int32_t kind; double threshold_eV; int32_t n_points; const double* energy_eV;
+                    const double* sigma_m2; };
+struct or_component { double mass_amu; double fraction; int32_t n_channels; const or_channel* channels; };
+struct or_params { double E_V_per_m, B_T, B_angle_rad, N_per_m3, T_K, init_energy_eV;
+                   int32_t secondaries, grid_P, grid_emin, grid_emax; double user_majorant; };
+
+enum { OR_OK = 0, OR_INVALID = -1, OR_CAPACITY = -3 };
+
+void or_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
+  const Words w = philox4x32_10(ctr, key);
+  for (int i = 0; i < 4; ++i) out[i] = w.w[i];
+}
+
+void or_stream_block(uint64_t seed, uint64_t id, uint32_t tag, uint32_t block, uint32_t* out) {
+  const Words w = stream_block(seed, id, tag, block);
+  for (int i = 0; i < 4; ++i) out[i] = w.w[i];
+}
+
+double or_uniform53(uint32_t hi, uint32_t lo) { return uniform53(hi, lo); }
+
+void* or_create(const or_component* comps, int32_t n_comps, const or_params* p, int32_t* status) {
+  *status = OR_INVALID;
+  if (!comps || n_comps <= 0 || !p) return nullptr;
+  if (!(p->N_per_m3 > 0.0) || !(p->E_V_per_m >= 0.0) || !(p->B_T >= 0.0) || !(p->init_energy_eV >= 0.0))
+    return nullptr;
+  if (p->grid_P <= 0 || (p->grid_P & (p->grid_P - 1)) != 0 || p->grid_emax <= p->grid_emin) return nullptr;
+  double fsum = 0.0;
+  auto* m = new Model();
+  m->p = {p->E_V_per_m, p->B_T, p->B_angle_rad, p->N_per_m3, p->T_K, p->init_energy_eV,
+          p->secondaries, p->grid_P, p->grid_emin, p->grid_emax, p->user_majorant};
+  for (int k = 0; k < n_comps; ++k) {
+    const or_component& c = comps[k];
+    if (!(c.mass_amu > 0.0) || !(c.fraction >= 0.0) || c.n_channels <= 0) { delete m; return nullptr; }
+    fsum += c.fraction;
+    for (int j = 0; j < c.n_channels; ++j) {
+      const or_channel& q = c.channels[j];
+      if (q.n_points < 2 || q.kind < 0 || q.kind > 3 || !(q.threshold_eV >= 0.0)) { delete m; return nullptr; }
+      Channel ch;
+      ch.kind = q.kind;
+      ch.threshold_eV = q.threshold_eV;
+      ch.e.assign(q.energy_eV, q.energy_eV + q.n_points);
+      ch.s.assign(q.sigma_m2, q.sigma_m2 + q.n_points);
+      for (int i = 0; i < q.n_points; ++i) {
+        if (!(ch.e[i] > 0.0) || !std::isfinite(ch.e[i]) || !(ch.s[i] >= 0.0) || !std::isfinite(ch.s[i])) {
+          delete m; return nullptr;
+        }
+        if (i > 0 && !(ch.e[i] > ch.e[i - 1])) { delete m; return nullptr; }
+      }
+      ch.component = k;
+      ch.mass_kg = c.mass_amu * kAmu;
+      ch.density = c.fraction * p->N_per_m3;
+      m->ch.push_back(std::move(ch));
+    }
+  }
+  if (std::fabs(fsum - 1.0) > 1e-9) { delete m; return nullptr; }
+  const int nc = static_cast<int>(m->ch.size());
+  m->G = (p->grid_emax - p->grid_emin) * p->grid_P + 1;
+  m->nodes.resize(m->G);
+  m->C.assign(static_cast<size_t>(nc) * m->G, 0.0);
+  double numax = 0.0;
+  for (int g = 0; g < m->G; ++g) {
+    const double eps = node_energy(m->p, g);
+    m->nodes[g] = eps;
+    double acc = 0.0;
+    for (int c = 0; c < nc; ++c) {
+      acc += rate_raw(m->ch[c], eps);       // running sum in channel order (eq. frequency)
+      m->C[static_cast<size_t>(c) * m->G + g] = acc;
+    }
+    if (!(acc > 0.0)) { delete m; return nullptr; }   // every electron must be able to collide
+    numax = std::max(numax, acc);
+  }
+  // Constant trial frequency (the paper's LazyTrialFrequency: the table maximum) raised by
+  // 2^-20 so that nu(eps) <= nu' holds after interpolation; a user value must not be below
+  // the maximum (the paper's FixedTrialFrequency refuses such a value).
+  if (p->user_majorant > 0.0) {
+    if (p->user_majorant < numax) { delete m; return nullptr; }
+    m->majorant = p->user_majorant;
+  } else {
+    m->majorant = (1.0 + 0x1.0p-20) * numax;
+  }
+  m->node_min = std::ldexp(1.0, p->grid_emin);
+  m->node_max = std::ldexp(1.0, p->grid_emax);
+  m->omega = kQe * p->B_T / kMe;
+  m->a = {0.0, 0.0, -kQe * p->E_V_per_m / kMe};
+  m->bhat = {std::sin(p->B_angle_rad), 0.0, std::cos(p->B_angle_rad)};
+  if (p->B_T > 0.0) {
+    const Vec3 Evec{0.0, 0.0, p->E_V_per_m};
+    const Vec3 Bvec = scale(m->bhat, p->B_T);
+    m->vD = scale(cross(Evec, Bvec), 1.0 / (p->B_T * p->B_T));
+  } else {
+    m->vD = {0.0, 0.0, 0.0};
+  }
+  *status = OR_OK;
+  return m;
+}
+
+void or_destroy(void* h) { delete static_cast<Model*>(h); }
+
+int32_t or_n_channels(void* h) { return static_cast<int32_t>(static_cast<Model*>(h)->ch.size()); }
+int32_t or_grid_size(void* h) { return static_cast<Model*>(h)->G; }
+double or_majorant(void* h) { return static_cast<Model*>(h)->majorant; }
+
+void or_tables(void* h, double* nodes, double* C) {
+  const Model& m = *static_cast<Model*>(h);
+  std::copy(m.nodes.begin(), m.nodes.end(), nodes);
+  std::copy(m.C.begin(), m.C.end(), C);
+}
+
+double or_sigma_raw(void* h, int32_t c, double eps) { return sigma_raw(static_cast<Model*>(h)->ch[c], eps); }
+double or_rate_raw_total(void* h, double eps) {
+  const Model& m = *static_cast<Model*>(h);
+  double acc = 0.0;
+  for (const auto& ch : m.ch) acc += rate_raw(ch, eps);
+  return acc;
+}
+double or_nu_grid(void* h, double eps, int32_t* over) {
+  bool ov = false;
+  const double v = nu_total(*static_cast<Model*>(h), eps, &ov);
+  if (over) *over = ov ? 1 : 0;
+  return v;
+}
+double or_channel_cum(void* h, int32_t c, double eps) {
+  const Model& m = *static_cast<Model*>(h);
+  return interp(m, &m.C[static_cast<size_t>(c) * m.G], eps, nullptr);
+}
+// Real/null decision and channel for a given energy and x = R nu'; -1 means null.
+int32_t or_select(void* h, double eps, double x) {
+  const Model& m = *static_cast<Model*>(h);
+  const int nc = static_cast<int>(m.ch.size());
+  if (!(x < nu_total(m, eps))) return -1;
+  int c = 0;
+  while (c < nc - 1 && !(x < interp(m, &m.C[static_cast<size_t>(c) * m.G], eps, nullptr))) ++c;
+  return c;
+}
+
+void or_move(void* h, const double* r0, const double* v0, double T, double* r, double* v) {
+  const Model& m = *static_cast<Model*>(h);
+  Vec3 rr, vv;
+  move(m, {r0[0], r0[1], r0[2]}, {v0[0], v0[1], v0[2]}, T, &rr, &vv);
+  r[0] = rr.x; r[1] = rr.y; r[2] = rr.z;
+  v[0] = vv.x; v[1] = vv.y; v[2] = vv.z;
+}
+
+double or_energy_after(int32_t kind, double eps, double eps_k, double cos_t, double mass_amu) {
+  const double M = mass_amu * kAmu;
+  if (kind == ELASTIC) return energy_after_elastic(eps, cos_t, M);
+  if (kind == ATTACHMENT) return 0.0;
+  return energy_after_inelastic(eps, eps_k, cos_t, M);
+}
+
+double or_const(int32_t which) {
+  switch (which) {
+    case 0: return kQe;
+    case 1: return kMe;
+    case 2: return kAmu;
+    default: return 0.0;
+  }
+}
+
+// Run n_electrons primaries (ids 0..n-1) for n_collisions real collisions each, on
+// n_threads host threads.  Returns a result handle (records sorted by id).
+void* or_run(void* h, int64_t n_electrons, int64_t n_collisions, uint64_t seed, int32_t n_threads,
+             int64_t capacity, const uint64_t* trace_ids, int32_t n_trace, int32_t max_events,
+             int64_t first_id) {
+  const Model& m = *static_cast<Model*>(h);
+  auto* res = new RunResult();
+  res->status = OR_OK;
+  if (n_electrons < 0 || n_collisions < 0 || n_collisions > 0xffffffffLL) {
+    res->status = OR_INVALID;
+    return res;
+  }
+  std::atomic<int64_t> created(n_electrons);
+  std::atomic<int> cap_err(0);
+  RunCtx cx;
+  cx.m = &m;
+  cx.seed = seed;
+  cx.n_coll = static_cast<uint32_t>(n_collisions);
+  if (trace_ids && n_trace > 0) cx.trace_ids.assign(trace_ids, trace_ids + n_trace);
+  cx.max_events = max_events;
+  cx.created = &created;
+  cx.capacity = capacity > 0 ? capacity : (int64_t{1} << 62);
+  cx.capacity_error = &cap_err;
+  if (n_threads <= 0) n_threads = 1;
+  std::atomic<int64_t> next(0);
+  std::mutex mu;
+  auto worker = [&]() {
+    std::vector<Record> recs;
+    std::vector<Event> evs;
+    std::vector<Electron> stack;
+    for (;;) {
+      const int64_t i = next.fetch_add(1);
+      if (i >= n_electrons) break;
+      stack.push_back(primary(m, seed, static_cast<uint64_t>(first_id + i)));
+      while (!stack.empty()) {
+        const Electron e = stack.back();
+        stack.pop_back();
+        recs.push_back(simulate(cx, e, stack, evs));
+      }
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    res->records.insert(res->records.end(), recs.begin(), recs.end());
+    res->events.insert(res->events.end(), evs.begin(), evs.end());
+  };
+  std::vector<std::thread> th;
+  for (int i = 0; i < n_threads; ++i) th.emplace_back(worker);
+  for (auto& t : th) t.join();
+  std::sort(res->records.begin(), res->records.end(),
+            [](const Record& a, const Record& b) { return a.id < b.id; });
+  std::stable_sort(res->events.begin(), res->events.end(), [](const Event& a, const Event& b) {
+    if (a.id != b.id) return a.id < b.id;
+    if (a.k != b.k) return a.k < b.k;
+    return a.block < b.block;
+  });
+  if (cap_err.load()) res->status = OR_CAPACITY;
+  return res;
+}
+
+int32_t or_run_status(void* r) { return static_cast<RunResult*>(r)->status; }
+int64_t or_run_count(void* r) { return static_cast<int64_t>(static_cast<RunResult*>(r)->records.size()); }
+int64_t or_run_event_count(void* r) { return static_cast<int64_t>(static_cast<RunResult*>(r)->events.size()); }
+int32_t or_record_size() { return static_cast<int32_t>(sizeof(Record)); }
+int32_t or_event_size() { return static_cast<int32_t>(sizeof(Event)); }
+void or_run_copy(void* r, void* out) {
+  const auto& v = static_cast<RunResult*>(r)->records;
+  if (!v.empty()) std::memcpy(out, v.data(), v.size() * sizeof(Record));
+}
+void or_run_copy_events(void* r, void* out) {
+  const auto& v = static_cast<RunResult*>(r)->events;
+  if (!v.empty()) std::memcpy(out, v.data(), v.size() * sizeof(Event));
+}
+void or_run_free(void* r) { delete static_cast<RunResult*>(r); }
+
+}  // extern "C"
