@@ -1,0 +1,227 @@
+#!/usr/bin/env python3
+"""Benchmark: real collisions/s of the electron-swarm hot path on one MI355X.
+
+Workload (the argon-like E/N sweep): 32 swarm instances of a synthetic argon-like gas at
+E/N log-spaced over 1-1000 Td, B = 0, 100,000 electrons x 20,000 real collisions each,
+seed 0, dummy ionisation (6.4e10 real collisions per step).
+
+A step is one batched launch of all 32 instances in FP32-mixed precision: one persistent
+kernel (launch shape from the autotuner) plus the tally reductions, replayed from a
+hipGraph.  `value` = real collisions per second over the timed steps.  Also measured once:
+the same workload as 32 plain FP64 single-instance runs, the FP32-vs-FP64 tally agreement,
+a short serving run (p50/p99 request latency), and the FP64 CPU oracle on a bounded sample
+on the host cores.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic VALU work per unit (lane-instruction slots; transcendental and 32-bit integer
+# multiply instructions count 4 slots each, as they issue at quarter rate), FP32-mixed path,
+# B = 0.  Trial: half a Philox4x32-10 call (10 rounds x (2 mul-hi/lo x 4 + 2 xor)), two
+# uniforms, -ln(1-u)/nu', v_z and |v|^2 and eps, the octave-grid position from the bits,
+# the interpolated rate, x = R nu' and the compare.  Real collision: channel search,
+# onset compare, one Philox call, isotropic direction, cos(theta), energy transfer, FP64
+# position/time/energy-sum updates and the new velocity.  Derivation in the design notes.
+OPS_PER_TRIAL = 76
+OPS_PER_REAL = 185
+PEAK_LANE_OPS = 256 * 64 * 2.4e9      # 256 CUs x 64 FP32 lanes/clock x 2.4 GHz = 3.93e13 /s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--electrons", type=int, default=100_000)
+    ap.add_argument("--collisions", type=int, default=20_000)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=5.0)
+    ap.add_argument("--serve-seconds", type=float, default=8.0)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+def log(args, *a):
+    if not args.quiet:
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def agreement(a, b, keys):
+    ok = 0
+    for k in keys:
+        va, sa, _ = a[k]
+        vb, sb, _ = b[k]
+        if math.isfinite(va) and math.isfinite(vb) and abs(va - vb) <= 3 * math.hypot(sa, sb) + 0.005 * abs(vb):
+            ok += 1
+    return ok
+
+
+def cpu_baseline(args):
+    """The oracle as it stands, on the host cores, on a bounded sample of the workload."""
+    import oracle
+    import synth
+    cfgs = synth.cfg2_argon_sweep()
+    idx = (0, 10, 21, 31)
+    n_e = 256
+    threads = max(1, len(os.sched_getaffinity(0)))
+    t0 = time.perf_counter()
+    real = 0
+    trials = 0
+    for i in idx:
+        m = oracle.OracleModel.from_config(cfgs[i])
+        r = m.run(n_e, args.collisions, 0, n_threads=threads)
+        k = (r.records["k_end"].astype("i8") - r.records["k_start"]).sum()
+        real += int(k)
+        trials += int(k + r.records["n_null"].sum() + r.records["n_forbidden"].sum())
+    dt = time.perf_counter() - t0
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": real / dt, "unit": "real collisions/s", "cores": threads, "kind": "oracle",
+            "sample": f"electrons 0..{n_e - 1} x {args.collisions} collisions at E/N index {list(idx)} "
+                      f"of the 32-point sweep ({real:.3g} real collisions, {dt:.1f} s)",
+            "trials_per_s": trials / dt, "cpu_model": model}
+
+
+def serve(sw, args):
+    """Poisson stream of random-mixture requests into the continuous-batching server."""
+    import numpy as np
+    import synth
+    rng = np.random.default_rng(5)
+    arrivals = []
+    t = 0.0
+    while True:
+        t += rng.exponential(1.0 / args.serve_rate)
+        if t >= args.serve_seconds:
+            break
+        arrivals.append(t)
+    reqs = [synth.cfg5_request(i) for i in range(len(arrivals))]
+    srv = sw.swarm_server_create(200 << 30, sw.SWARM_FP32_MIXED)
+    try:
+        t0 = sw.swarm_server_now(srv)
+        tickets = []
+        for a, c in zip(arrivals, reqs):
+            while sw.swarm_server_now(srv) - t0 < a:
+                time.sleep(0.001)
+            tickets.append(sw.swarm_server_submit(srv, c.components, sw.params_from_config(c, 1),
+                                                  c.n_electrons, c.n_collisions, c.seed))
+        sw.swarm_server_drain(srv)
+        t_end = sw.swarm_server_now(srv)
+        lat, real = [], 0
+        for tk in tickets:
+            done, tal, info = sw.swarm_server_poll(srv, tk)
+            lat.append(info["done_s"] - info["submit_s"])
+            real += tal["n_real"]
+        lat = np.array(lat)
+        offered = sum(c.n_electrons * c.n_collisions for c in reqs) / args.serve_seconds
+        return {"requests": len(tickets), "rate_per_s": args.serve_rate, "arrival_window_s": args.serve_seconds,
+                "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+                "served_real_per_s": real / (t_end - t0), "offered_real_per_s": offered,
+                "makespan_s": t_end - t0}
+    finally:
+        sw.swarm_server_destroy(srv)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1901_08140_amd as sw
+    import synth
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    cfgs = synth.cfg2_argon_sweep(n_electrons=args.electrons, n_collisions=args.collisions)
+    jobs = [(c.n_electrons, c.n_collisions, c.seed) for c in cfgs]
+    h32 = [sw.Swarm.from_config(c, sw.SWARM_FP32_MIXED) for c in cfgs]
+    handles = [h.h for h in h32]
+    opts = {"use_graph": 1}
+    if not args.no_autotune:
+        best = sw.swarm_autotune(handles, jobs, 300)
+        opts.update(best)
+        opts["use_graph"] = 1
+        log(args, "autotuned launch options", opts)
+    batch = sw.swarm_batch_create(handles, jobs, opts)
+    for _ in range(args.warmup):
+        sw.swarm_batch_launch(batch)
+        sw.swarm_batch_wait(batch)
+    torch.cuda.synchronize()
+    dev_ms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sw.swarm_batch_launch(batch)
+        dev_ms.append(sw.swarm_batch_wait(batch))
+        log(args, f"step {len(dev_ms)}: {dev_ms[-1]:.1f} ms")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tall32 = [sw.swarm_batch_tallies(batch, i) for i in range(len(cfgs))]
+    sw.swarm_batch_destroy(batch)
+    real_per_step = sum(t["n_real"] for t in tall32)
+    trials_per_step = sum(t["n_real"] + t["n_null"] + t["n_forbidden"] for t in tall32)
+    value = real_per_step * args.steps / wall
+    avg_ms = sum(dev_ms) / len(dev_ms)
+    ops = trials_per_step * OPS_PER_TRIAL + real_per_step * OPS_PER_REAL
+    achieved = ops / (avg_ms * 1e-3)
+    out = {
+        "metric": "real collisions/s on 1 MI355X (FP32 batched vs FP64 plain); p50/p99 solve latency",
+        "value": value, "unit": "real collisions/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 (f64 positions, times, sums, onset compare)", "data": "synthetic",
+        "config": {"workload": f"argon-like E/N sweep: 32 x 1-1000 Td, B=0, {args.electrons} electrons x "
+                               f"{args.collisions} real collisions each, dummy ionisation, seed 0",
+                   "instances": len(cfgs), "electrons": args.electrons, "collisions": args.collisions,
+                   "launch": opts},
+        "trials_per_s": trials_per_step * args.steps / wall,
+        "efficiency": real_per_step / trials_per_step,
+        "device_ms_per_step": avg_ms,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e9, "peak": PEAK_LANE_OPS / 1e9, "unit": "Gop/s",
+                     "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                     "kernel": "k_swarm_dummy<float,false,false>",
+                     "ops_per_trial": OPS_PER_TRIAL, "ops_per_real": OPS_PER_REAL},
+    }
+    if not args.no_fp64:
+        h64 = [sw.Swarm.from_config(c, sw.SWARM_FP64) for c in cfgs]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for h, (ne, nc, seed) in zip(h64, jobs):
+            h.run(ne, nc, seed)
+        torch.cuda.synchronize()
+        dt64 = time.perf_counter() - t1
+        tall64 = [h.tallies() for h in h64]
+        real64 = sum(t["n_real"] for t in tall64)
+        keys = ["W", "mean_energy", "mean_energy_after", "D", "DL", "DT", "alpha"]
+        agree = sum(agreement(a, b, keys) for a, b in zip(tall32, tall64))
+        out["fp64_plain"] = {"value": real64 / dt64, "unit": "real collisions/s", "seconds": dt64,
+                             "speedup_fp32_batched": value / (real64 / dt64)}
+        out["fp32_vs_fp64_within_tolerance"] = f"{agree}/{len(keys) * len(cfgs)}"
+        log(args, f"fp64 plain {real64 / dt64:.3e}/s; fp32 within tolerance {agree}/{len(keys) * len(cfgs)}")
+    if args.serve_seconds > 0 and args.serve_rate > 0:
+        out["serving"] = serve(sw, args)
+        out["p50_latency_s"] = out["serving"]["p50_latency_s"]
+        out["p99_latency_s"] = out["serving"]["p99_latency_s"]
+        log(args, "serving", out["serving"])
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args)
+        log(args, "cpu baseline", out["cpu_baseline"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

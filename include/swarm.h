@@ -1,0 +1,287 @@
+/*
+ * swarm.h -- C ABI of the MI355X (gfx950) electron-swarm library (libswarm.so).
+ *
+ * The library runs the Monte-Carlo swarm method of "Betaboltz: a Monte-Carlo simulation
+ * tool for gas scattering processes" (Renda, Ciubotaru, Banu; arXiv 1901.08140) on the GPU:
+ * electrons fly freely in static uniform E and B fields (section "Theoretical framework",
+ * classical equations of motion), collide after flight times drawn against a constant
+ * trial frequency nu' >= nu (eq. random_time, null-collision technique), are tested for a
+ * real or null collision (eq. null_fraction) with the collision frequency of eq. frequency,
+ * scatter isotropically with the energy transfer of eqs. delta_energy_ela/delta_energy_ine,
+ * ionise and attach, and are reduced into the swarm attributes of section "Determination
+ * of swarm attributes" (drift velocity, mean energies, diffusion, Townsend coefficients).
+ *
+ * Conventions shared by every entry point
+ *  - Units: SI, except energies in eV and masses in unified atomic mass units.
+ *  - Frame (section "Determination of swarm attributes"): z along E, B in the xz plane at
+ *    angle B_angle_rad from E.  Electrons drift towards -z; scalar drift velocity and
+ *    Townsend coefficients are reported along -z (positive numbers), vectors in the frame.
+ *  - Every function returns swarm_status (0 = SWARM_OK, < 0 = error) unless stated; no
+ *    C++ exception crosses the ABI.  swarm_strerror() names a status; swarm_last_error()
+ *    gives a human-readable message for the calling thread's last failure.
+ *  - Input arrays are read during the call and copied; the library keeps no caller
+ *    pointer.  A handle owns its device memory and frees it in swarm_destroy().
+ *  - A handle is not thread-safe; distinct handles may be used from distinct threads.
+ *  - Work is issued on params.stream (a hipStream_t, e.g. torch's current stream) or, if
+ *    it is NULL, on a stream the handle creates.  Entry points that return results to the
+ *    host synchronise that stream before returning.
+ */
+#ifndef SWARM_H_
+#define SWARM_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SWARM_OK = 0,
+  SWARM_ERR_INVALID_ARG = -1,   /* an argument failed validation (message says which)  */
+  SWARM_ERR_OUT_OF_MEMORY = -2, /* device or host allocation failed                     */
+  SWARM_ERR_CAPACITY = -3,      /* real-secondaries growth exceeded params.capacity     */
+  SWARM_ERR_DEVICE = -4,        /* a HIP call failed (message holds the HIP error)      */
+  SWARM_ERR_STATE = -5,         /* e.g. tallies requested before any run               */
+  SWARM_PENDING = 1             /* swarm_server_poll: the request has not finished yet */
+} swarm_status;
+
+/* Collision process classes (section "Theoretical framework"). */
+typedef enum { SWARM_ELASTIC = 0, SWARM_EXCITATION = 1, SWARM_IONIZATION = 2,
+               SWARM_ATTACHMENT = 3 } swarm_kind;
+
+/* Arithmetic of the per-electron loop.  SWARM_FP64: everything in binary64.
+ * SWARM_FP32_MIXED: flight-time sampling, table interpolation, motion and scattering in
+ * binary32; positions, times, energy sums and the energy-versus-threshold comparison near
+ * the inelastic onset in binary64.  Both use the same random streams. */
+typedef enum { SWARM_FP64 = 0, SWARM_FP32_MIXED = 1 } swarm_precision;
+
+/* Ionisation/attachment handling (section "Determination of swarm attributes"):
+ * DUMMY counts ionisations/attachments without creating or removing electrons (an
+ * attached electron restarts at rest, an ionising one keeps half the remaining energy);
+ * REAL appends the ejected electron as a new swarm member and removes attached ones. */
+typedef enum { SWARM_DUMMY = 0, SWARM_REAL = 1 } swarm_secondaries;
+
+/* One cross-section table: n_points >= 2 strictly increasing energies (> 0, eV) and
+ * cross-sections (>= 0, finite, m^2).  Extended outside the points as in section
+ * "Extension of the cross-section tables" (elastic: constant to the left; inelastic:
+ * zero below threshold_eV; right: power law through the last two points). */
+typedef struct {
+  int32_t kind;            /* swarm_kind */
+  double threshold_eV;     /* >= 0; energy lost in excitation/ionisation */
+  int32_t n_points;
+  const double* energy_eV;
+  const double* sigma_m2;
+} swarm_channel;
+
+/* One gas component: target mass, number fraction of the density (fractions of all
+ * components sum to 1 within 1e-9) and its channels.  Channel order (components in
+ * order, then channels in order) fixes the collision-process order used in selection. */
+typedef struct {
+  double mass_amu;         /* > 0 */
+  double fraction;         /* >= 0 */
+  int32_t n_channels;      /* >= 1 */
+  const swarm_channel* channels;
+} swarm_component;
+
+typedef struct {
+  double E_V_per_m;        /* >= 0, along +z */
+  double B_T;              /* >= 0 */
+  double B_angle_rad;      /* angle of B from E, B in the xz plane */
+  double N_per_m3;         /* gas number density, > 0 */
+  double T_K;              /* gas temperature (targets are at rest; bookkeeping only) */
+  double init_energy_eV;   /* energy of the primaries, isotropic directions; >= 0 */
+  int32_t precision;       /* swarm_precision */
+  int32_t secondaries;     /* swarm_secondaries */
+  int32_t grid_points_per_octave;  /* power of two <= 1024; 0 = default 64 */
+  int32_t grid_min_exp2;   /* rate grid covers [2^min, 2^max] eV; both 0 = default -14, 12 */
+  int32_t grid_max_exp2;
+  double user_majorant;    /* 0: nu' = (1+2^-20) max nu on the grid (the paper's
+                              LazyTrialFrequency); > 0: a fixed nu' (FixedTrialFrequency),
+                              refused with SWARM_ERR_INVALID_ARG if below that maximum */
+  int64_t capacity;        /* REAL mode: maximum number of electrons (primaries plus
+                              secondaries) of one run; 0 = 64 x n_electrons */
+  void* stream;            /* hipStream_t or NULL */
+} swarm_params;
+
+/* Per-electron result record (one per electron that existed in the run), as stored on
+ * the device.  r and t are measured from the primary's start (t = 0 at the origin). */
+typedef struct {
+  uint64_t id;             /* primaries: index; secondaries: 2^63 | hash of (parent, k) */
+  uint32_t flags;          /* 1 finished (made all its real collisions), 2 attached,
+                              4 stopped at the per-electron trial-block cap (2^31 - 1) */
+  uint32_t k_start;        /* real collisions inherited from the lineage at birth */
+  uint32_t k_end;          /* real-collision count when the electron stopped */
+  uint32_t G, D;           /* ionisations and attachments made by this electron */
+  uint32_t n_forbidden;    /* channel picks below the inelastic onset (treated as null) */
+  uint32_t n_over;         /* real collisions above the top of the rate grid */
+  uint32_t pad;
+  uint64_t n_null;         /* null trials */
+  uint64_t blocks;         /* random-number blocks used (two candidate trials each) */
+  double r[3], t;
+  double sum_eps, sum_epsp; /* sums of the energies before / after its real collisions */
+} swarm_record;
+
+/* One traced event (real collision or forbidden channel pick) of a traced electron. */
+typedef struct {
+  uint64_t id;
+  int32_t type;            /* 1 real, 2 forbidden */
+  int32_t channel;
+  uint32_t k, block, sub, pad;   /* real index before the event, trial block, 0/1 in block */
+  double eps, epsp, t, r[3];     /* energy before/after (eV), time and position after */
+} swarm_event;
+
+typedef struct { double value, stat_sigma, spread; } swarm_stat;
+
+/* Swarm tallies (section "Determination of swarm attributes").  Over the finished set F:
+ *   W = (1/N) sum z_n/t_n (vector W*, scalar along -z);  d_n = x_n - t_n W_z z^ (paper
+ *   form) or x_n - t_n W* (vector form);  D = (1/N) sum |d|^2/t, D_L = (1/N) sum
+ *   (d.z)^2/(2t), D_T = (1/N) sum |d_perp|^2/(4t);  sigma = (1/N) sum 2|d| (and the L, T
+ *   parts);  alpha = (1/N) sum G_n/z_n, eta = (1/N) sum D_n/z_n (z along -z).
+ * Over all electrons: mean energies before/after real collisions; counts; efficiency =
+ * real/(real + null + forbidden).  spread = sample standard deviation of the per-electron
+ * quantity (the paper's printed +-), stat_sigma = spread/sqrt(N). */
+typedef struct {
+  swarm_stat W, Wx, Wy, Wz, mean_energy, mean_energy_after;
+  swarm_stat D, DL, DT, sigma, sigmaL, sigmaT;
+  swarm_stat D_vec, DL_vec, DT_vec, sigma_vec, sigmaL_vec, sigmaT_vec;
+  swarm_stat alpha, eta;
+  double alpha_rate, eta_rate;   /* sum G / sum z and sum D / sum z over F */
+  double efficiency, majorant;
+  int64_t n_real, n_null, n_forbidden, n_fail, n_over;
+  int64_t n_electrons, n_finished, n_attached, n_stuck, n_created;
+  int64_t n_ionizations, n_attachments, n_dropped;
+} swarm_tallies_t;
+
+typedef struct swarm* swarm_t;
+
+/* Build a swarm instance: validates the inputs, copies the tables to the device and
+ * builds (in kernels) the octave-grid rate tables nu_c(eps_g) = n_k sigma_c(eps_g)
+ * sqrt(2 eps_g / m) (eq. frequency), their running sums over channels, the trial
+ * frequency and the field constants.  *out is set only on SWARM_OK. */
+swarm_status swarm_create(const swarm_component* comps, int32_t n_comps,
+                          const swarm_params* params, swarm_t* out);
+
+/* Simulate n_electrons primaries (ids 0..n-1) at the origin, each until it has made
+ * n_collisions real collisions (the paper's I; section "Determination of swarm
+ * attributes"), with the given seed.  Synchronous.  In REAL mode secondaries inherit the
+ * parent's count.  Returns SWARM_ERR_CAPACITY (results kept, dropped electrons counted)
+ * if REAL growth exceeds the capacity.  Previous results of the handle are replaced. */
+swarm_status swarm_run(swarm_t h, int64_t n_electrons, int64_t n_collisions, uint64_t seed);
+
+/* Tallies of the last run (computed by deterministic fixed-order device reductions). */
+swarm_status swarm_tallies(swarm_t h, swarm_tallies_t* out);
+
+/* Copy up to max_records records of the last run to host memory `out` (primaries in id
+ * order first, then secondaries in creation order); *n_out = number of records run. */
+swarm_status swarm_records(swarm_t h, swarm_record* out, int64_t max_records, int64_t* n_out);
+
+/* Select electrons to trace in the following runs (n_ids <= 256, max_events per
+ * electron <= 4096); n_ids = 0 switches tracing off.  Tracing uses a separate kernel
+ * build; results are otherwise identical. */
+swarm_status swarm_set_trace(swarm_t h, const uint64_t* ids, int32_t n_ids, int32_t max_events);
+
+/* Copy the events of the last traced run: out holds n_ids x max_events slots (slot
+ * i*max_events + j = event j of ids[i]); counts[i] = number of events of ids[i]. */
+swarm_status swarm_trace_events(swarm_t h, swarm_event* out, int32_t* counts);
+
+/* Copy the device-built tables: nodes (G energies, eV), cum (n_channels x G, channel
+ * major, FP64 running sums of channel rates), majorant (nu', 1/s).  Any may be NULL. */
+swarm_status swarm_tables(swarm_t h, int32_t* grid_size, int32_t* n_channels, double* nodes,
+                          double* cum, double* majorant);
+
+/* Device time in milliseconds of the last run's simulation kernel (HIP events on the
+ * launch stream) and of its whole device section (simulation plus tallies). */
+swarm_status swarm_last_timing(swarm_t h, double* kernel_ms, double* total_ms);
+
+void swarm_destroy(swarm_t h);             /* NULL-safe */
+const char* swarm_strerror(swarm_status s);
+const char* swarm_last_error(void);        /* thread-local message of the last failure */
+
+/* ---- Batched runs: many uneven instances in one persistent launch ------------------ */
+
+typedef struct {
+  int64_t n_electrons;
+  int64_t n_collisions;
+  uint64_t seed;
+} swarm_job;
+
+/* Launch-shape options.  They only change how work is scheduled on the GPU, never the
+ * per-electron arithmetic or random streams, so results are bit-identical for any
+ * choice.  Zero fields mean "autotune" (swarm_autotune) or the built-in default. */
+typedef struct {
+  int32_t block_size;      /* 64..1024, multiple of 64 */
+  int32_t chunk;           /* electrons per work item (multiple of block_size) */
+  int32_t pending_trigger; /* lanes waiting on a real collision before the wave serves them (1..64) */
+  int32_t use_graph;       /* capture the launch in a hipGraph and replay it */
+} swarm_launch_opts;
+
+typedef struct swarm_batch* swarm_batch_t;
+
+/* A batch of instances (all DUMMY mode, all the same precision) with one job each.  The
+ * batch keeps the per-instance results on the device; swarm_batch_launch runs every job
+ * in one persistent kernel (work items of `chunk` electrons, instance tables staged in
+ * LDS), followed by the tally kernels, captured once in a hipGraph when use_graph != 0. */
+swarm_status swarm_batch_create(swarm_t* handles, const swarm_job* jobs, int32_t n,
+                                const swarm_launch_opts* opts, swarm_batch_t* out);
+swarm_status swarm_batch_launch(swarm_batch_t b);                  /* asynchronous */
+swarm_status swarm_batch_wait(swarm_batch_t b, double* device_ms); /* synchronise */
+/* Tallies of instance i of the last launch (also stored in handle i). */
+swarm_status swarm_batch_tallies(swarm_batch_t b, int32_t i, swarm_tallies_t* out);
+void swarm_batch_destroy(swarm_batch_t b);
+
+/* Convenience: create, launch, wait and destroy a batch; afterwards swarm_tallies and
+ * swarm_records of each handle return its instance's results. */
+swarm_status swarm_batch_run(swarm_t* handles, const swarm_job* jobs, int32_t n,
+                             const swarm_launch_opts* opts);
+
+/* Autotuner: times the result-invariant launch options on a shortened copy of the batch
+ * (same instances, budgets cut to probe_collisions) and writes the fastest to *best. */
+swarm_status swarm_autotune(swarm_t* handles, const swarm_job* jobs, int32_t n,
+                            int64_t probe_collisions, swarm_launch_opts* best);
+
+/* ---- Serving: continuous batching of arriving swarm requests ------------------------ */
+
+typedef struct {
+  int64_t hbm_budget_bytes;   /* admission limit on device memory held by requests */
+  int32_t precision;          /* swarm_precision of every request */
+  int64_t quantum_collisions; /* real collisions per electron per scheduling epoch */
+  int32_t max_active;         /* instances per epoch (0 = 1024) */
+  swarm_launch_opts opts;
+  void* stream;               /* hipStream_t or NULL */
+} swarm_server_params;
+
+typedef struct {
+  double submit_s, admit_s, done_s;   /* seconds on the server's monotonic clock */
+  int64_t n_real;                     /* real collisions of the request */
+  int64_t epochs;                     /* scheduling epochs the request took part in */
+  int64_t bytes;                      /* device memory charged against the budget */
+} swarm_request_info;
+
+typedef struct swarm_server* swarm_server_t;
+
+/* A server owns a scheduler thread.  Requests are admitted while the device memory they
+ * need fits the budget; admitted requests keep their tables and electron state resident
+ * and advance together: each epoch is one persistent launch over all admitted requests in
+ * which every unfinished electron makes up to quantum_collisions more real collisions.
+ * Requests that arrive while an epoch runs join the next one.  Because electrons stop at
+ * real-collision boundaries and the random streams are counter based, a request's
+ * result does not depend on what it was batched with. */
+swarm_status swarm_server_create(const swarm_server_params* p, swarm_server_t* out);
+/* Queue a request (inputs copied); *ticket identifies it.  DUMMY mode only. */
+swarm_status swarm_server_submit(swarm_server_t s, const swarm_component* comps, int32_t n_comps,
+                                 const swarm_params* params, int64_t n_electrons,
+                                 int64_t n_collisions, uint64_t seed, int64_t* ticket);
+/* SWARM_OK with the tallies once finished, SWARM_PENDING before; info may be NULL. */
+swarm_status swarm_server_poll(swarm_server_t s, int64_t ticket, swarm_tallies_t* out,
+                               swarm_request_info* info);
+/* Block until every submitted request has finished. */
+swarm_status swarm_server_drain(swarm_server_t s);
+/* Seconds on the server clock (the clock of swarm_request_info). */
+double swarm_server_now(swarm_server_t s);
+void swarm_server_destroy(swarm_server_t s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif  /* SWARM_H_ */

@@ -353,6 +353,7 @@ Record simulate(const RunCtx& cx, const Electron& e0, std::vector<Electron>& chi
           ev.block = blk; ev.sub = sub; ev.eps = eps; ev.epsp = eps;
           ev.t = t + T; ev.r[0] = r.x; ev.r[1] = r.y; ev.r[2] = r.z;
           events.push_back(ev);
+          ++n_ev;
         }
         break;
       }

@@ -1,0 +1,549 @@
+// Host runtime of libswarm: argument validation, device memory, kernel launches, hipGraph
+// capture of batched launches, the launch-shape autotuner and the C ABI of swarm.h.
+// No method arithmetic happens here: tables, physics constants, the simulation and the
+// tallies are all computed by the kernels in swarm_kernels.hip.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "swarm_api_internal.hpp"
+
+using namespace swarm_impl;
+
+namespace swarm_impl {
+
+thread_local std::string g_last_error;
+
+swarm_status fail(swarm_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+swarm_status hip_fail(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? SWARM_ERR_OUT_OF_MEMORY : SWARM_ERR_DEVICE, "%s: %s", what,
+              hipGetErrorString(e));
+}
+
+DeviceInfo& device_info() {
+  static DeviceInfo info = [] {
+    DeviceInfo d{};
+    if (hipGetDevice(&d.device) != hipSuccess) d.device = 0;
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, d.device) == hipSuccess) {
+      d.n_cu = p.multiProcessorCount;
+      d.lds_per_block = static_cast<int64_t>(p.sharedMemPerBlock);
+    } else {
+      d.n_cu = 256;
+      d.lds_per_block = 65536;
+    }
+    return d;
+  }();
+  return info;
+}
+
+size_t lds_bytes_for(int precision, int G) {
+  return static_cast<size_t>(G) * (precision == SWARM_FP32_MIXED ? sizeof(float2) : sizeof(double2));
+}
+
+DevBuf::~DevBuf() { reset(); }
+void DevBuf::reset() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+hipError_t DevBuf::ensure(size_t n) {
+  if (n <= bytes && p) return hipSuccess;
+  reset();
+  if (n == 0) return hipSuccess;
+  hipError_t e = hipMalloc(&p, n);
+  if (e != hipSuccess) {
+    p = nullptr;
+    return e;
+  }
+  bytes = n;
+  return hipSuccess;
+}
+
+}  // namespace swarm_impl
+
+namespace {
+
+swarm_status validate(const swarm_component* comps, int32_t n_comps, const swarm_params* p) {
+  if (!comps || n_comps <= 0) return fail(SWARM_ERR_INVALID_ARG, "need at least one component");
+  if (!p) return fail(SWARM_ERR_INVALID_ARG, "params is NULL");
+  if (!(p->N_per_m3 > 0.0) || !std::isfinite(p->N_per_m3)) return fail(SWARM_ERR_INVALID_ARG, "N must be > 0");
+  if (!(p->E_V_per_m >= 0.0) || !std::isfinite(p->E_V_per_m)) return fail(SWARM_ERR_INVALID_ARG, "E must be >= 0");
+  if (!(p->B_T >= 0.0) || !std::isfinite(p->B_T)) return fail(SWARM_ERR_INVALID_ARG, "B must be >= 0");
+  if (!std::isfinite(p->B_angle_rad)) return fail(SWARM_ERR_INVALID_ARG, "B angle must be finite");
+  if (!(p->init_energy_eV >= 0.0) || !std::isfinite(p->init_energy_eV))
+    return fail(SWARM_ERR_INVALID_ARG, "initial energy must be >= 0");
+  if (p->precision != SWARM_FP64 && p->precision != SWARM_FP32_MIXED)
+    return fail(SWARM_ERR_INVALID_ARG, "unknown precision %d", p->precision);
+  if (p->secondaries != SWARM_DUMMY && p->secondaries != SWARM_REAL)
+    return fail(SWARM_ERR_INVALID_ARG, "unknown secondaries mode %d", p->secondaries);
+  if (!(p->user_majorant >= 0.0) || !std::isfinite(p->user_majorant))
+    return fail(SWARM_ERR_INVALID_ARG, "user majorant must be >= 0");
+  if (p->capacity < 0) return fail(SWARM_ERR_INVALID_ARG, "capacity must be >= 0");
+  const int P = p->grid_points_per_octave ? p->grid_points_per_octave : 64;
+  if (P <= 0 || P > 1024 || (P & (P - 1)) != 0)
+    return fail(SWARM_ERR_INVALID_ARG, "grid points per octave must be a power of two <= 1024");
+  int emin = p->grid_min_exp2, emax = p->grid_max_exp2;
+  if (emin == 0 && emax == 0) { emin = -14; emax = 12; }
+  if (emax <= emin || emin < -60 || emax > 60) return fail(SWARM_ERR_INVALID_ARG, "bad grid exponent range");
+  double fsum = 0.0;
+  int nc = 0;
+  for (int k = 0; k < n_comps; ++k) {
+    const swarm_component& c = comps[k];
+    if (!(c.mass_amu > 0.0) || !std::isfinite(c.mass_amu))
+      return fail(SWARM_ERR_INVALID_ARG, "component %d: mass must be > 0", k);
+    if (!(c.fraction >= 0.0) || !std::isfinite(c.fraction))
+      return fail(SWARM_ERR_INVALID_ARG, "component %d: fraction must be >= 0", k);
+    if (c.n_channels <= 0 || !c.channels) return fail(SWARM_ERR_INVALID_ARG, "component %d: no channels", k);
+    fsum += c.fraction;
+    for (int j = 0; j < c.n_channels; ++j) {
+      const swarm_channel& q = c.channels[j];
+      if (q.kind < 0 || q.kind > 3) return fail(SWARM_ERR_INVALID_ARG, "component %d channel %d: bad kind", k, j);
+      if (!(q.threshold_eV >= 0.0) || !std::isfinite(q.threshold_eV))
+        return fail(SWARM_ERR_INVALID_ARG, "component %d channel %d: threshold must be >= 0", k, j);
+      if (q.n_points < 2 || !q.energy_eV || !q.sigma_m2)
+        return fail(SWARM_ERR_INVALID_ARG, "component %d channel %d: need >= 2 points", k, j);
+      for (int i = 0; i < q.n_points; ++i) {
+        if (!(q.energy_eV[i] > 0.0) || !std::isfinite(q.energy_eV[i]))
+          return fail(SWARM_ERR_INVALID_ARG, "component %d channel %d: energies must be > 0 and finite", k, j);
+        if (!(q.sigma_m2[i] >= 0.0) || !std::isfinite(q.sigma_m2[i]))
+          return fail(SWARM_ERR_INVALID_ARG, "component %d channel %d: cross-sections must be >= 0 and finite", k, j);
+        if (i > 0 && !(q.energy_eV[i] > q.energy_eV[i - 1]))
+          return fail(SWARM_ERR_INVALID_ARG, "component %d channel %d: energies must increase strictly", k, j);
+      }
+      ++nc;
+    }
+  }
+  if (std::fabs(fsum - 1.0) > 1e-9) return fail(SWARM_ERR_INVALID_ARG, "fractions sum to %.12g, not 1", fsum);
+  if (nc > 4096) return fail(SWARM_ERR_INVALID_ARG, "too many channels (%d > 4096)", nc);
+  return SWARM_OK;
+}
+
+hipError_t sync_desc_to_device(swarm* h) {
+  return hipMemcpyAsync(h->d_desc, &h->desc, sizeof(InstanceDesc), hipMemcpyHostToDevice, h->stream);
+}
+
+// Tally tiles of a set of instances with known record counts.
+void make_tiles(const std::vector<int64_t>& nrec, std::vector<TallyTile>& tiles, std::vector<int32_t>& base) {
+  tiles.clear();
+  base.assign(nrec.size(), 0);
+  int32_t b = 0;
+  for (size_t i = 0; i < nrec.size(); ++i) {
+    base[i] = b;
+    const int64_t nt = (nrec[i] + kTallyTile - 1) / kTallyTile;
+    for (int64_t t = 0; t < nt; ++t) {
+      TallyTile tt;
+      tt.inst = static_cast<int32_t>(i);
+      tt.tile = static_cast<int32_t>(t);
+      tt.first = t * kTallyTile;
+      tt.count = std::min<int64_t>(kTallyTile, nrec[i] - tt.first);
+      tiles.push_back(tt);
+    }
+    b += static_cast<int32_t>(nt);
+  }
+}
+
+}  // namespace
+
+namespace swarm_impl {
+
+hipError_t TallyPlan::prepare(const std::vector<int64_t>& nrec, hipStream_t s) {
+  std::vector<TallyTile> tiles;
+  std::vector<int32_t> base;
+  make_tiles(nrec, tiles, base);
+  n_inst = static_cast<int32_t>(nrec.size());
+  n_tiles = static_cast<int32_t>(tiles.size());
+  hipError_t e;
+  if ((e = d_tiles.ensure(std::max<size_t>(1, tiles.size()) * sizeof(TallyTile))) != hipSuccess) return e;
+  if ((e = d_base.ensure(base.size() * sizeof(int32_t))) != hipSuccess) return e;
+  if ((e = d_nrec.ensure(nrec.size() * sizeof(int64_t))) != hipSuccess) return e;
+  if ((e = d_part1.ensure(std::max<size_t>(1, tiles.size()) * kTally1 * sizeof(double))) != hipSuccess) return e;
+  if ((e = d_part2.ensure(std::max<size_t>(1, tiles.size()) * kTally2 * sizeof(double))) != hipSuccess) return e;
+  if ((e = d_tot.ensure(nrec.size() * (kTally1 + kTally2) * sizeof(double))) != hipSuccess) return e;
+  if ((e = d_out.ensure(nrec.size() * sizeof(swarm_tallies_t))) != hipSuccess) return e;
+  h_tiles = tiles;
+  h_base = base;
+  h_nrec = nrec;
+  if (!tiles.empty() && (e = hipMemcpyAsync(d_tiles.p, h_tiles.data(), tiles.size() * sizeof(TallyTile),
+                                            hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(d_base.p, h_base.data(), base.size() * sizeof(int32_t), hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(d_nrec.p, h_nrec.data(), nrec.size() * sizeof(int64_t), hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+hipError_t TallyPlan::launch(const InstanceDesc* d_descs, hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  return launch_tallies(d_descs, static_cast<const TallyTile*>(d_tiles.p), n_tiles,
+                        static_cast<const int32_t*>(d_base.p), static_cast<const int64_t*>(d_nrec.p), n_inst,
+                        static_cast<double*>(d_part1.p), static_cast<double*>(d_part2.p),
+                        static_cast<double*>(d_tot.p), static_cast<swarm_tallies_t*>(d_out.p), s);
+}
+
+// Work items of `chunk` electrons per instance, heaviest collision budgets first so that
+// the long items start early and the persistent grid drains evenly.
+void make_items(const std::vector<int64_t>& n_e, const std::vector<int64_t>& n_c, int64_t chunk,
+                std::vector<WorkItem>& items) {
+  items.clear();
+  std::vector<int> order(n_e.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = static_cast<int>(i);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n_c[a] > n_c[b]; });
+  for (int i : order) {
+    for (int64_t f = 0; f < n_e[i]; f += chunk) {
+      WorkItem w;
+      w.inst = i;
+      w.pad = 0;
+      w.first = f;
+      w.count = std::min<int64_t>(chunk, n_e[i] - f);
+      items.push_back(w);
+    }
+  }
+}
+
+int default_block(int precision) { return precision == SWARM_FP32_MIXED ? 256 : 256; }
+
+swarm_launch_opts resolve_opts(const swarm_launch_opts* o, int precision) {
+  swarm_launch_opts r{};
+  r.block_size = (o && o->block_size) ? o->block_size : default_block(precision);
+  r.chunk = (o && o->chunk) ? o->chunk : r.block_size * 8;
+  r.pending_trigger = (o && o->pending_trigger) ? o->pending_trigger : 24;
+  r.use_graph = o ? o->use_graph : 0;
+  r.block_size = std::max(64, std::min(1024, (r.block_size / 64) * 64));
+  r.chunk = std::max(r.block_size, (r.chunk / r.block_size) * r.block_size);
+  r.pending_trigger = std::max(1, std::min(64, r.pending_trigger));
+  return r;
+}
+
+}  // namespace swarm_impl
+
+// =======================================================================================
+// Single-instance API
+// =======================================================================================
+extern "C" {
+
+const char* swarm_strerror(swarm_status s) {
+  switch (s) {
+    case SWARM_OK: return "ok";
+    case SWARM_ERR_INVALID_ARG: return "invalid argument";
+    case SWARM_ERR_OUT_OF_MEMORY: return "out of memory";
+    case SWARM_ERR_CAPACITY: return "capacity exceeded";
+    case SWARM_ERR_DEVICE: return "device error";
+    case SWARM_ERR_STATE: return "invalid state";
+    case SWARM_PENDING: return "pending";
+  }
+  return "unknown status";
+}
+
+const char* swarm_last_error(void) { return g_last_error.c_str(); }
+
+swarm_status swarm_create(const swarm_component* comps, int32_t n_comps, const swarm_params* params,
+                          swarm_t* out) {
+  if (!out) return fail(SWARM_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  swarm_status st = validate(comps, n_comps, params);
+  if (st != SWARM_OK) return st;
+  auto h = std::make_unique<swarm>();
+  h->params = *params;
+  if (params->stream) {
+    h->stream = static_cast<hipStream_t>(params->stream);
+    h->own_stream = false;
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+    h->own_stream = true;
+  }
+  DeviceInfo& dev = device_info();
+  (void)dev;
+  // Flatten the raw tables (argument marshalling only).
+  std::vector<double> e_all, s_all, thr, mass, frac;
+  std::vector<int32_t> off, npt, kind, comp;
+  for (int k = 0; k < n_comps; ++k) {
+    mass.push_back(comps[k].mass_amu);
+    frac.push_back(comps[k].fraction);
+    for (int j = 0; j < comps[k].n_channels; ++j) {
+      const swarm_channel& q = comps[k].channels[j];
+      off.push_back(static_cast<int32_t>(e_all.size()));
+      npt.push_back(q.n_points);
+      kind.push_back(q.kind);
+      comp.push_back(k);
+      thr.push_back(q.threshold_eV);
+      e_all.insert(e_all.end(), q.energy_eV, q.energy_eV + q.n_points);
+      s_all.insert(s_all.end(), q.sigma_m2, q.sigma_m2 + q.n_points);
+      h->kinds.push_back(q.kind);
+    }
+  }
+  const int nc = static_cast<int>(off.size());
+  const int P = params->grid_points_per_octave ? params->grid_points_per_octave : 64;
+  int emin = params->grid_min_exp2, emax = params->grid_max_exp2;
+  if (emin == 0 && emax == 0) { emin = -14; emax = 12; }
+  int p_log2 = 0;
+  while ((1 << p_log2) < P) ++p_log2;
+  const int G = (emax - emin) * P + 1;
+  InstanceDesc& d = h->desc;
+  std::memset(&d, 0, sizeof(d));
+  d.G = G; d.nc = nc; d.p_log2 = p_log2; d.emin = emin; d.emax = emax; d.n_raw_channels = nc;
+  d.precision = params->precision; d.secondaries = params->secondaries;
+  d.E = params->E_V_per_m; d.B = params->B_T; d.B_angle = params->B_angle_rad; d.N = params->N_per_m3;
+  d.eps0 = params->init_energy_eV; d.user_majorant = params->user_majorant;
+  h->has_b = params->B_T > 0.0;
+  // one arena for the raw inputs and the tables
+  auto al = [](size_t n) { return (n + 255) & ~size_t(255); };
+  const size_t b_e = al(e_all.size() * 8), b_s = b_e, b_i = al(nc * 4), b_cd = al(nc * 8), b_k = al(n_comps * 8);
+  const size_t b_nodes = al(static_cast<size_t>(G) * 8);
+  const size_t b_cm = al(static_cast<size_t>(G) * nc * 8);
+  const size_t b_nu64 = al(static_cast<size_t>(G) * 16), b_nu32 = al(static_cast<size_t>(G) * 8);
+  const size_t b_c64 = al(static_cast<size_t>(G) * nc * 16), b_c32 = al(static_cast<size_t>(G) * nc * 8);
+  const size_t b_ch = al(nc * sizeof(ChannelDev));
+  const size_t total = b_e + b_s + 4 * b_i + b_cd + 2 * b_k + b_nodes + b_cm + b_nu64 + b_nu32 + b_c64 + b_c32 + b_ch +
+                       al(sizeof(InstanceDesc)) + al(sizeof(RunCounters));
+  hipError_t e = h->arena.ensure(total);
+  if (e != hipSuccess) return hip_fail(e, "allocating instance tables");
+  char* base = static_cast<char*>(h->arena.p);
+  size_t o = 0;
+  auto take = [&](size_t n) { char* r = base + o; o += n; return r; };
+  double* d_e = reinterpret_cast<double*>(take(b_e));
+  double* d_s = reinterpret_cast<double*>(take(b_s));
+  int32_t* d_off = reinterpret_cast<int32_t*>(take(b_i));
+  int32_t* d_n = reinterpret_cast<int32_t*>(take(b_i));
+  int32_t* d_kind = reinterpret_cast<int32_t*>(take(b_i));
+  int32_t* d_comp = reinterpret_cast<int32_t*>(take(b_i));
+  double* d_thr = reinterpret_cast<double*>(take(b_cd));
+  double* d_mass = reinterpret_cast<double*>(take(b_k));
+  double* d_frac = reinterpret_cast<double*>(take(b_k));
+  d.nodes = reinterpret_cast<double*>(take(b_nodes));
+  d.cum_cm = reinterpret_cast<double*>(take(b_cm));
+  d.nu64 = reinterpret_cast<double2*>(take(b_nu64));
+  d.nu32 = reinterpret_cast<float2*>(take(b_nu32));
+  d.cum64 = reinterpret_cast<double2*>(take(b_c64));
+  d.cum32 = reinterpret_cast<float2*>(take(b_c32));
+  d.chan = reinterpret_cast<ChannelDev*>(take(b_ch));
+  h->d_desc = reinterpret_cast<InstanceDesc*>(take(al(sizeof(InstanceDesc))));
+  d.ctr = reinterpret_cast<RunCounters*>(take(al(sizeof(RunCounters))));
+  d.raw_e = d_e; d.raw_s = d_s; d.raw_off = d_off; d.raw_n = d_n; d.raw_kind = d_kind;
+  d.raw_comp = d_comp; d.raw_thr = d_thr; d.comp_mass_amu = d_mass; d.comp_frac = d_frac;
+  hipStream_t s = h->stream;
+#define CP(dst, v) if ((e = hipMemcpyAsync(dst, v.data(), v.size() * sizeof(v[0]), hipMemcpyHostToDevice, s)) != hipSuccess) return hip_fail(e, "copying tables");
+  CP(d_e, e_all) CP(d_s, s_all) CP(d_off, off) CP(d_n, npt) CP(d_kind, kind) CP(d_comp, comp)
+  CP(d_thr, thr) CP(d_mass, mass) CP(d_frac, frac)
+#undef CP
+  if ((e = launch_fill_u64(reinterpret_cast<uint64_t*>(d.ctr), 0, sizeof(RunCounters) / 8, s)) != hipSuccess)
+    return hip_fail(e, "clearing counters");
+  if ((e = sync_desc_to_device(h.get())) != hipSuccess) return hip_fail(e, "copying descriptor");
+  if ((e = launch_build(h->d_desc, d, s)) != hipSuccess) return hip_fail(e, "table build launch");
+  if ((e = hipMemcpyAsync(&h->desc, h->d_desc, sizeof(InstanceDesc), hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return hip_fail(e, "reading descriptor");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "table build");
+  if (h->desc.built_ok == -1)
+    return fail(SWARM_ERR_INVALID_ARG, "the total collision frequency vanishes on part of the energy grid");
+  if (h->desc.built_ok == -2)
+    return fail(SWARM_ERR_INVALID_ARG, "user trial frequency %.6g is below the maximum collision frequency %.6g",
+                params->user_majorant, h->desc.numax);
+  if (h->desc.built_ok != 1) return fail(SWARM_ERR_DEVICE, "table build did not complete");
+  for (int i = 0; i < 3; ++i)
+    if ((e = hipEventCreate(&h->ev[i])) != hipSuccess) return hip_fail(e, "hipEventCreate");
+  h->opts = resolve_opts(nullptr, params->precision);
+  *out = h.release();
+  return SWARM_OK;
+}
+
+void swarm_destroy(swarm_t h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  for (int i = 0; i < 3; ++i)
+    if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+}
+
+swarm_status swarm_set_trace(swarm_t h, const uint64_t* ids, int32_t n_ids, int32_t max_events) {
+  if (!h) return fail(SWARM_ERR_INVALID_ARG, "handle is NULL");
+  if (n_ids < 0 || n_ids > kMaxTraceIds) return fail(SWARM_ERR_INVALID_ARG, "n_ids must be in [0, %d]", kMaxTraceIds);
+  if (n_ids > 0 && (!ids || max_events <= 0 || max_events > 4096))
+    return fail(SWARM_ERR_INVALID_ARG, "max_events must be in [1, 4096]");
+  h->n_trace = n_ids;
+  h->max_events = n_ids ? max_events : 0;
+  if (n_ids == 0) return SWARM_OK;
+  hipError_t e;
+  if ((e = h->trace_ids.ensure(n_ids * sizeof(uint64_t))) != hipSuccess) return hip_fail(e, "trace ids");
+  if ((e = h->trace_out.ensure(static_cast<size_t>(n_ids) * max_events * sizeof(swarm_event))) != hipSuccess)
+    return hip_fail(e, "trace buffer");
+  if ((e = h->trace_count.ensure(n_ids * sizeof(int32_t))) != hipSuccess) return hip_fail(e, "trace counts");
+  if ((e = hipMemcpyAsync(h->trace_ids.p, ids, n_ids * sizeof(uint64_t), hipMemcpyHostToDevice, h->stream)) != hipSuccess)
+    return hip_fail(e, "trace ids");
+  if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_fail(e, "trace ids");
+  return SWARM_OK;
+}
+
+swarm_status swarm_run(swarm_t h, int64_t n_electrons, int64_t n_collisions, uint64_t seed) {
+  if (!h) return fail(SWARM_ERR_INVALID_ARG, "handle is NULL");
+  if (n_electrons < 1) return fail(SWARM_ERR_INVALID_ARG, "n_electrons must be >= 1");
+  if (n_collisions < 1 || n_collisions > 0xffffffffLL)
+    return fail(SWARM_ERR_INVALID_ARG, "n_collisions must be in [1, 2^32-1]");
+  const bool real = h->desc.secondaries == SWARM_REAL;
+  int64_t capacity = n_electrons;
+  if (real) {
+    capacity = h->params.capacity ? h->params.capacity : 64 * n_electrons;
+    if (capacity < n_electrons) return fail(SWARM_ERR_INVALID_ARG, "capacity below n_electrons");
+  }
+  hipStream_t s = h->stream;
+  hipError_t e;
+  h->have_run = false;
+  if ((e = h->records.ensure(static_cast<size_t>(capacity) * sizeof(swarm_record))) != hipSuccess)
+    return hip_fail(e, "allocating records");
+  InstanceDesc& d = h->desc;
+  d.n_electrons = n_electrons;
+  d.n_collisions = static_cast<uint32_t>(n_collisions);
+  d.quantum = 0;
+  d.seed = seed;
+  d.capacity = capacity;
+  d.records = static_cast<swarm_record*>(h->records.p);
+  d.saved = nullptr;
+  d.children = nullptr;
+  d.child_ready = nullptr;
+  const int64_t child_cap = capacity - n_electrons;
+  if (real && child_cap > 0) {
+    if ((e = h->children.ensure(static_cast<size_t>(child_cap) * sizeof(ChildState))) != hipSuccess)
+      return hip_fail(e, "allocating secondary queue");
+    if ((e = h->ready.ensure(static_cast<size_t>(child_cap) * sizeof(uint32_t))) != hipSuccess)
+      return hip_fail(e, "allocating secondary flags");
+    d.children = static_cast<ChildState*>(h->children.p);
+    d.child_ready = static_cast<uint32_t*>(h->ready.p);
+    if ((e = launch_fill_u32(d.child_ready, 0u, child_cap, s)) != hipSuccess) return hip_fail(e, "clearing flags");
+  }
+  const bool trace = h->n_trace > 0;
+  d.trace_ids = trace ? static_cast<const uint64_t*>(h->trace_ids.p) : nullptr;
+  d.n_trace = h->n_trace;
+  d.max_events = h->max_events;
+  d.trace_out = trace ? static_cast<swarm_event*>(h->trace_out.p) : nullptr;
+  d.trace_count = trace ? static_cast<int32_t*>(h->trace_count.p) : nullptr;
+  if (trace && (e = launch_fill_u32(reinterpret_cast<uint32_t*>(d.trace_count), 0u, h->n_trace, s)) != hipSuccess)
+    return hip_fail(e, "clearing trace counts");
+  // counters: all zero, live = number of primaries
+  RunCounters rc{};
+  rc.live = n_electrons;
+  if ((e = hipMemcpyAsync(d.ctr, &rc, sizeof(rc), hipMemcpyHostToDevice, s)) != hipSuccess) return hip_fail(e, "counters");
+  if ((e = sync_desc_to_device(h)) != hipSuccess) return hip_fail(e, "descriptor");
+  const swarm_launch_opts& o = h->opts;
+  const size_t lds = lds_bytes_for(d.precision, d.G);
+  DeviceInfo& dev = device_info();
+  const int per_cu = swarm_kernel_max_blocks_per_cu(d.precision, h->has_b, trace, real, o.block_size, lds);
+  if ((e = hipEventRecord(h->ev[0], s)) != hipSuccess) return hip_fail(e, "event");
+  if (!real) {
+    std::vector<WorkItem> items;
+    make_items({n_electrons}, {n_collisions}, o.chunk, items);
+    if ((e = h->items.ensure(items.size() * sizeof(WorkItem) + 256)) != hipSuccess) return hip_fail(e, "work items");
+    h->h_items = items;
+    int32_t* d_ctr = reinterpret_cast<int32_t*>(static_cast<char*>(h->items.p) + items.size() * sizeof(WorkItem));
+    if ((e = hipMemcpyAsync(h->items.p, h->h_items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, s)) != hipSuccess)
+      return hip_fail(e, "work items");
+    if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(d_ctr), 0u, 1, s)) != hipSuccess) return hip_fail(e, "item counter");
+    const int grid = std::max(1, std::min<int>(static_cast<int>(items.size()), dev.n_cu * per_cu));
+    if ((e = launch_swarm_dummy(h->d_desc, static_cast<const WorkItem*>(h->items.p), static_cast<int32_t>(items.size()),
+                                d_ctr, d.precision, h->has_b, trace, o.block_size, grid, o.pending_trigger, lds, s)) != hipSuccess)
+      return hip_fail(e, "swarm kernel launch");
+  } else {
+    const int64_t want = (n_electrons + o.block_size - 1) / o.block_size;
+    const int grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want * 4, static_cast<int64_t>(dev.n_cu) * per_cu)));
+    if ((e = launch_swarm_real(h->d_desc, d.precision, h->has_b, trace, o.block_size, grid, o.pending_trigger, lds, s)) != hipSuccess)
+      return hip_fail(e, "swarm kernel launch");
+  }
+  if ((e = hipEventRecord(h->ev[1], s)) != hipSuccess) return hip_fail(e, "event");
+  RunCounters hc{};
+  if ((e = hipMemcpyAsync(&hc, d.ctr, sizeof(hc), hipMemcpyDeviceToHost, s)) != hipSuccess) return hip_fail(e, "counters");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "swarm kernel");
+  if (hc.poll_overrun) return fail(SWARM_ERR_DEVICE, "secondary queue wait limit reached (%llu waves)",
+                                   static_cast<unsigned long long>(hc.poll_overrun));
+  h->n_records = n_electrons + (real ? std::min<int64_t>(static_cast<int64_t>(hc.child_tail), child_cap) : 0);
+  if ((e = h->tally.prepare({h->n_records}, s)) != hipSuccess) return hip_fail(e, "tally plan");
+  if ((e = h->tally.launch(h->d_desc, s)) != hipSuccess) return hip_fail(e, "tally launch");
+  if ((e = hipEventRecord(h->ev[2], s)) != hipSuccess) return hip_fail(e, "event");
+  if ((e = hipMemcpyAsync(&h->tallies, h->tally.d_out.p, sizeof(swarm_tallies_t), hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return hip_fail(e, "tallies");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "tallies");
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, h->ev[0], h->ev[1]);
+  h->kernel_ms = ms;
+  (void)hipEventElapsedTime(&ms, h->ev[0], h->ev[2]);
+  h->total_ms = ms;
+  h->have_run = true;
+  h->traced = trace;
+  if (hc.dropped) return fail(SWARM_ERR_CAPACITY, "%llu secondaries did not fit the capacity of %lld electrons",
+                              static_cast<unsigned long long>(hc.dropped), static_cast<long long>(capacity));
+  return SWARM_OK;
+}
+
+swarm_status swarm_tallies(swarm_t h, swarm_tallies_t* out) {
+  if (!h || !out) return fail(SWARM_ERR_INVALID_ARG, "NULL argument");
+  if (!h->have_run) return fail(SWARM_ERR_STATE, "no completed run");
+  *out = h->tallies;
+  return SWARM_OK;
+}
+
+swarm_status swarm_records(swarm_t h, swarm_record* out, int64_t max_records, int64_t* n_out) {
+  if (!h || !n_out) return fail(SWARM_ERR_INVALID_ARG, "NULL argument");
+  if (!h->have_run) return fail(SWARM_ERR_STATE, "no completed run");
+  *n_out = h->n_records;
+  const int64_t n = std::min(max_records, h->n_records);
+  if (out && n > 0) {
+    hipError_t e = hipMemcpyAsync(out, h->desc.records, static_cast<size_t>(n) * sizeof(swarm_record),
+                                  hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "copying records");
+  }
+  return SWARM_OK;
+}
+
+swarm_status swarm_trace_events(swarm_t h, swarm_event* out, int32_t* counts) {
+  if (!h || !out || !counts) return fail(SWARM_ERR_INVALID_ARG, "NULL argument");
+  if (!h->have_run || !h->traced) return fail(SWARM_ERR_STATE, "no traced run");
+  hipError_t e = hipMemcpyAsync(out, h->trace_out.p, static_cast<size_t>(h->n_trace) * h->max_events * sizeof(swarm_event),
+                                hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(counts, h->trace_count.p, h->n_trace * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(e, "copying trace");
+  return SWARM_OK;
+}
+
+swarm_status swarm_tables(swarm_t h, int32_t* grid_size, int32_t* n_channels, double* nodes, double* cum,
+                          double* majorant) {
+  if (!h) return fail(SWARM_ERR_INVALID_ARG, "handle is NULL");
+  if (grid_size) *grid_size = h->desc.G;
+  if (n_channels) *n_channels = h->desc.nc;
+  if (majorant) *majorant = h->desc.majorant;
+  hipError_t e = hipSuccess;
+  if (nodes) e = hipMemcpyAsync(nodes, h->desc.nodes, h->desc.G * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess && cum)
+    e = hipMemcpyAsync(cum, h->desc.cum_cm, static_cast<size_t>(h->desc.G) * h->desc.nc * sizeof(double),
+                       hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(e, "copying tables");
+  return SWARM_OK;
+}
+
+swarm_status swarm_last_timing(swarm_t h, double* kernel_ms, double* total_ms) {
+  if (!h) return fail(SWARM_ERR_INVALID_ARG, "handle is NULL");
+  if (!h->have_run) return fail(SWARM_ERR_STATE, "no completed run");
+  if (kernel_ms) *kernel_ms = h->kernel_ms;
+  if (total_ms) *total_ms = h->total_ms;
+  return SWARM_OK;
+}
+
+}  // extern "C"

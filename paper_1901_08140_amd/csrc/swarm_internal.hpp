@@ -1,0 +1,154 @@
+// Internal structures shared by the host runtime (swarm_api.cpp) and the device code
+// (swarm_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/swarm.h"
+
+namespace swarm_impl {
+
+constexpr int kMaxTraceIds = 256;
+constexpr int kTallyTile = 2048;          // records per tally work-group (fixed: determinism)
+constexpr int kTallyThreads = 256;
+constexpr int kTally1 = 24;               // pass-1 accumulators
+constexpr int kTally2 = 32;               // pass-2 accumulators
+constexpr uint32_t kMaxBlocks = 0x7fffffffu;   // per-electron cap on trial blocks
+
+// Lane states of the swarm kernels.
+enum : int { ST_ACTIVE = 0, ST_PENDING = 1, ST_IDLE = 2, ST_WAIT = 3, ST_DONE = 4, ST_STOPPED = 5 };
+
+// Per-channel constants built on the device from the raw inputs.
+struct ChannelDev {
+  int32_t kind;
+  int32_t comp;
+  double thr;      // threshold (eV)
+  double onset;    // thr * (m+M)/M: lowest energy at which the inelastic process is allowed
+  double c_ela;    // 2 m M / (m+M)^2
+  double c_M;      // M / (m+M)
+  double c_mM;     // (m+M) / M
+  float thr_f, c_ela_f, c_M_f, c_mM_f;
+};
+
+// Saved electron state at a real-collision boundary (serving epochs resume from it).
+struct SavedState {
+  double r[3], t;
+  double v[3];
+  double sum_eps, sum_epsp;
+  uint64_t id;
+  uint32_t block, k, k_start, G, D, n_forb, n_over, n_null;
+  uint32_t started, pad;
+};
+
+// Child electron waiting in the real-secondaries queue.
+struct ChildState {
+  double r[3], t;
+  double v[3];
+  uint64_t id;
+  uint32_t k, pad;
+};
+
+// Device counters of one instance's run.
+struct RunCounters {
+  uint64_t prim_next;     // real mode: next primary index
+  uint64_t child_tail;    // real mode: reserved child slots
+  uint64_t child_head;    // real mode: claimed child slots
+  int64_t live;           // real mode: electrons not yet stopped (queued or running)
+  uint64_t dropped;       // secondaries that did not fit the capacity
+  uint64_t n_done;        // electrons that reached their final real collision or stopped
+  uint64_t poll_overrun;  // waves that hit the bounded-wait limit (must stay 0)
+  uint64_t pad;
+};
+
+// One swarm instance as seen by the kernels.  Fields in the first group are written by
+// the host (pointers, sizes, run parameters); the physics constants in the second group
+// are computed by the build kernels from the raw inputs.
+struct InstanceDesc {
+  // ---- host-written ----------------------------------------------------------------
+  int32_t G, nc, p_log2, emin, emax;
+  int32_t n_raw_channels;
+  int32_t precision, secondaries;
+  double E, B, B_angle, N, eps0, user_majorant;
+  const double* raw_e;        // concatenated raw energies
+  const double* raw_s;        // concatenated raw cross-sections
+  const int32_t* raw_off;     // per channel: first point
+  const int32_t* raw_n;       // per channel: number of points
+  const int32_t* raw_kind;
+  const int32_t* raw_comp;
+  const double* raw_thr;
+  const double* comp_mass_amu;
+  const double* comp_frac;
+  double* nodes;              // G node energies (eV)
+  double* cum_cm;             // nc x G running sums, channel major (FP64)
+  double2* nu64;              // G pairs (F, F[g+1]-F[g]) of the total rate
+  float2* nu32;
+  double2* cum64;             // G x nc pairs, node major
+  float2* cum32;
+  ChannelDev* chan;
+  // run parameters
+  int64_t n_electrons;
+  uint32_t n_collisions;
+  uint32_t quantum;           // real collisions per electron per launch (0 = no limit)
+  uint64_t seed;
+  int64_t capacity;           // real mode: records available
+  swarm_record* records;      // per-electron results
+  SavedState* saved;          // resumable runs (serving); NULL otherwise
+  ChildState* children;       // real mode queue
+  uint32_t* child_ready;      // real mode ready flags
+  RunCounters* ctr;
+  // tracing
+  const uint64_t* trace_ids;
+  int32_t n_trace, max_events;
+  swarm_event* trace_out;
+  int32_t* trace_count;
+  // ---- device-written (build kernels) ------------------------------------------------
+  double majorant, inv_majorant;
+  double c_eps;               // m / (2 e): eps (eV) = c_eps |v|^2
+  double c_speed;             // sqrt(2 e / m): |v| = c_speed sqrt(eps)
+  double speed0;
+  double az;                  // -e E / m (acceleration along z)
+  double omega;               // e B / m
+  double bx, bz;              // unit vector of B
+  double vDy;                 // E x B / B^2 = (0, E sin(th) / B, 0)
+  double apar;                // a . b
+  double numax;
+  float majorant_f, cT_f;     // cT_f = ln2 / nu' (flight time from log2)
+  float c_eps_f, c_speed_f, speed0_f, az_f, omega_rev_f, bx_f, bz_f, vDy_f, apar_f;
+  int32_t built_ok;           // 1 after a successful build, -1 if a node has zero rate
+  int32_t pad_;
+};
+
+struct WorkItem {
+  int32_t inst;
+  int32_t pad;
+  int64_t first;       // first electron index of the item
+  int64_t count;       // electrons in the item
+};
+
+struct TallyTile {
+  int32_t inst;
+  int32_t tile;        // tile index within the instance
+  int64_t first;
+  int64_t count;
+};
+
+// Launchers implemented in swarm_kernels.hip.
+hipError_t launch_build(InstanceDesc* d_desc, const InstanceDesc& h_desc, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
+hipError_t launch_swarm_dummy(const InstanceDesc* d_desc, const WorkItem* d_items, int32_t n_items,
+                              int32_t* d_item_counter, int precision, bool has_b, bool trace,
+                              int block_size, int grid, int pending_trigger, size_t lds_bytes,
+                              hipStream_t s);
+hipError_t launch_swarm_real(const InstanceDesc* d_desc, int precision, bool has_b, bool trace,
+                             int block_size, int grid, int pending_trigger, size_t lds_bytes,
+                             hipStream_t s);
+hipError_t launch_tallies(const InstanceDesc* d_desc, const TallyTile* d_tiles, int32_t n_tiles,
+                          const int32_t* d_tile_base, const int64_t* d_nrec, int32_t n_inst,
+                          double* d_part1, double* d_part2, double* d_tot1,
+                          swarm_tallies_t* d_out, hipStream_t s);
+int swarm_kernel_max_blocks_per_cu(int precision, bool has_b, bool trace, bool real, int block_size,
+                                   size_t lds_bytes);
+
+}  // namespace swarm_impl

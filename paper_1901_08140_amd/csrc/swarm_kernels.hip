@@ -1,0 +1,1230 @@
+// Device code of the MI355X electron-swarm library: rate-table build, the persistent
+// per-electron null-collision kernels (FP64 and FP32-mixed), and the deterministic tally
+// reductions.  Method: "Betaboltz: a Monte-Carlo simulation tool for gas scattering
+// processes" (arXiv 1901.08140), section "Theoretical framework" (eqs. freetime,
+// frequency, random_time, null_fraction, delta_energy_ela, delta_energy_ine), section
+// "Extension of the cross-section tables" and section "Determination of swarm attributes".
+//
+// Layout of the work: one electron per lane, its whole state in registers; the total
+// rate table of the instance is staged in LDS as (F[g], F[g+1]-F[g]) pairs on an octave
+// grid so that the per-trial null test is one LDS read and one FMA; the per-channel
+// running sums are read from global memory (L2) only at real collisions.  Random numbers
+// come from Philox4x32-10 keyed by the run seed with counter (block, stream tag, electron
+// id), so any electron's history is independent of scheduling.
+//
+// Built with -ffp-contract=off: every fused multiply-add below is written explicitly, so
+// the arithmetic of an electron is the same in every launch shape.
+
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include "swarm_internal.hpp"
+
+namespace swarm_impl {
+namespace {
+
+constexpr double kQe = 1.602176634e-19;     // C
+constexpr double kMe = 9.1093837015e-31;    // kg
+constexpr double kAmu = 1.66053906660e-27;  // kg
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kLn2 = 0.69314718055994530942;
+
+// ---------------------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 multiplications
+// (v_mad_u64_u32 on CDNA) and xors; the key schedule adds the Weyl constants per round.
+// ---------------------------------------------------------------------------------------
+struct W4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ W4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                      uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    const uint64_t p0 = static_cast<uint64_t>(c0) * 0xD2511F53u;
+    const uint64_t p1 = static_cast<uint64_t>(c2) * 0xCD9E8D57u;
+    const uint32_t n0 = static_cast<uint32_t>(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = static_cast<uint32_t>(p0 >> 32) ^ c3 ^ k1;
+    c1 = static_cast<uint32_t>(p1);
+    c3 = static_cast<uint32_t>(p0);
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return {c0, c1, c2, c3};
+}
+
+enum : uint32_t { TAG_TRIAL_HI = 0, TAG_TRIAL_LO = 1, TAG_SCAT_HI = 2, TAG_SCAT_LO = 3,
+                  TAG_INIT_HI = 4, TAG_INIT_LO = 5, TAG_CHILD = 6 };
+
+struct Key { uint32_t k0, k1; };
+
+__device__ __forceinline__ W4 draw(Key key, uint64_t id, uint32_t tag, uint32_t block) {
+  return philox10(block, tag, static_cast<uint32_t>(id), static_cast<uint32_t>(id >> 32), key.k0, key.k1);
+}
+
+// Uniforms on [0,1).  FP64: 53 bits, the HI word on top of the upper 21 bits of the LO
+// word (exact: both parts are integers scaled by powers of two).  FP32: the top 24 bits of
+// the HI word, i.e. the FP64 uniform truncated.
+__device__ __forceinline__ double uni(uint32_t hi, uint32_t lo, double) {
+  return fma(static_cast<double>(hi), 0x1.0p-32, static_cast<double>(lo >> 11) * 0x1.0p-53);
+}
+__device__ __forceinline__ float uni(uint32_t hi, uint32_t, float) {
+  return static_cast<float>(hi >> 8) * 0x1.0p-24f;
+}
+
+// Flight-time increment -ln(1-u)/nu' (eq. random_time).  FP32 uses the hardware log2 with
+// cT = ln2/nu'; FP64 the libm logarithm with cT = 1/nu'.  1-u is exact in both.
+__device__ __forceinline__ float flight(float u, float cT) { return -__builtin_amdgcn_logf(1.0f - u) * cT; }
+__device__ __forceinline__ double flight(double u, double cT) { return -log(1.0 - u) * cT; }
+
+__device__ __forceinline__ float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+__device__ __forceinline__ float fma_(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return fma(a, b, c); }
+
+// sin/cos of 2 pi u for u in [0,1): FP32 through the hardware unit (input in revolutions).
+__device__ __forceinline__ void sincos_rev(float u, float* s, float* c) {
+  *s = __builtin_amdgcn_sinf(u);
+  *c = __builtin_amdgcn_cosf(u);
+}
+__device__ __forceinline__ void sincos_rev(double u, double* s, double* c) {
+  sincos(2.0 * kPi * u, s, c);
+}
+
+// Isotropic unit vector: cos(Theta) = 1 - 2u, Phi = 2 pi u'.
+template <typename R>
+__device__ __forceinline__ void iso_dir(R uc, R up, R* nx, R* ny, R* nz) {
+  const R ct = R(1) - R(2) * uc;
+  const R st = sqrt_(fmax((R)0, (R(1) - ct) * (R(1) + ct)));
+  R s, c;
+  sincos_rev(up, &s, &c);
+  *nx = st * c;
+  *ny = st * s;
+  *nz = ct;
+}
+
+// Octave-grid position of an energy: eps = 2^e (1 + f), node g = (e - emin) P + floor(f P),
+// weight w = f P - floor(f P).  Both come straight from the binary representation (P is a
+// power of two), so they are exact.  Below the grid: node 0, w = 0; at or above the top
+// node 2^emax: the last node, w = 0 (`over` set).
+__device__ __forceinline__ void grid_pos(float eps, int off, int p, int G, int* g, float* w, bool* over) {
+  const uint32_t b = __float_as_uint(eps);
+  const int graw = static_cast<int>(b >> (23 - p)) - off;
+  const float w1 = __uint_as_float(((b << (9 + p)) >> 9) | 0x3F800000u) - 1.0f;
+  const bool in = (graw >= 0) & (graw < G - 1);
+  *g = graw < 0 ? 0 : (graw > G - 1 ? G - 1 : graw);
+  *w = in ? w1 : 0.0f;
+  *over = graw >= G - 1;
+}
+__device__ __forceinline__ void grid_pos(double eps, int off, int p, int G, int* g, double* w, bool* over) {
+  const uint64_t b = static_cast<uint64_t>(__double_as_longlong(eps));
+  const int64_t graw = static_cast<int64_t>(b >> (52 - p)) - off;
+  const uint64_t mb = ((b << (12 + p)) >> 12) | 0x3FF0000000000000ull;
+  const double w1 = __longlong_as_double(static_cast<long long>(mb)) - 1.0;
+  const bool in = (graw >= 0) & (graw < G - 1);
+  *g = graw < 0 ? 0 : (graw > G - 1 ? G - 1 : static_cast<int>(graw));
+  *w = in ? w1 : 0.0;
+  *over = graw >= G - 1;
+}
+
+template <typename R> struct Pair;
+template <> struct Pair<float> { using T = float2; };
+template <> struct Pair<double> { using T = double2; };
+
+// Interpolated value F[g] + w (F[g+1] - F[g]) from a (F, dF) pair.
+__device__ __forceinline__ float lerp_pair(float2 q, float w) { return fmaf(w, q.y, q.x); }
+__device__ __forceinline__ double lerp_pair(double2 q, double w) { return q.x + w * q.y; }
+
+// =======================================================================================
+// Table build (create time): raw tables -> extension -> rates on the octave grid ->
+// running sums over channels -> pairs for the kernels; then the trial frequency and the
+// field constants.  One thread per grid node.
+// =======================================================================================
+
+// Cross-section of raw channel c at eps with the extension rules of section "Extension of
+// the cross-section tables": elastic constant to the left of the table; inelastic zero
+// below threshold, with a (threshold, 0) point in front of a table that starts above it;
+// to the right the power law A eps^K through the last two points (zero if either is 0);
+// linear interpolation between points.
+__device__ double sigma_ext(const InstanceDesc& d, int c, double eps) {
+  const double* e = d.raw_e + d.raw_off[c];
+  const double* s = d.raw_s + d.raw_off[c];
+  const int n = d.raw_n[c];
+  const int kind = d.raw_kind[c];
+  const double thr = d.raw_thr[c];
+  bool lead = false;                       // virtual first point (thr, 0)
+  if (kind != SWARM_ELASTIC) {
+    if (eps < thr) return 0.0;
+    lead = e[0] > thr;
+  }
+  const double e_first = lead ? thr : e[0];
+  const double s_first = lead ? 0.0 : s[0];
+  if (eps <= e_first) return s_first;
+  if (eps > e[n - 1]) {
+    const double e1 = e[n - 2], e2 = e[n - 1], s1 = s[n - 2], s2 = s[n - 1];
+    if (!(s1 > 0.0) || !(s2 > 0.0)) return 0.0;
+    const double K = log(s2 / s1) / log(e2 / e1);
+    const double A = s2 / pow(e2, K);
+    return A * pow(eps, K);
+  }
+  if (lead && eps <= e[0]) {
+    const double t = (eps - thr) / (e[0] - thr);
+    return 0.0 + (s[0] - 0.0) * t;
+  }
+  // smallest i >= 1 with e[i] >= eps (binary search; e[0] < eps <= e[n-1])
+  int lo = 1, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (e[mid] < eps) lo = mid + 1; else hi = mid;
+  }
+  const double t = (eps - e[lo - 1]) / (e[lo] - e[lo - 1]);
+  return s[lo - 1] + (s[lo] - s[lo - 1]) * t;
+}
+
+__global__ void k_build_rates(InstanceDesc* desc) {
+  const InstanceDesc& d = *desc;
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= d.G) return;
+  const int P = 1 << d.p_log2;
+  const int o = g / P, i = g % P;
+  const double eps = ldexp(1.0 + static_cast<double>(i) / P, d.emin + o);
+  double acc = 0.0;
+  for (int c = 0; c < d.nc; ++c) {
+    const int comp = d.raw_comp[c];
+    const double dens = d.comp_frac[comp] * d.N;
+    // eq. frequency: nu_c = n_k sigma_c(eps) sqrt(2 eps / m), eps in joule
+    acc += dens * sigma_ext(d, c, eps) * sqrt(2.0 * eps * kQe / kMe);
+    d.cum_cm[static_cast<size_t>(c) * d.G + g] = acc;
+  }
+  d.nodes[g] = eps;
+}
+
+// Pairs (F[g], F[g+1]-F[g]) of every running sum (node major) and of the total rate.
+__global__ void k_build_pairs(InstanceDesc* desc) {
+  const InstanceDesc& d = *desc;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= static_cast<int64_t>(d.G) * d.nc) return;
+  const int g = static_cast<int>(idx / d.nc), c = static_cast<int>(idx % d.nc);
+  const double* F = d.cum_cm + static_cast<size_t>(c) * d.G;
+  const double f0 = F[g];
+  const double df = g + 1 < d.G ? F[g + 1] - f0 : 0.0;
+  d.cum64[idx] = make_double2(f0, df);
+  d.cum32[idx] = make_float2(static_cast<float>(f0), static_cast<float>(df));
+  if (c == d.nc - 1) {
+    d.nu64[g] = make_double2(f0, df);
+    d.nu32[g] = make_float2(static_cast<float>(f0), static_cast<float>(df));
+  }
+}
+
+// Trial frequency (maximum of the total rate, raised by 2^-20 so that the interpolated
+// rate never exceeds it: the paper's LazyTrialFrequency), channel constants and field
+// constants.  One work-group; fixed-order reduction.
+__global__ void k_build_constants(InstanceDesc* desc) {
+  InstanceDesc& d = *desc;
+  __shared__ double smax[256];
+  __shared__ int szero[256];
+  const double* F = d.cum_cm + static_cast<size_t>(d.nc - 1) * d.G;
+  double m = 0.0;
+  int zero = 0;
+  for (int g = threadIdx.x; g < d.G; g += blockDim.x) {
+    m = fmax(m, F[g]);
+    zero |= !(F[g] > 0.0);
+  }
+  smax[threadIdx.x] = m;
+  szero[threadIdx.x] = zero;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+      szero[threadIdx.x] |= szero[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  for (int c = threadIdx.x; c < d.nc; c += blockDim.x) {
+    const int comp = d.raw_comp[c];
+    const double M = d.comp_mass_amu[comp] * kAmu;
+    const double mm = kMe;
+    ChannelDev ch;
+    ch.kind = d.raw_kind[c];
+    ch.comp = comp;
+    ch.thr = d.raw_thr[c];
+    ch.onset = ch.thr * ((mm + M) / M);
+    ch.c_ela = 2.0 * mm * M / ((mm + M) * (mm + M));
+    ch.c_M = M / (mm + M);
+    ch.c_mM = (mm + M) / M;
+    ch.thr_f = static_cast<float>(ch.thr);
+    ch.c_ela_f = static_cast<float>(ch.c_ela);
+    ch.c_M_f = static_cast<float>(ch.c_M);
+    ch.c_mM_f = static_cast<float>(ch.c_mM);
+    d.chan[c] = ch;
+  }
+  if (threadIdx.x == 0) {
+    const double numax = smax[0];
+    d.numax = numax;
+    double nup = (1.0 + 0x1.0p-20) * numax;
+    int ok = szero[0] ? -1 : 1;
+    if (d.user_majorant > 0.0) {
+      if (d.user_majorant < numax) ok = -2;
+      nup = d.user_majorant;
+    }
+    d.built_ok = ok;
+    d.majorant = nup;
+    d.inv_majorant = 1.0 / nup;
+    d.majorant_f = static_cast<float>(nup);
+    d.cT_f = static_cast<float>(kLn2 / nup);
+    d.c_eps = 0.5 * kMe / kQe;
+    d.c_speed = sqrt(2.0 * kQe / kMe);
+    d.speed0 = sqrt(2.0 * d.eps0 * kQe / kMe);
+    d.az = -kQe * d.E / kMe;
+    d.omega = kQe * d.B / kMe;
+    d.bx = sin(d.B_angle);
+    d.bz = cos(d.B_angle);
+    d.vDy = d.B > 0.0 ? d.E * d.B * d.bx / (d.B * d.B) : 0.0;   // (E z^ x B b^)/B^2 = (0, E sin th / B, 0)
+    d.apar = d.az * d.bz;
+    d.c_eps_f = static_cast<float>(d.c_eps);
+    d.c_speed_f = static_cast<float>(d.c_speed);
+    d.speed0_f = static_cast<float>(d.speed0);
+    d.az_f = static_cast<float>(d.az);
+    d.omega_rev_f = static_cast<float>(d.omega / (2.0 * kPi));
+    d.bx_f = static_cast<float>(d.bx);
+    d.bz_f = static_cast<float>(d.bz);
+    d.vDy_f = static_cast<float>(d.vDy);
+    d.apar_f = static_cast<float>(d.apar);
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_fill_u64(uint64_t* p, uint64_t v, int64_t n) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+// =======================================================================================
+// Per-electron null-collision loop.
+// =======================================================================================
+
+// Instance constants in the working precision, loaded once per work item.
+template <typename R>
+struct Consts {
+  R nup, cT, c_eps, c_speed, speed0, az, omega, bx, bz, vDy, apar;
+  R omega_rev;   // FP32 trial phase in revolutions
+  bool magnetic; // B > 0 (kernels built for B may also serve B = 0 instances)
+  int G, nc, off, p;
+  uint32_t n_coll, quantum;
+  Key key;
+  const typename Pair<R>::T* cum;
+  const ChannelDev* chan;
+};
+
+template <typename R>
+__device__ __forceinline__ Consts<R> load_consts(const InstanceDesc& d) {
+  Consts<R> c;
+  if constexpr (sizeof(R) == 8) {
+    c.nup = d.majorant; c.cT = d.inv_majorant; c.c_eps = d.c_eps; c.c_speed = d.c_speed;
+    c.speed0 = d.speed0; c.az = d.az; c.omega = d.omega; c.bx = d.bx; c.bz = d.bz; c.vDy = d.vDy;
+    c.apar = d.apar; c.omega_rev = 0.0;
+    c.cum = reinterpret_cast<const typename Pair<R>::T*>(d.cum64);
+    c.off = (1023 + d.emin) << d.p_log2;
+  } else {
+    c.nup = d.majorant_f; c.cT = d.cT_f; c.c_eps = d.c_eps_f; c.c_speed = d.c_speed_f;
+    c.speed0 = d.speed0_f; c.az = d.az_f; c.omega = static_cast<float>(d.omega); c.bx = d.bx_f;
+    c.bz = d.bz_f; c.vDy = d.vDy_f; c.apar = d.apar_f; c.omega_rev = d.omega_rev_f;
+    c.cum = reinterpret_cast<const typename Pair<R>::T*>(d.cum32);
+    c.off = (127 + d.emin) << d.p_log2;
+  }
+  c.magnetic = d.B > 0.0;
+  c.G = d.G; c.nc = d.nc; c.p = d.p_log2;
+  c.n_coll = d.n_collisions; c.quantum = d.quantum;
+  c.key = {static_cast<uint32_t>(d.seed), static_cast<uint32_t>(d.seed >> 32)};
+  c.chan = d.chan;
+  return c;
+}
+
+template <typename R>
+struct Lane {
+  double rx, ry, rz, t;     // anchor (state right after the last real collision), FP64
+  R vx, vy, vz;             // anchor velocity
+  R T;                      // flight time since the anchor
+  R q0;                     // B = 0: vx^2 + vy^2;  B != 0: |vD|^2 + |u0|^2
+  R vpar;                   // B != 0: v0 . b
+  R u0x, u0y, u0z;          // B != 0: v0 - (v0.b) b - vD
+  R w0x, w0y, w0z;          // B != 0: b x u0
+  R Bc, Bs;                 // B != 0: 2 vD.u0, 2 vD.w0
+  double se, sep;           // sums of energies before / after real collisions
+  uint64_t id;
+  int64_t rec;              // record slot
+  uint32_t block, k, k_start, k_stop, G, D, nforb, nover, nnull, flags;
+  int state;
+  int trace_slot, n_ev;
+  R p_eps, p_x;             // pending real-collision candidate: energy and x = R nu'
+  uint32_t p_sub, p_block;
+};
+
+// Velocity-dependent constants of the flight that starts at the anchor.
+template <typename R, bool HB>
+__device__ __forceinline__ void set_anchor(Lane<R>& L, const Consts<R>& C) {
+  if (!HB || !C.magnetic) {
+    L.q0 = L.vx * L.vx + L.vy * L.vy;
+  } else {
+    L.vpar = L.vx * C.bx + L.vz * C.bz;
+    L.u0x = (L.vx - C.bx * L.vpar);
+    L.u0y = (L.vy - C.vDy);
+    L.u0z = (L.vz - C.bz * L.vpar);
+    L.w0x = -(C.bz * L.u0y);
+    L.w0y = C.bz * L.u0x - C.bx * L.u0z;
+    L.w0z = C.bx * L.u0y;
+    L.q0 = C.vDy * C.vDy + (L.u0x * L.u0x + L.u0y * L.u0y + L.u0z * L.u0z);
+    L.Bc = R(2) * C.vDy * L.u0y;
+    L.Bs = R(2) * C.vDy * L.w0y;
+  }
+}
+
+// |v(T)|^2 during free flight (classical motion in uniform E and B).
+template <typename R, bool HB>
+__device__ __forceinline__ R speed2_at(const Lane<R>& L, const Consts<R>& C, R T) {
+  if (!HB || !C.magnetic) {
+    const R vz = fma_(C.az, T, L.vz);
+    return fma_(vz, vz, L.q0);
+  } else {
+    R s, c;
+    if constexpr (sizeof(R) == 4) {
+      const float x = __builtin_amdgcn_fractf(C.omega_rev * T);
+      s = __builtin_amdgcn_sinf(x);
+      c = __builtin_amdgcn_cosf(x);
+    } else {
+      sincos(C.omega * T, &s, &c);
+    }
+    const R vp = fma_(C.apar, T, L.vpar);
+    return fma_(vp, vp, fma_(L.Bs, s, fma_(L.Bc, c, L.q0)));
+  }
+}
+
+// Velocity and displacement after a flight of duration T from the anchor (the same
+// equations of motion, written per component).
+template <typename R, bool HB>
+__device__ __forceinline__ void move_full(const Lane<R>& L, const Consts<R>& C, R T,
+                                          R* vx, R* vy, R* vz, double* rx, double* ry, double* rz) {
+  if (!HB || !C.magnetic) {
+    *vx = L.vx;
+    *vy = L.vy;
+    *vz = L.vz + C.az * T;
+    if constexpr (sizeof(R) == 8) {
+      *rx = L.rx + L.vx * T;
+      *ry = L.ry + L.vy * T;
+      *rz = (L.rz + L.vz * T) + C.az * (0.5 * T * T);
+    } else {
+      *rx = L.rx + static_cast<double>(L.vx * T);
+      *ry = L.ry + static_cast<double>(L.vy * T);
+      *rz = L.rz + static_cast<double>(fma_(C.az * 0.5f * T, T, L.vz * T));
+    }
+  } else {
+    R s, c, sh;
+    if constexpr (sizeof(R) == 4) {
+      const float x = __builtin_amdgcn_fractf(C.omega_rev * T);
+      s = __builtin_amdgcn_sinf(x);
+      c = __builtin_amdgcn_cosf(x);
+      sh = __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(0.5f * C.omega_rev * T));
+    } else {
+      const double wt = C.omega * T;
+      sincos(wt, &s, &c);
+      sh = sin(0.5 * wt);
+    }
+    const R omc = R(2) * sh * sh;   // 1 - cos(wT)
+    const R px = C.bx * L.vpar, pz = C.bz * L.vpar;       // v_par0
+    const R ax = C.bx * C.apar, az = C.bz * C.apar;       // a_par
+    *vx = ((px + ax * T) + R(0)) + (L.u0x * c + L.w0x * s);
+    *vy = ((R(0) + R(0) * T) + C.vDy) + (L.u0y * c + L.w0y * s);
+    *vz = ((pz + az * T) + R(0)) + (L.u0z * c + L.w0z * s);
+    const R hT2 = R(0.5) * T * T;
+    const R inv_w = R(1) / C.omega;
+    const R dx = ((px + R(0)) * T + ax * hT2) + (L.u0x * s + L.w0x * omc) * inv_w;
+    const R dy = ((R(0) + C.vDy) * T + R(0) * hT2) + (L.u0y * s + L.w0y * omc) * inv_w;
+    const R dz = ((pz + R(0)) * T + az * hT2) + (L.u0z * s + L.w0z * omc) * inv_w;
+    *rx = L.rx + static_cast<double>(dx);
+    *ry = L.ry + static_cast<double>(dy);
+    *rz = L.rz + static_cast<double>(dz);
+  }
+}
+
+// Start a primary: at the origin, energy eps0, isotropic direction from the INIT stream.
+template <typename R, bool HB>
+__device__ __forceinline__ void init_primary(Lane<R>& L, const Consts<R>& C, uint64_t id) {
+  const W4 h = draw(C.key, id, TAG_INIT_HI, 0);
+  W4 l = {0, 0, 0, 0};
+  if constexpr (sizeof(R) == 8) l = draw(C.key, id, TAG_INIT_LO, 0);
+  R nx, ny, nz;
+  iso_dir<R>(uni(h.x, l.x, R(0)), uni(h.y, l.y, R(0)), &nx, &ny, &nz);
+  L.vx = C.speed0 * nx;
+  L.vy = C.speed0 * ny;
+  L.vz = C.speed0 * nz;
+  L.rx = L.ry = L.rz = 0.0;
+  L.t = 0.0;
+  L.id = id;
+  L.k = L.k_start = 0;
+  L.block = 0;
+  L.G = L.D = L.nforb = L.nover = L.nnull = L.flags = 0;
+  L.se = L.sep = 0.0;
+  L.T = R(0);
+  set_anchor<R, HB>(L, C);
+}
+
+template <typename R>
+__device__ __forceinline__ void write_record(const InstanceDesc& d, const Lane<R>& L) {
+  swarm_record r;
+  r.id = L.id;
+  r.flags = L.flags;
+  r.k_start = L.k_start;
+  r.k_end = L.k;
+  r.G = L.G;
+  r.D = L.D;
+  r.n_forbidden = L.nforb;
+  r.n_over = L.nover;
+  r.pad = 0;
+  r.n_null = L.nnull;
+  r.blocks = L.block;
+  r.r[0] = L.rx; r.r[1] = L.ry; r.r[2] = L.rz;
+  r.t = L.t;
+  r.sum_eps = L.se;
+  r.sum_epsp = L.sep;
+  d.records[L.rec] = r;
+}
+
+template <typename R>
+__device__ __forceinline__ void save_state(const InstanceDesc& d, const Lane<R>& L, int64_t e) {
+  SavedState s;
+  s.r[0] = L.rx; s.r[1] = L.ry; s.r[2] = L.rz;
+  s.t = L.t;
+  s.v[0] = L.vx; s.v[1] = L.vy; s.v[2] = L.vz;
+  s.sum_eps = L.se;
+  s.sum_epsp = L.sep;
+  s.id = L.id;
+  s.block = L.block; s.k = L.k; s.k_start = L.k_start; s.G = L.G; s.D = L.D;
+  s.n_forb = L.nforb; s.n_over = L.nover; s.n_null = L.nnull;
+  s.started = 1; s.pad = L.flags;
+  d.saved[e] = s;
+}
+
+template <typename R, bool HB>
+__device__ __forceinline__ void load_state(const InstanceDesc& d, Lane<R>& L, const Consts<R>& C, int64_t e) {
+  const SavedState s = d.saved[e];
+  L.rx = s.r[0]; L.ry = s.r[1]; L.rz = s.r[2];
+  L.t = s.t;
+  L.vx = static_cast<R>(s.v[0]); L.vy = static_cast<R>(s.v[1]); L.vz = static_cast<R>(s.v[2]);
+  L.se = s.sum_eps; L.sep = s.sum_epsp;
+  L.id = s.id;
+  L.block = s.block; L.k = s.k; L.k_start = s.k_start; L.G = s.G; L.D = s.D;
+  L.nforb = s.n_forb; L.nover = s.n_over; L.nnull = s.n_null; L.flags = s.pad;
+  L.T = R(0);
+  set_anchor<R, HB>(L, C);
+}
+
+template <bool TR>
+__device__ __forceinline__ int find_trace(const InstanceDesc& d, uint64_t id) {
+  if constexpr (!TR) {
+    return -1;
+  } else {
+    for (int i = 0; i < d.n_trace; ++i)
+      if (d.trace_ids[i] == id) return i;
+    return -1;
+  }
+}
+
+template <typename R, bool TR>
+__device__ __forceinline__ void trace_event(const InstanceDesc& d, Lane<R>& L, int type, int ch,
+                                            R eps, R epsp, double t, double rx, double ry, double rz) {
+  if constexpr (TR) {
+    if (L.trace_slot >= 0 && L.n_ev < d.max_events) {
+      swarm_event ev;
+      ev.id = L.id; ev.type = type; ev.channel = ch; ev.k = L.k; ev.block = L.p_block;
+      ev.sub = L.p_sub; ev.pad = 0; ev.eps = static_cast<double>(eps);
+      ev.epsp = static_cast<double>(epsp); ev.t = t; ev.r[0] = rx; ev.r[1] = ry; ev.r[2] = rz;
+      d.trace_out[static_cast<int64_t>(L.trace_slot) * d.max_events + L.n_ev] = ev;
+      L.n_ev += 1;
+      d.trace_count[L.trace_slot] = L.n_ev;
+    }
+  }
+}
+
+// One random-number block = two candidate trials (eq. random_time for the flight time,
+// eq. null_fraction for the real/null test with x = R nu' < nu(eps)).  A non-null
+// outcome of the first trial leaves the second unused.  The total rate comes from the
+// LDS pair table.
+template <typename R, bool HB>
+__device__ __forceinline__ void trial_block(Lane<R>& L, const Consts<R>& C,
+                                            const typename Pair<R>::T* __restrict__ s_nu) {
+  if (L.block >= kMaxBlocks) {
+    L.flags |= 4u;
+    L.state = ST_STOPPED;    // stopped at the cap: recorded and flagged
+    return;
+  }
+  const W4 h = draw(C.key, L.id, TAG_TRIAL_HI, L.block);
+  W4 l = {0, 0, 0, 0};
+  if constexpr (sizeof(R) == 8) l = draw(C.key, L.id, TAG_TRIAL_LO, L.block);
+  const uint32_t blk = L.block;
+  L.block = blk + 1;
+#pragma unroll
+  for (int sub = 0; sub < 2; ++sub) {
+    const uint32_t hf = sub ? h.z : h.x, hr = sub ? h.w : h.y;
+    const uint32_t lf = sub ? l.z : l.x, lr = sub ? l.w : l.y;
+    const R uf = uni(hf, lf, R(0));
+    const R ur = uni(hr, lr, R(0));
+    const R T = L.T + flight(uf, C.cT);
+    L.T = T;
+    const R eps = C.c_eps * speed2_at<R, HB>(L, C, T);
+    int g;
+    R w;
+    bool over;
+    grid_pos(eps, C.off, C.p, C.G, &g, &w, &over);
+    const R nu = lerp_pair(s_nu[g], w);
+    const R x = ur * C.nup;
+    if (x < nu) {
+      L.state = ST_PENDING;
+      L.p_eps = eps;
+      L.p_x = x;
+      L.p_sub = sub;
+      L.p_block = blk;
+      return;
+    }
+    L.nnull += 1;
+  }
+}
+
+// Outcome of serving a pending candidate.
+enum : int { RC_CONTINUE = 0, RC_STOP = 1 };
+
+// A pending candidate: channel selection (min c with x < C_c(eps)), the kinematic onset
+// check, isotropic scattering with Fraser-Mathieson energy transfer, ionisation and
+// attachment, then the anchor moves to the collision point.  Returns RC_STOP when the
+// electron has reached its stop count or was removed.
+template <typename R, bool HB, bool TR, bool REAL>
+__device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L, const Consts<R>& C,
+                                              bool* spawn, ChildState* child) {
+  *spawn = false;
+  const R eps = L.p_eps;
+  const R x = L.p_x;
+  int g;
+  R w;
+  bool over;
+  grid_pos(eps, C.off, C.p, C.G, &g, &w, &over);
+  const typename Pair<R>::T* row = C.cum + static_cast<int64_t>(g) * C.nc;
+  int lo = 0, hi = C.nc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (x < lerp_pair(row[mid], w)) hi = mid; else lo = mid + 1;
+  }
+  const ChannelDev ch = C.chan[lo];
+  R vx, vy, vz;
+  double rx, ry, rz;
+  move_full<R, HB>(L, C, L.T, &vx, &vy, &vz, &rx, &ry, &rz);
+  if (ch.kind == SWARM_EXCITATION || ch.kind == SWARM_IONIZATION) {
+    // Energy versus the inelastic onset eps_k (m+M)/M, compared in FP64.
+    double e64;
+    if constexpr (sizeof(R) == 8) {
+      e64 = eps;
+    } else {
+      const double dx = vx, dy = vy, dz = vz;
+      e64 = d.c_eps * (dx * dx + dy * dy + dz * dz);
+    }
+    if (e64 < ch.onset) {
+      L.nforb += 1;
+      trace_event<R, TR>(d, L, 2, lo, eps, eps, L.t + static_cast<double>(L.T), L.rx, L.ry, L.rz);
+      L.state = ST_ACTIVE;
+      return RC_CONTINUE;
+    }
+  }
+  if (over) L.nover += 1;
+  const W4 h = draw(C.key, L.id, TAG_SCAT_HI, L.k);
+  W4 l = {0, 0, 0, 0};
+  if constexpr (sizeof(R) == 8) l = draw(C.key, L.id, TAG_SCAT_LO, L.k);
+  R nx, ny, nz;
+  iso_dir<R>(uni(h.x, l.x, R(0)), uni(h.y, l.y, R(0)), &nx, &ny, &nz);
+  const R v2 = vx * vx + vy * vy + vz * vz;
+  R cos_t;
+  if constexpr (sizeof(R) == 8) cos_t = v2 > 0.0 ? (nx * vx + ny * vy + nz * vz) / sqrt(v2) : 0.0;
+  else cos_t = v2 > 0.0f ? (nx * vx + ny * vy + nz * vz) * rsqrt_(v2) : 0.0f;
+  R c_ela, c_M, c_mM, thr;
+  if constexpr (sizeof(R) == 8) { c_ela = ch.c_ela; c_M = ch.c_M; c_mM = ch.c_mM; thr = ch.thr; }
+  else { c_ela = ch.c_ela_f; c_M = ch.c_M_f; c_mM = ch.c_mM_f; thr = ch.thr_f; }
+  R epsp;
+  if (ch.kind == SWARM_ELASTIC) {
+    epsp = eps * (R(1) - c_ela * (R(1) - cos_t));                       // eq. delta_energy_ela
+  } else if (ch.kind == SWARM_ATTACHMENT) {
+    epsp = R(0);                                                       // plastic collision
+  } else {
+    const R ratio = thr / eps;
+    const R root = sqrt_(fmax(R(0), R(1) - c_mM * ratio));
+    epsp = eps * (R(1) - c_M * ratio + c_ela * (root * cos_t - R(1)));  // eq. delta_energy_ine
+  }
+  epsp = fmax(epsp, R(0));
+  L.se += static_cast<double>(eps);
+  bool removed = false;
+  if (ch.kind == SWARM_IONIZATION) {
+    epsp = epsp * R(0.5);            // equal sharing with the ejected electron
+    L.G += 1;
+    if constexpr (REAL) {
+      const W4 cw = draw(C.key, L.id, TAG_CHILD, L.k);
+      R sx, sy, sz;
+      iso_dir<R>(uni(h.z, l.z, R(0)), uni(h.w, l.w, R(0)), &sx, &sy, &sz);
+      const R sp = C.c_speed * sqrt_(epsp);
+      child->r[0] = rx; child->r[1] = ry; child->r[2] = rz;
+      child->t = L.t + static_cast<double>(L.T);
+      child->v[0] = sp * sx; child->v[1] = sp * sy; child->v[2] = sp * sz;
+      child->id = (static_cast<uint64_t>(cw.x) | (static_cast<uint64_t>(cw.y) << 32)) | (1ull << 63);
+      child->k = L.k + 1;
+      child->pad = 0;
+      *spawn = true;
+    }
+  } else if (ch.kind == SWARM_ATTACHMENT) {
+    L.D += 1;
+    if constexpr (REAL) removed = true;
+  }
+  L.sep += static_cast<double>(epsp);
+  const double tn = L.t + static_cast<double>(L.T);
+  trace_event<R, TR>(d, L, 1, lo, eps, epsp, tn, rx, ry, rz);
+  L.k += 1;
+  L.rx = rx; L.ry = ry; L.rz = rz;
+  L.t = tn;
+  L.T = R(0);
+  const R sp = C.c_speed * sqrt_(epsp);
+  L.vx = sp * nx; L.vy = sp * ny; L.vz = sp * nz;
+  if (removed) {
+    L.flags |= 2u;
+    return RC_STOP;
+  }
+  if (L.k >= L.k_stop) return RC_STOP;
+  set_anchor<R, HB>(L, C);
+  L.state = ST_ACTIVE;
+  return RC_CONTINUE;
+}
+
+// ---------------------------------------------------------------------------------------
+// Dummy-mode persistent kernel over work items (instance, electron range).  A work-group
+// claims an item, stages the instance's total-rate pairs in LDS (if it changed), and its
+// lanes take electrons of the item one after another.  Lanes that reach a real-collision
+// candidate wait; the wave serves all waiting lanes together once `pend_trig` of them
+// wait (or no lane can make progress otherwise), which keeps the costly collision code
+// from running for one lane at a time.
+// ---------------------------------------------------------------------------------------
+template <typename R, bool HB, bool TR>
+__global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restrict__ descs,
+                                                     const WorkItem* __restrict__ items, int n_items,
+                                                     int* __restrict__ item_ctr, int pend_trig) {
+  using PT = typename Pair<R>::T;
+  extern __shared__ __align__(16) unsigned char smem[];
+  PT* s_nu = reinterpret_cast<PT*>(smem);
+  __shared__ int s_item;
+  __shared__ int s_next;
+  int cur_inst = -1;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(item_ctr, 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
+    if (it >= n_items) break;
+    const WorkItem wi = items[it];
+    const int inst = __builtin_amdgcn_readfirstlane(wi.inst);
+    const InstanceDesc& d = descs[inst];
+    if (inst != cur_inst) {
+      const PT* src = reinterpret_cast<const PT*>(sizeof(R) == 8 ? static_cast<const void*>(d.nu64)
+                                                                 : static_cast<const void*>(d.nu32));
+      for (int g = threadIdx.x; g < d.G; g += blockDim.x) s_nu[g] = src[g];
+      cur_inst = inst;
+    }
+    if (threadIdx.x == 0) s_next = 0;
+    __syncthreads();
+    const Consts<R> C = load_consts<R>(d);
+    const int64_t count = wi.count;
+    Lane<R> L;
+    L.state = ST_IDLE;
+    L.trace_slot = -1;
+    L.n_ev = 0;
+    for (;;) {
+      if (L.state == ST_IDLE) {
+        const int e = atomicAdd(&s_next, 1);
+        if (e < count) {
+          const int64_t ei = wi.first + e;
+          const uint32_t started = d.saved != nullptr ? d.saved[ei].started : 0u;
+          if (started != 2u) {          // 2: finished in an earlier launch
+            L.rec = ei;
+            if (started == 1u) load_state<R, HB>(d, L, C, ei);
+            else init_primary<R, HB>(L, C, static_cast<uint64_t>(ei));
+            L.k_stop = C.quantum ? min(C.n_coll, L.k + C.quantum) : C.n_coll;
+            if constexpr (TR) {
+              L.trace_slot = find_trace<TR>(d, L.id);
+              L.n_ev = L.trace_slot >= 0 ? d.trace_count[L.trace_slot] : 0;
+            }
+            L.state = ST_ACTIVE;
+          }
+        } else {
+          L.state = ST_DONE;
+        }
+      }
+      if (L.state == ST_ACTIVE) trial_block<R, HB>(L, C, s_nu);
+      const uint64_t pend = __ballot(L.state == ST_PENDING);
+      const uint64_t act = __ballot(L.state == ST_ACTIVE);
+      if (pend != 0 && (__popcll(pend) >= pend_trig || act == 0)) {
+        if (L.state == ST_PENDING) {
+          bool spawn;
+          ChildState child;
+          if (real_collision<R, HB, TR, false>(d, L, C, &spawn, &child) == RC_STOP) L.state = ST_STOPPED;
+        }
+      }
+      // An electron that stopped leaves its final record (budget reached or block cap) or
+      // its resumable state (end of the launch's quantum).
+      if (L.state == ST_STOPPED) {
+        if (L.k >= C.n_coll || (L.flags & 4u)) {
+          if (L.k >= C.n_coll) L.flags |= 1u;
+          write_record(d, L);
+          atomicAdd(reinterpret_cast<unsigned long long*>(&d.ctr->n_done), 1ull);
+          if (d.saved != nullptr) d.saved[L.rec].started = 2u;
+        } else {
+          save_state(d, L, L.rec);
+        }
+        L.state = ST_IDLE;
+      }
+      if (__ballot(L.state != ST_DONE) == 0) break;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Real-secondaries kernel (one instance).  Lanes take primaries from a global counter and
+// then secondaries from a queue.  A secondary is appended with one atomic per wave (ballot
+// of the ionising lanes, prefix rank from the lane mask) and published with a ready flag
+// after its state is written.  The kernel ends when every electron has stopped (`live`
+// reaches 0); idle waves sleep between polls and give up after a bounded number of polls.
+// ---------------------------------------------------------------------------------------
+template <typename R, bool HB, bool TR>
+__global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restrict__ desc, int pend_trig) {
+  using PT = typename Pair<R>::T;
+  extern __shared__ __align__(16) unsigned char smem[];
+  PT* s_nu = reinterpret_cast<PT*>(smem);
+  const InstanceDesc& d = *desc;
+  {
+    const PT* src = reinterpret_cast<const PT*>(sizeof(R) == 8 ? static_cast<const void*>(d.nu64)
+                                                               : static_cast<const void*>(d.nu32));
+    for (int g = threadIdx.x; g < d.G; g += blockDim.x) s_nu[g] = src[g];
+  }
+  __syncthreads();
+  const Consts<R> C = load_consts<R>(d);
+  RunCounters* ctr = d.ctr;
+  const int64_t N = d.n_electrons;
+  const int64_t child_cap = d.capacity - N;
+  Lane<R> L;
+  L.state = ST_IDLE;
+  L.trace_slot = -1;
+  L.n_ev = 0;
+  bool prim_left = true;
+  int64_t slot = -1;
+  uint32_t polls = 0;
+  const uint64_t lane_lt = (1ull << __lane_id()) - 1ull;
+  for (;;) {
+    if (L.state == ST_IDLE && prim_left) {
+      const uint64_t e = atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->prim_next), 1ull);
+      if (static_cast<int64_t>(e) < N) {
+        init_primary<R, HB>(L, C, e);
+        L.rec = static_cast<int64_t>(e);
+        L.k_stop = C.n_coll;
+        if constexpr (TR) {
+          L.trace_slot = find_trace<TR>(d, L.id);
+          L.n_ev = 0;
+        }
+        L.state = ST_ACTIVE;
+      } else {
+        prim_left = false;
+      }
+    }
+    if (L.state == ST_IDLE) {
+      // claim the next queue slot; it is filled when its parent ionises (or never, if the
+      // run ends first)
+      slot = static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->child_head), 1ull));
+      L.state = ST_WAIT;
+    }
+    if (L.state == ST_WAIT) {
+      bool got = false;
+      if (slot < child_cap) {
+        const uint32_t rdy = __hip_atomic_load(&d.child_ready[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (rdy != 0u) {
+          __atomic_thread_fence(__ATOMIC_ACQUIRE);
+          const ChildState cs = d.children[slot];
+          L.rx = cs.r[0]; L.ry = cs.r[1]; L.rz = cs.r[2];
+          L.t = cs.t;
+          L.vx = static_cast<R>(cs.v[0]); L.vy = static_cast<R>(cs.v[1]); L.vz = static_cast<R>(cs.v[2]);
+          L.id = cs.id;
+          L.k = L.k_start = cs.k;
+          L.k_stop = C.n_coll;
+          L.block = 0;
+          L.G = L.D = L.nforb = L.nover = L.nnull = L.flags = 0;
+          L.se = L.sep = 0.0;
+          L.T = R(0);
+          L.rec = N + slot;
+          set_anchor<R, HB>(L, C);
+          if constexpr (TR) {
+            L.trace_slot = find_trace<TR>(d, L.id);
+            L.n_ev = 0;
+          }
+          got = true;
+          // a secondary born at its lineage's last collision has nothing left to do
+          L.state = L.k >= L.k_stop ? ST_STOPPED : ST_ACTIVE;
+        }
+      }
+      if (!got) {
+        const int64_t live = __hip_atomic_load(&ctr->live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (live == 0) L.state = ST_DONE;
+      }
+    }
+    if (L.state == ST_ACTIVE) trial_block<R, HB>(L, C, s_nu);
+    const uint64_t pend = __ballot(L.state == ST_PENDING);
+    const uint64_t act = __ballot(L.state == ST_ACTIVE);
+    if (pend != 0 && (__popcll(pend) >= pend_trig || act == 0)) {
+      bool spawn = false;
+      ChildState child;
+      if (L.state == ST_PENDING) {
+        if (real_collision<R, HB, TR, true>(d, L, C, &spawn, &child) == RC_STOP) L.state = ST_STOPPED;
+      }
+      // append the secondaries of this wave: one reservation, ranks from the lane mask
+      const uint64_t sm = __ballot(spawn);
+      if (sm != 0) {
+        const int leader = __ffsll(static_cast<long long>(sm)) - 1;
+        unsigned long long base = 0;
+        if (static_cast<int>(__lane_id()) == leader) {
+          const unsigned long long n = __popcll(sm);
+          atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->live), n);
+          base = atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->child_tail), n);
+        }
+        base = __shfl(base, leader);
+        if (spawn) {
+          const int64_t s = static_cast<int64_t>(base + __popcll(sm & lane_lt));
+          if (s < child_cap) {
+            d.children[s] = child;
+            __atomic_thread_fence(__ATOMIC_RELEASE);
+            __hip_atomic_store(&d.child_ready[s], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          } else {
+            atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->dropped), 1ull);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->live), static_cast<unsigned long long>(-1ll));
+          }
+        }
+      }
+    }
+    if (L.state == ST_STOPPED) {
+      if (L.k >= C.n_coll && !(L.flags & 2u)) L.flags |= 1u;   // attached electrons are not finished
+      write_record(d, L);
+      atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->n_done), 1ull);
+      atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->live), static_cast<unsigned long long>(-1ll));
+      L.state = ST_IDLE;
+    }
+    const uint64_t busy = __ballot(L.state == ST_ACTIVE || L.state == ST_PENDING || L.state == ST_IDLE);
+    if (busy == 0) {
+      if (__ballot(L.state != ST_DONE) == 0) break;
+      __builtin_amdgcn_s_sleep(32);
+      if (++polls > (1u << 27)) {     // bounded wait: report and leave
+        if (__lane_id() == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->poll_overrun), 1ull);
+        break;
+      }
+    } else {
+      polls = 0;
+    }
+  }
+}
+
+// =======================================================================================
+// Tallies: two passes of fixed-tile, fixed-tree FP64 reductions (bitwise reproducible for
+// a given record order), then a finishing kernel per instance.
+// =======================================================================================
+
+__device__ __forceinline__ void block_sum(double* vals, int nq, double* s_red) {
+  // s_red: nq x kTallyThreads doubles.  Fixed pairwise tree over threads.
+  for (int q = 0; q < nq; ++q) s_red[q * kTallyThreads + threadIdx.x] = vals[q];
+  __syncthreads();
+  for (int s = kTallyThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+      for (int q = 0; q < nq; ++q)
+        s_red[q * kTallyThreads + threadIdx.x] += s_red[q * kTallyThreads + threadIdx.x + s];
+    __syncthreads();
+  }
+}
+
+// pass-1 accumulator indices
+enum {
+  T1_NF = 0, T1_VX, T1_VY, T1_VZ, T1_AG, T1_AD, T1_ZH, T1_GF, T1_DF,
+  T1_KREAL, T1_KNULL, T1_KFORB, T1_KOVER, T1_NATT, T1_NSTUCK, T1_NCREATED, T1_GALL, T1_DALL,
+  T1_SE, T1_SEP, T1_NK, T1_PE, T1_PEP, T1_NREC
+};
+// pass-2 accumulator indices
+enum {
+  T2_VX = 0, T2_VY, T2_VZ, T2_AG, T2_AD, T2_PE, T2_PEP,
+  T2_Q = 7   // then 12 diffusion quantities (paper form 6, vector form 6), value and square
+};
+
+__global__ void __launch_bounds__(kTallyThreads) k_tally1(const InstanceDesc* __restrict__ descs,
+                                                         const TallyTile* __restrict__ tiles,
+                                                         const int32_t* __restrict__ tile_base,
+                                                         double* __restrict__ part1) {
+  __shared__ double s_red[kTally1 * kTallyThreads];
+  const TallyTile tt = tiles[blockIdx.x];
+  const InstanceDesc& d = descs[tt.inst];
+  double a[kTally1];
+  for (int q = 0; q < kTally1; ++q) a[q] = 0.0;
+  for (int64_t j = threadIdx.x; j < tt.count; j += kTallyThreads) {
+    const swarm_record r = d.records[tt.first + j];
+    const double kr = static_cast<double>(r.k_end) - static_cast<double>(r.k_start);
+    a[T1_NREC] += 1.0;
+    a[T1_KREAL] += kr;
+    a[T1_KNULL] += static_cast<double>(r.n_null);
+    a[T1_KFORB] += static_cast<double>(r.n_forbidden);
+    a[T1_KOVER] += static_cast<double>(r.n_over);
+    a[T1_NATT] += (r.flags & 2u) ? 1.0 : 0.0;
+    a[T1_NSTUCK] += (r.flags & 4u) ? 1.0 : 0.0;
+    a[T1_NCREATED] += (r.id >> 63) ? 1.0 : 0.0;
+    a[T1_GALL] += static_cast<double>(r.G);
+    a[T1_DALL] += static_cast<double>(r.D);
+    a[T1_SE] += r.sum_eps;
+    a[T1_SEP] += r.sum_epsp;
+    if (kr > 0.0) {
+      a[T1_NK] += 1.0;
+      a[T1_PE] += r.sum_eps / kr;
+      a[T1_PEP] += r.sum_epsp / kr;
+    }
+    if (r.flags & 1u) {
+      const double zh = -r.r[2];
+      a[T1_NF] += 1.0;
+      a[T1_VX] += r.r[0] / r.t;
+      a[T1_VY] += r.r[1] / r.t;
+      a[T1_VZ] += r.r[2] / r.t;
+      a[T1_AG] += static_cast<double>(r.G) / zh;
+      a[T1_AD] += static_cast<double>(r.D) / zh;
+      a[T1_ZH] += zh;
+      a[T1_GF] += static_cast<double>(r.G);
+      a[T1_DF] += static_cast<double>(r.D);
+    }
+  }
+  block_sum(a, kTally1, s_red);
+  if (threadIdx.x < kTally1)
+    part1[(static_cast<int64_t>(tile_base[tt.inst]) + tt.tile) * kTally1 + threadIdx.x] =
+        s_red[threadIdx.x * kTallyThreads];
+}
+
+// Sum the tiles of each instance in tile order.
+__global__ void k_tally_sum(const int32_t* __restrict__ tile_base, const int64_t* __restrict__ nrec,
+                            const double* __restrict__ part, int nq, double* __restrict__ tot) {
+  const int inst = blockIdx.x;
+  const int q = threadIdx.x;
+  if (q >= nq) return;
+  const int ntiles = static_cast<int>((nrec[inst] + kTallyTile - 1) / kTallyTile);
+  double s = 0.0;
+  for (int t = 0; t < ntiles; ++t) s += part[(static_cast<int64_t>(tile_base[inst]) + t) * nq + q];
+  tot[static_cast<int64_t>(inst) * nq + q] = s;
+}
+
+__device__ __forceinline__ void diff6(double dx, double dy, double dz, double t, double* q) {
+  const double dz2 = dz * dz, dp2 = dx * dx + dy * dy;
+  q[0] = (dz2 + dp2) / t;
+  q[1] = dz2 / (2.0 * t);
+  q[2] = dp2 / (4.0 * t);
+  q[3] = 2.0 * sqrt(dz2 + dp2);
+  q[4] = 2.0 * fabs(dz);
+  q[5] = 2.0 * sqrt(dp2);
+}
+
+__global__ void __launch_bounds__(kTallyThreads) k_tally2(const InstanceDesc* __restrict__ descs,
+                                                         const TallyTile* __restrict__ tiles,
+                                                         const int32_t* __restrict__ tile_base,
+                                                         const double* __restrict__ tot1,
+                                                         double* __restrict__ part2) {
+  __shared__ double s_red[kTally2 * kTallyThreads];
+  const TallyTile tt = tiles[blockIdx.x];
+  const InstanceDesc& d = descs[tt.inst];
+  const double* t1 = tot1 + static_cast<int64_t>(tt.inst) * kTally1;
+  const double nf = t1[T1_NF];
+  const double mvx = t1[T1_VX] / nf, mvy = t1[T1_VY] / nf, mvz = t1[T1_VZ] / nf;
+  const double mag = t1[T1_AG] / nf, mad = t1[T1_AD] / nf;
+  const double mpe = t1[T1_PE] / t1[T1_NK], mpep = t1[T1_PEP] / t1[T1_NK];
+  double a[kTally2];
+  for (int q = 0; q < kTally2; ++q) a[q] = 0.0;
+  for (int64_t j = threadIdx.x; j < tt.count; j += kTallyThreads) {
+    const swarm_record r = d.records[tt.first + j];
+    const double kr = static_cast<double>(r.k_end) - static_cast<double>(r.k_start);
+    if (kr > 0.0) {
+      const double pe = r.sum_eps / kr - mpe, pep = r.sum_epsp / kr - mpep;
+      a[T2_PE] += pe * pe;
+      a[T2_PEP] += pep * pep;
+    }
+    if (r.flags & 1u) {
+      const double t = r.t;
+      const double vx = r.r[0] / t - mvx, vy = r.r[1] / t - mvy, vz = r.r[2] / t - mvz;
+      const double zh = -r.r[2];
+      const double ag = static_cast<double>(r.G) / zh - mag, ad = static_cast<double>(r.D) / zh - mad;
+      a[T2_VX] += vx * vx;
+      a[T2_VY] += vy * vy;
+      a[T2_VZ] += vz * vz;
+      a[T2_AG] += ag * ag;
+      a[T2_AD] += ad * ad;
+      double q[6];
+      diff6(r.r[0], r.r[1], r.r[2] - t * mvz, t, q);          // paper form: d = x - t W_z z^
+      for (int i = 0; i < 6; ++i) { a[T2_Q + i] += q[i]; a[T2_Q + 12 + i] += q[i] * q[i]; }
+      diff6(r.r[0] - t * mvx, r.r[1] - t * mvy, r.r[2] - t * mvz, t, q);   // vector form
+      for (int i = 0; i < 6; ++i) { a[T2_Q + 6 + i] += q[i]; a[T2_Q + 18 + i] += q[i] * q[i]; }
+    }
+  }
+  block_sum(a, kTally2 - 1, s_red);   // kTally2 - 1 = 31 accumulators used
+  if (threadIdx.x < kTally2 - 1)
+    part2[(static_cast<int64_t>(tile_base[tt.inst]) + tt.tile) * kTally2 + threadIdx.x] =
+        s_red[threadIdx.x * kTallyThreads];
+}
+
+__device__ __forceinline__ swarm_stat mk_stat(double mean, double ss_dev, double n) {
+  swarm_stat s;
+  s.value = mean;
+  const double sd = n > 1.0 ? sqrt(ss_dev / (n - 1.0)) : 0.0;
+  s.spread = sd;
+  s.stat_sigma = n > 0.0 ? sd / sqrt(n) : 0.0;
+  return s;
+}
+
+__device__ __forceinline__ swarm_stat mk_stat_sq(double sum, double sumsq, double n) {
+  const double mean = sum / n;
+  double ss = sumsq - sum * mean;
+  if (ss < 0.0) ss = 0.0;
+  return mk_stat(mean, ss, n);
+}
+
+__global__ void k_tally_final(const InstanceDesc* __restrict__ descs, const double* __restrict__ tot1,
+                              const double* __restrict__ tot2, swarm_tallies_t* __restrict__ out) {
+  const int inst = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  const InstanceDesc& d = descs[inst];
+  const double* a = tot1 + static_cast<int64_t>(inst) * kTally1;
+  const double* b = tot2 + static_cast<int64_t>(inst) * kTally2;
+  swarm_tallies_t T;
+  const double nf = a[T1_NF];
+  T.Wx = mk_stat(a[T1_VX] / nf, b[T2_VX], nf);
+  T.Wy = mk_stat(a[T1_VY] / nf, b[T2_VY], nf);
+  T.Wz = mk_stat(a[T1_VZ] / nf, b[T2_VZ], nf);
+  T.W = T.Wz;
+  T.W.value = -T.Wz.value;
+  const double kreal = a[T1_KREAL];
+  T.mean_energy = mk_stat(a[T1_PE] / a[T1_NK], b[T2_PE], a[T1_NK]);
+  T.mean_energy_after = mk_stat(a[T1_PEP] / a[T1_NK], b[T2_PEP], a[T1_NK]);
+  T.mean_energy.value = a[T1_SE] / kreal;
+  T.mean_energy_after.value = a[T1_SEP] / kreal;
+  swarm_stat* dst[12] = {&T.D, &T.DL, &T.DT, &T.sigma, &T.sigmaL, &T.sigmaT,
+                         &T.D_vec, &T.DL_vec, &T.DT_vec, &T.sigma_vec, &T.sigmaL_vec, &T.sigmaT_vec};
+  for (int i = 0; i < 12; ++i) *dst[i] = mk_stat_sq(b[T2_Q + i], b[T2_Q + 12 + i], nf);
+  T.alpha = mk_stat(a[T1_AG] / nf, b[T2_AG], nf);
+  T.eta = mk_stat(a[T1_AD] / nf, b[T2_AD], nf);
+  T.alpha_rate = a[T1_GF] / a[T1_ZH];
+  T.eta_rate = a[T1_DF] / a[T1_ZH];
+  const double trials = kreal + a[T1_KNULL] + a[T1_KFORB];
+  T.efficiency = kreal / trials;
+  T.majorant = d.majorant;
+  T.n_real = static_cast<int64_t>(kreal);
+  T.n_null = static_cast<int64_t>(a[T1_KNULL]);
+  T.n_forbidden = static_cast<int64_t>(a[T1_KFORB]);
+  T.n_fail = 0;
+  T.n_over = static_cast<int64_t>(a[T1_KOVER]);
+  T.n_electrons = static_cast<int64_t>(a[T1_NREC]);
+  T.n_finished = static_cast<int64_t>(nf);
+  T.n_attached = static_cast<int64_t>(a[T1_NATT]);
+  T.n_stuck = static_cast<int64_t>(a[T1_NSTUCK]);
+  T.n_created = static_cast<int64_t>(a[T1_NCREATED]);
+  T.n_ionizations = static_cast<int64_t>(a[T1_GALL]);
+  T.n_attachments = static_cast<int64_t>(a[T1_DALL]);
+  T.n_dropped = d.ctr ? static_cast<int64_t>(d.ctr->dropped) : 0;
+  out[inst] = T;
+}
+
+template <typename R, bool HB, bool TR>
+void* dummy_fn() { return reinterpret_cast<void*>(&k_swarm_dummy<R, HB, TR>); }
+template <typename R, bool HB, bool TR>
+void* real_fn() { return reinterpret_cast<void*>(&k_swarm_real<R, HB, TR>); }
+
+void* pick_kernel(int precision, bool has_b, bool trace, bool real) {
+  const bool f32 = precision == SWARM_FP32_MIXED;
+#define SW_PICK(R)                                                                            \
+  if (real) {                                                                                 \
+    if (has_b) return trace ? real_fn<R, true, true>() : real_fn<R, true, false>();           \
+    return trace ? real_fn<R, false, true>() : real_fn<R, false, false>();                    \
+  }                                                                                           \
+  if (has_b) return trace ? dummy_fn<R, true, true>() : dummy_fn<R, true, false>();           \
+  return trace ? dummy_fn<R, false, true>() : dummy_fn<R, false, false>();
+  if (f32) { SW_PICK(float) }
+  SW_PICK(double)
+#undef SW_PICK
+}
+
+}  // namespace
+
+// =======================================================================================
+// Host-side launchers.
+// =======================================================================================
+hipError_t launch_build(InstanceDesc* d_desc, const InstanceDesc& h, hipStream_t s) {
+  hipLaunchKernelGGL(k_build_rates, dim3((h.G + 127) / 128), dim3(128), 0, s, d_desc);
+  const int64_t n = static_cast<int64_t>(h.G) * h.nc;
+  hipLaunchKernelGGL(k_build_pairs, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, d_desc);
+  hipLaunchKernelGGL(k_build_constants, dim3(1), dim3(256), 0, s, d_desc);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill_u32, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill_u64, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_swarm_dummy(const InstanceDesc* d_desc, const WorkItem* d_items, int32_t n_items,
+                              int32_t* d_item_counter, int precision, bool has_b, bool trace,
+                              int block_size, int grid, int pending_trigger, size_t lds_bytes,
+                              hipStream_t s) {
+  void* fn = pick_kernel(precision, has_b, trace, false);
+  void* args[] = {const_cast<InstanceDesc**>(&d_desc), const_cast<WorkItem**>(&d_items), &n_items,
+                  &d_item_counter, &pending_trigger};
+  return hipLaunchKernel(fn, dim3(grid), dim3(block_size), args, lds_bytes, s);
+}
+
+hipError_t launch_swarm_real(const InstanceDesc* d_desc, int precision, bool has_b, bool trace,
+                             int block_size, int grid, int pending_trigger, size_t lds_bytes,
+                             hipStream_t s) {
+  void* fn = pick_kernel(precision, has_b, trace, true);
+  void* args[] = {const_cast<InstanceDesc**>(&d_desc), &pending_trigger};
+  return hipLaunchKernel(fn, dim3(grid), dim3(block_size), args, lds_bytes, s);
+}
+
+hipError_t launch_tallies(const InstanceDesc* d_desc, const TallyTile* d_tiles, int32_t n_tiles,
+                          const int32_t* d_tile_base, const int64_t* d_nrec, int32_t n_inst,
+                          double* d_part1, double* d_part2, double* d_tot1,
+                          swarm_tallies_t* d_out, hipStream_t s) {
+  double* d_tot2 = d_tot1 + static_cast<int64_t>(n_inst) * kTally1;
+  hipLaunchKernelGGL(k_tally1, dim3(n_tiles), dim3(kTallyThreads), 0, s, d_desc, d_tiles, d_tile_base, d_part1);
+  hipLaunchKernelGGL(k_tally_sum, dim3(n_inst), dim3(64), 0, s, d_tile_base, d_nrec, d_part1, kTally1, d_tot1);
+  hipLaunchKernelGGL(k_tally2, dim3(n_tiles), dim3(kTallyThreads), 0, s, d_desc, d_tiles, d_tile_base, d_tot1, d_part2);
+  hipLaunchKernelGGL(k_tally_sum, dim3(n_inst), dim3(64), 0, s, d_tile_base, d_nrec, d_part2, kTally2, d_tot2);
+  hipLaunchKernelGGL(k_tally_final, dim3(n_inst), dim3(64), 0, s, d_desc, d_tot1, d_tot2, d_out);
+  return hipGetLastError();
+}
+
+int swarm_kernel_max_blocks_per_cu(int precision, bool has_b, bool trace, bool real, int block_size,
+                                   size_t lds_bytes) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pick_kernel(precision, has_b, trace, real),
+                                                   block_size, lds_bytes) != hipSuccess)
+    return 1;
+  return n > 0 ? n : 1;
+}
+
+}  // namespace swarm_impl

@@ -1,0 +1,427 @@
+// Serving: continuous batching of swarm requests on one GPU.
+//
+// A scheduler thread owns the device work.  Requests wait in FIFO order until the device
+// memory they need (tables, per-electron state and records) fits the HBM budget; admitted
+// requests keep that memory until they finish.  All admitted, unfinished requests advance
+// together in epochs: one persistent launch in which every unfinished electron makes up to
+// `quantum` more real collisions and stops at a real-collision boundary, saving its state.
+// Requests admitted while an epoch runs (their tables are built on a second stream) join
+// the next epoch.  Finished requests get their tallies reduced on the device and their
+// memory is released.  Since electrons stop only at real-collision boundaries and the
+// random streams are keyed by (seed, electron, counter), a request's results are the same
+// bits whatever it was batched with and however the epochs fell.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "swarm_api_internal.hpp"
+
+using namespace swarm_impl;
+
+namespace {
+
+struct ChannelCopy {
+  int32_t kind;
+  double thr;
+  std::vector<double> e, s;
+};
+struct ComponentCopy {
+  double mass, frac;
+  std::vector<ChannelCopy> ch;
+};
+
+struct Request {
+  int64_t ticket = 0;
+  std::vector<ComponentCopy> comps;
+  swarm_params params{};
+  int64_t n_e = 0, n_c = 0;
+  uint64_t seed = 0;
+  // scheduler state
+  swarm* h = nullptr;
+  DevBuf saved;
+  int slot = -1;
+  int64_t bytes = 0;
+  int64_t epochs = 0;
+  double submit_s = 0, admit_s = 0, done_s = 0;
+  swarm_status status = SWARM_PENDING;
+  swarm_tallies_t tallies{};
+};
+
+}  // namespace
+
+struct swarm_server {
+  swarm_server_params p{};
+  std::chrono::steady_clock::time_point t0;
+  hipStream_t compute = nullptr, setup = nullptr;
+  std::mutex mu;
+  std::condition_variable cv, cv_done;
+  std::deque<std::shared_ptr<Request>> pending;
+  std::vector<std::shared_ptr<Request>> active;
+  std::map<int64_t, std::shared_ptr<Request>> all;
+  int64_t next_ticket = 1;
+  int64_t n_unfinished = 0;
+  int64_t used_bytes = 0;
+  bool stop = false;
+  std::thread th;
+  // device state of the epochs
+  DevBuf ctrs, descs, items;
+  std::vector<int> free_slots;
+  int max_slots = 0;
+  TallyPlan tally;
+  double rate = 0.0;   // measured real collisions per second (adaptive quantum)
+
+  double now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+namespace {
+
+// Device memory charged for a request: tables (as allocated by swarm_create) plus records
+// and resumable state of every electron.
+int64_t request_bytes(const Request& r) {
+  int64_t nc = 0, pts = 0;
+  for (const auto& c : r.comps) {
+    nc += static_cast<int64_t>(c.ch.size());
+    for (const auto& ch : c.ch) pts += static_cast<int64_t>(ch.e.size());
+  }
+  const int P = r.params.grid_points_per_octave ? r.params.grid_points_per_octave : 64;
+  int emin = r.params.grid_min_exp2, emax = r.params.grid_max_exp2;
+  if (emin == 0 && emax == 0) { emin = -14; emax = 12; }
+  const int64_t G = static_cast<int64_t>(emax - emin) * P + 1;
+  const int64_t tables = 16 * pts + G * (8 + 16 + 8) + G * nc * (8 + 16 + 8) + nc * 64 + 4096;
+  return tables + r.n_e * static_cast<int64_t>(sizeof(swarm_record) + sizeof(SavedState));
+}
+
+swarm_status admit(swarm_server* s, const std::shared_ptr<Request>& r) {
+  std::vector<std::vector<swarm_channel>> chs(r->comps.size());
+  std::vector<swarm_component> comps(r->comps.size());
+  for (size_t k = 0; k < r->comps.size(); ++k) {
+    for (auto& c : r->comps[k].ch)
+      chs[k].push_back({c.kind, c.thr, static_cast<int32_t>(c.e.size()), c.e.data(), c.s.data()});
+    comps[k] = {r->comps[k].mass, r->comps[k].frac, static_cast<int32_t>(chs[k].size()), chs[k].data()};
+  }
+  swarm_params p = r->params;
+  p.precision = s->p.precision;
+  p.secondaries = SWARM_DUMMY;
+  p.stream = s->setup;
+  swarm_t h = nullptr;
+  swarm_status st = swarm_create(comps.data(), static_cast<int32_t>(comps.size()), &p, &h);
+  if (st != SWARM_OK) return st;
+  r->h = h;
+  hipError_t e;
+  if ((e = h->records.ensure(static_cast<size_t>(r->n_e) * sizeof(swarm_record))) != hipSuccess ||
+      (e = r->saved.ensure(static_cast<size_t>(r->n_e) * sizeof(SavedState))) != hipSuccess)
+    return hip_fail(e, "request memory");
+  // saved.started = 0 for every electron: clear the whole state array
+  if ((e = launch_fill_u64(static_cast<uint64_t*>(r->saved.p), 0ull,
+                           static_cast<int64_t>(r->n_e) * sizeof(SavedState) / 8, s->setup)) != hipSuccess)
+    return hip_fail(e, "clearing state");
+  RunCounters* c = static_cast<RunCounters*>(s->ctrs.p) + r->slot;
+  if ((e = launch_fill_u64(reinterpret_cast<uint64_t*>(c), 0ull, sizeof(RunCounters) / 8, s->setup)) != hipSuccess)
+    return hip_fail(e, "clearing counters");
+  if ((e = hipStreamSynchronize(s->setup)) != hipSuccess) return hip_fail(e, "request setup");
+  InstanceDesc& d = h->desc;
+  d.n_electrons = r->n_e;
+  d.n_collisions = static_cast<uint32_t>(r->n_c);
+  d.seed = r->seed;
+  d.capacity = r->n_e;
+  d.records = static_cast<swarm_record*>(h->records.p);
+  d.saved = static_cast<SavedState*>(r->saved.p);
+  d.children = nullptr;
+  d.child_ready = nullptr;
+  d.ctr = c;
+  d.trace_ids = nullptr;
+  d.n_trace = 0;
+  d.trace_out = nullptr;
+  d.trace_count = nullptr;
+  return SWARM_OK;
+}
+
+void finish(swarm_server* s, const std::shared_ptr<Request>& r, swarm_status st) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  r->status = st;
+  r->done_s = s->now();
+  if (r->h) {
+    swarm_destroy(r->h);
+    r->h = nullptr;
+  }
+  r->saved.reset();
+  if (r->slot >= 0) s->free_slots.push_back(r->slot);
+  r->slot = -1;
+  s->used_bytes -= r->bytes;
+  r->bytes = 0;
+  r->comps.clear();
+  --s->n_unfinished;
+  s->cv_done.notify_all();
+}
+
+// Admit queued requests in arrival order while they fit the budget and a slot is free.
+void admit_pending(swarm_server* s) {
+  for (;;) {
+    std::shared_ptr<Request> r;
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      if (s->pending.empty() || s->free_slots.empty()) return;
+      const int64_t need = request_bytes(*s->pending.front());
+      if (s->used_bytes + need > s->p.hbm_budget_bytes && !s->active.empty()) return;
+      r = s->pending.front();
+      s->pending.pop_front();
+      r->slot = s->free_slots.back();
+      s->free_slots.pop_back();
+      r->bytes = need;
+      s->used_bytes += need;
+      r->admit_s = s->now();
+    }
+    const swarm_status st = admit(s, r);
+    if (st != SWARM_OK) {
+      finish(s, r, st);
+      continue;
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->active.push_back(r);
+  }
+}
+
+void scheduler(swarm_server* s) {
+  std::vector<InstanceDesc> descs;
+  std::vector<WorkItem> items;
+  hipEvent_t ev0, ev1;
+  (void)hipEventCreate(&ev0);
+  (void)hipEventCreate(&ev1);
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv.wait(lk, [&] { return s->stop || !s->pending.empty() || !s->active.empty(); });
+      if (s->stop && s->active.empty() && s->pending.empty()) break;
+    }
+    admit_pending(s);
+    std::vector<std::shared_ptr<Request>> act;
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      act = s->active;
+    }
+    if (act.empty()) continue;
+    // epoch quantum: fixed, or sized so that an epoch lasts about 50 ms at the measured rate
+    int64_t electrons = 0, max_nc = 0;
+    for (auto& r : act) { electrons += r->n_e; max_nc = std::max(max_nc, r->n_c); }
+    int64_t q = s->p.quantum_collisions;
+    if (q <= 0) {
+      q = s->rate > 0 ? static_cast<int64_t>(0.05 * s->rate / std::max<int64_t>(1, electrons)) : 1000;
+      q = std::max<int64_t>(64, std::min<int64_t>(q, max_nc));
+    }
+    descs.clear();
+    std::vector<int64_t> ne, nc;
+    int G = 0;
+    bool magnetic = false;
+    for (auto& r : act) {
+      InstanceDesc d = r->h->desc;
+      d.quantum = static_cast<uint32_t>(std::min<int64_t>(q, 0xffffffffLL));
+      descs.push_back(d);
+      ne.push_back(r->n_e);
+      nc.push_back(r->n_c);
+      G = std::max(G, d.G);
+      magnetic |= r->h->has_b;
+      r->epochs += 1;
+    }
+    const swarm_launch_opts o = resolve_opts(&s->p.opts, s->p.precision);
+    make_items(ne, nc, o.chunk, items);
+    hipError_t e;
+    bool ok = (e = s->descs.ensure(descs.size() * sizeof(InstanceDesc))) == hipSuccess &&
+              (e = s->items.ensure(items.size() * sizeof(WorkItem) + 256)) == hipSuccess;
+    int32_t* item_ctr = ok ? reinterpret_cast<int32_t*>(static_cast<char*>(s->items.p) + items.size() * sizeof(WorkItem)) : nullptr;
+    const size_t lds = lds_bytes_for(s->p.precision, G);
+    if (ok) ok = (e = hipMemcpyAsync(s->descs.p, descs.data(), descs.size() * sizeof(InstanceDesc), hipMemcpyHostToDevice, s->compute)) == hipSuccess &&
+                 (e = hipMemcpyAsync(s->items.p, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, s->compute)) == hipSuccess &&
+                 (e = launch_fill_u32(reinterpret_cast<uint32_t*>(item_ctr), 0u, 1, s->compute)) == hipSuccess &&
+                 (e = hipEventRecord(ev0, s->compute)) == hipSuccess;
+    if (ok) {
+      const int per_cu = swarm_kernel_max_blocks_per_cu(s->p.precision, magnetic, false, false, o.block_size, lds);
+      const int grid = std::max(1, std::min<int>(static_cast<int>(items.size()), device_info().n_cu * per_cu));
+      ok = (e = launch_swarm_dummy(static_cast<const InstanceDesc*>(s->descs.p), static_cast<const WorkItem*>(s->items.p),
+                                   static_cast<int32_t>(items.size()), item_ctr, s->p.precision, magnetic, false,
+                                   o.block_size, grid, o.pending_trigger, lds, s->compute)) == hipSuccess &&
+           (e = hipEventRecord(ev1, s->compute)) == hipSuccess;
+    }
+    // while the epoch runs, prepare the requests that arrived meanwhile
+    if (ok) admit_pending(s);
+    std::vector<RunCounters> hc(s->max_slots);
+    if (ok) ok = (e = hipMemcpyAsync(hc.data(), s->ctrs.p, s->max_slots * sizeof(RunCounters), hipMemcpyDeviceToHost, s->compute)) == hipSuccess &&
+                 (e = hipStreamSynchronize(s->compute)) == hipSuccess;
+    if (!ok) {
+      (void)hip_fail(e, "serving epoch");
+      for (auto& r : act) finish(s, r, SWARM_ERR_DEVICE);
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->active.clear();
+      continue;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ev0, ev1);
+    // finished requests: tallies on the device, then release
+    std::vector<std::shared_ptr<Request>> fin;
+    std::vector<int64_t> fin_n;
+    std::vector<InstanceDesc> fin_desc;
+    int64_t work = 0;
+    for (size_t i = 0; i < act.size(); ++i) {
+      const int64_t done_now = static_cast<int64_t>(hc[act[i]->slot].n_done);
+      work += std::min<int64_t>(q, act[i]->n_c) * act[i]->n_e;
+      if (done_now >= act[i]->n_e) {
+        fin.push_back(act[i]);
+        fin_n.push_back(act[i]->n_e);
+        fin_desc.push_back(descs[i]);
+      }
+    }
+    if (ms > 0) {
+      const double r_now = static_cast<double>(work) / (ms * 1e-3);
+      s->rate = s->rate > 0 ? 0.5 * s->rate + 0.5 * r_now : r_now;
+    }
+    if (!fin.empty()) {
+      DevBuf fd;
+      ok = (e = fd.ensure(fin_desc.size() * sizeof(InstanceDesc))) == hipSuccess &&
+           (e = hipMemcpyAsync(fd.p, fin_desc.data(), fin_desc.size() * sizeof(InstanceDesc), hipMemcpyHostToDevice, s->compute)) == hipSuccess &&
+           (e = s->tally.prepare(fin_n, s->compute)) == hipSuccess &&
+           (e = s->tally.launch(static_cast<const InstanceDesc*>(fd.p), s->compute)) == hipSuccess;
+      std::vector<swarm_tallies_t> out(fin.size());
+      if (ok) ok = (e = hipMemcpyAsync(out.data(), s->tally.d_out.p, out.size() * sizeof(swarm_tallies_t), hipMemcpyDeviceToHost, s->compute)) == hipSuccess &&
+                   (e = hipStreamSynchronize(s->compute)) == hipSuccess;
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (auto& r : fin) s->active.erase(std::find(s->active.begin(), s->active.end(), r));
+      }
+      for (size_t i = 0; i < fin.size(); ++i) {
+        if (ok) fin[i]->tallies = out[i];
+        else (void)hip_fail(e, "serving tallies");
+        finish(s, fin[i], ok ? SWARM_OK : SWARM_ERR_DEVICE);
+      }
+    }
+  }
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+}
+
+}  // namespace
+
+extern "C" {
+
+swarm_status swarm_server_create(const swarm_server_params* p, swarm_server_t* out) {
+  if (!p || !out) return fail(SWARM_ERR_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  if (p->hbm_budget_bytes <= 0) return fail(SWARM_ERR_INVALID_ARG, "hbm budget must be > 0");
+  if (p->precision != SWARM_FP64 && p->precision != SWARM_FP32_MIXED) return fail(SWARM_ERR_INVALID_ARG, "bad precision");
+  if (p->quantum_collisions < 0) return fail(SWARM_ERR_INVALID_ARG, "quantum must be >= 0");
+  auto s = std::make_unique<swarm_server>();
+  s->p = *p;
+  s->t0 = std::chrono::steady_clock::now();
+  s->max_slots = p->max_active > 0 ? p->max_active : 1024;
+  hipError_t e;
+  if (p->stream) s->compute = static_cast<hipStream_t>(p->stream);
+  else if ((e = hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
+  if ((e = hipStreamCreateWithFlags(&s->setup, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
+  if ((e = s->ctrs.ensure(s->max_slots * sizeof(RunCounters))) != hipSuccess) return hip_fail(e, "counters");
+  for (int i = s->max_slots - 1; i >= 0; --i) s->free_slots.push_back(i);
+  swarm_server* raw = s.get();
+  s->th = std::thread([raw] { scheduler(raw); });
+  *out = s.release();
+  return SWARM_OK;
+}
+
+swarm_status swarm_server_submit(swarm_server_t s, const swarm_component* comps, int32_t n_comps,
+                                 const swarm_params* params, int64_t n_electrons, int64_t n_collisions,
+                                 uint64_t seed, int64_t* ticket) {
+  if (!s || !comps || !params || !ticket) return fail(SWARM_ERR_INVALID_ARG, "NULL argument");
+  if (params->secondaries != SWARM_DUMMY) return fail(SWARM_ERR_INVALID_ARG, "serving takes dummy-secondaries requests");
+  if (n_electrons < 1) return fail(SWARM_ERR_INVALID_ARG, "n_electrons must be >= 1");
+  if (n_collisions < 1 || n_collisions > 0xffffffffLL) return fail(SWARM_ERR_INVALID_ARG, "bad n_collisions");
+  auto r = std::make_shared<Request>();
+  for (int k = 0; k < n_comps; ++k) {
+    ComponentCopy c;
+    c.mass = comps[k].mass_amu;
+    c.frac = comps[k].fraction;
+    for (int j = 0; j < comps[k].n_channels && comps[k].channels; ++j) {
+      const swarm_channel& q = comps[k].channels[j];
+      ChannelCopy ch;
+      ch.kind = q.kind;
+      ch.thr = q.threshold_eV;
+      if (q.n_points > 0 && q.energy_eV && q.sigma_m2) {
+        ch.e.assign(q.energy_eV, q.energy_eV + q.n_points);
+        ch.s.assign(q.sigma_m2, q.sigma_m2 + q.n_points);
+      }
+      c.ch.push_back(std::move(ch));
+    }
+    r->comps.push_back(std::move(c));
+  }
+  r->params = *params;
+  r->params.stream = nullptr;
+  r->n_e = n_electrons;
+  r->n_c = n_collisions;
+  r->seed = seed;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    r->ticket = s->next_ticket++;
+    r->submit_s = s->now();
+    s->pending.push_back(r);
+    s->all[r->ticket] = r;
+    ++s->n_unfinished;
+    *ticket = r->ticket;
+  }
+  s->cv.notify_all();
+  return SWARM_OK;
+}
+
+swarm_status swarm_server_poll(swarm_server_t s, int64_t ticket, swarm_tallies_t* out, swarm_request_info* info) {
+  if (!s) return fail(SWARM_ERR_INVALID_ARG, "server is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->all.find(ticket);
+  if (it == s->all.end()) return fail(SWARM_ERR_INVALID_ARG, "unknown ticket %lld", static_cast<long long>(ticket));
+  const Request& r = *it->second;
+  if (info) {
+    info->submit_s = r.submit_s;
+    info->admit_s = r.admit_s;
+    info->done_s = r.done_s;
+    info->n_real = r.status == SWARM_OK ? r.tallies.n_real : 0;
+    info->epochs = r.epochs;
+    info->bytes = r.bytes;
+  }
+  if (r.status == SWARM_PENDING) return SWARM_PENDING;
+  if (r.status != SWARM_OK) return fail(r.status, "request %lld failed", static_cast<long long>(ticket));
+  if (out) *out = r.tallies;
+  return SWARM_OK;
+}
+
+swarm_status swarm_server_drain(swarm_server_t s) {
+  if (!s) return fail(SWARM_ERR_INVALID_ARG, "server is NULL");
+  std::unique_lock<std::mutex> lk(s->mu);
+  s->cv_done.wait(lk, [&] { return s->n_unfinished == 0; });
+  return SWARM_OK;
+}
+
+double swarm_server_now(swarm_server_t s) { return s ? s->now() : 0.0; }
+
+void swarm_server_destroy(swarm_server_t s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv.notify_all();
+  if (s->th.joinable()) s->th.join();
+  for (auto& kv : s->all) {
+    if (kv.second->h) swarm_destroy(kv.second->h);
+    kv.second->h = nullptr;
+  }
+  if (s->setup) (void)hipStreamDestroy(s->setup);
+  if (!s->p.stream && s->compute) (void)hipStreamDestroy(s->compute);
+  delete s;
+}
+
+}  // extern "C"

@@ -16,6 +16,6 @@ from .tables import (  # noqa: F401
     grid_node_energies,
 )
 from .configs import (  # noqa: F401
-    SwarmConfig, td_to_field, cfg1_maxwell, cfg2_argon_sweep, cfg3_mixture_real,
-    cfg4_batch, cfg5_requests, N_DEFAULT,
+    SwarmConfig, td_to_field, cfg1_maxwell, cfg2_argon_sweep, cfg2_td_values, cfg3_mixture_real,
+    cfg4_batch, cfg4_mixtures, cfg5_request, cfg5_requests, mixture_ar_co2, N_DEFAULT, DUMMY, REAL,
 )
