@@ -24,15 +24,17 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic VALU work per unit (lane-instruction slots; transcendental and 32-bit integer
-# multiply instructions count 4 slots each, as they issue at quarter rate), FP32-mixed path,
-# B = 0.  Trial: half a Philox4x32-10 call (10 rounds x (2 mul-hi/lo x 4 + 2 xor)), two
-# uniforms, -ln(1-u)/nu', v_z and |v|^2 and eps, the octave-grid position from the bits,
-# the interpolated rate, x = R nu' and the compare.  Real collision: channel search,
-# onset compare, one Philox call, isotropic direction, cos(theta), energy transfer, FP64
-# position/time/energy-sum updates and the new velocity.  Derivation in the design notes.
-OPS_PER_TRIAL = 76
-OPS_PER_REAL = 185
+# Algorithmic VALU work per unit, in lane-instruction slots of the FP32-mixed path with
+# B = 0 (full-rate VALU instruction = 1 slot; transcendentals log/sqrt/rsqrt/sin/cos = 2, as
+# measured on gfx950; 32x32->64 integer multiply-add = 1, also measured full rate).
+# Trial (52): half a Philox4x32-10 call (20 multiply-adds + 40 xors per call), the flight
+# time from the 24-bit uniform (6 + log), x = R nu' (3), |v(T)|^2 m/2e (2 FMA), octave-grid
+# position from the bits (8), interpolated rate and compare (2).  Real collision (133): one
+# Philox call for the scattering block (60), channel search over the running sums (12),
+# onset compare in FP64 (8), isotropic direction (16), cos(theta) (6), energy transfer (3),
+# FP64 energy sums, position and time (16), new velocity (6), next-flight constants (4).
+OPS_PER_TRIAL = 52
+OPS_PER_REAL = 133
 PEAK_LANE_OPS = 256 * 64 * 2.4e9      # 256 CUs x 64 FP32 lanes/clock x 2.4 GHz = 3.93e13 /s
 
 
@@ -47,14 +49,34 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=5.0)
     ap.add_argument("--serve-seconds", type=float, default=8.0)
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the launch shape with the autotuner first (default: the library default)")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only copy this many bytes device-to-device a few times (counter calibration)")
     return ap.parse_args()
 
 
 def log(args, *a):
     if not args.quiet:
         print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def committed_traffic():
+    """HBM bytes per launch of the swarm kernel from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a copy of known size), or None if the kernel source
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "swarm_dummy_f32_argon_sweep_traffic.json")
+    src = os.path.join(ROOT, "paper_1901_08140_amd", "csrc", "swarm_kernels.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != sha:
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
 def agreement(a, b, keys):
@@ -67,24 +89,33 @@ def agreement(a, b, keys):
     return ok
 
 
-def cpu_baseline(args):
-    """The oracle as it stands, on the host cores, on a bounded sample of the workload."""
+def cpu_baseline(args, target_s=15.0):
+    """The oracle as it stands, on the host cores, on a bounded sample of the workload:
+    the first electrons of four E/N points of the sweep (1, 9.3, 108 and 1000 Td), each
+    with the full collision budget; the sample size is set from a short calibration run so
+    that the timed part takes about `target_s` seconds."""
     import oracle
     import synth
     cfgs = synth.cfg2_argon_sweep()
     idx = (0, 10, 21, 31)
-    n_e = 256
     threads = max(1, len(os.sched_getaffinity(0)))
-    t0 = time.perf_counter()
-    real = 0
-    trials = 0
-    for i in idx:
-        m = oracle.OracleModel.from_config(cfgs[i])
-        r = m.run(n_e, args.collisions, 0, n_threads=threads)
-        k = (r.records["k_end"].astype("i8") - r.records["k_start"]).sum()
-        real += int(k)
-        trials += int(k + r.records["n_null"].sum() + r.records["n_forbidden"].sum())
-    dt = time.perf_counter() - t0
+    models = [oracle.OracleModel.from_config(cfgs[i]) for i in idx]
+
+    def run(n_e):
+        real = trials = 0
+        t0 = time.perf_counter()
+        for m in models:
+            r = m.run(n_e, args.collisions, 0, n_threads=threads)
+            k = (r.records["k_end"].astype("i8") - r.records["k_start"]).sum()
+            real += int(k)
+            trials += int(k + r.records["n_null"].sum() + r.records["n_forbidden"].sum())
+        return real, trials, time.perf_counter() - t0
+
+    cal = max(threads, 8)
+    real, _, dt = run(cal)
+    n_e = int(max(threads, min(100_000, cal * target_s / max(dt, 1e-3))))
+    n_e = max(threads, (n_e // threads) * threads)
+    real, trials, dt = run(n_e)
     model = ""
     try:
         for line in open("/proc/cpuinfo"):
@@ -94,8 +125,9 @@ def cpu_baseline(args):
     except OSError:
         pass
     return {"value": real / dt, "unit": "real collisions/s", "cores": threads, "kind": "oracle",
-            "sample": f"electrons 0..{n_e - 1} x {args.collisions} collisions at E/N index {list(idx)} "
-                      f"of the 32-point sweep ({real:.3g} real collisions, {dt:.1f} s)",
+            "sample": f"electrons 0..{n_e - 1} x {args.collisions} real collisions at E/N "
+                      f"{[round(cfgs[i].extra['td'], 3) for i in idx]} Td of the sweep, FP64 "
+                      f"({real:.3g} real collisions in {dt:.1f} s)",
             "trials_per_s": trials / dt, "cpu_model": model}
 
 
@@ -145,15 +177,24 @@ def main():
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_probe:
+        n = args.copy_probe // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 4, "copies": 3}), flush=True)
+        return
     import paper_1901_08140_amd as sw
     import synth
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
     cfgs = synth.cfg2_argon_sweep(n_electrons=args.electrons, n_collisions=args.collisions)
     jobs = [(c.n_electrons, c.n_collisions, c.seed) for c in cfgs]
     h32 = [sw.Swarm.from_config(c, sw.SWARM_FP32_MIXED) for c in cfgs]
     handles = [h.h for h in h32]
     opts = {"use_graph": 1}
-    if not args.no_autotune:
+    if args.autotune:
         best = sw.swarm_autotune(handles, jobs, 300)
         opts.update(best)
         opts["use_graph"] = 1
@@ -192,12 +233,14 @@ def main():
         "efficiency": real_per_step / trials_per_step,
         "device_ms_per_step": avg_ms,
         "roofline": {"bound": "alu", "achieved": achieved / 1e9, "peak": PEAK_LANE_OPS / 1e9, "unit": "Gop/s",
-                     "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                     "frac": achieved / PEAK_LANE_OPS, "traffic": committed_traffic(),
                      "kernel": "k_swarm_dummy<float,false,false>",
                      "ops_per_trial": OPS_PER_TRIAL, "ops_per_real": OPS_PER_REAL},
     }
     if not args.no_fp64:
+        # the plain FP64 form: one swarm per launch, default launch shape
         h64 = [sw.Swarm.from_config(c, sw.SWARM_FP64) for c in cfgs]
+        h64[0].run(*jobs[0])       # warm-up
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for h, (ne, nc, seed) in zip(h64, jobs):
@@ -211,7 +254,23 @@ def main():
         out["fp64_plain"] = {"value": real64 / dt64, "unit": "real collisions/s", "seconds": dt64,
                              "speedup_fp32_batched": value / (real64 / dt64)}
         out["fp32_vs_fp64_within_tolerance"] = f"{agree}/{len(keys) * len(cfgs)}"
+        worst = {}
+        for k in keys:
+            rel = [abs(a[k][0] - b[k][0]) / abs(b[k][0]) for a, b in zip(tall32, tall64)
+                   if b[k][0] != 0 and math.isfinite(a[k][0]) and math.isfinite(b[k][0])]
+            worst[k] = max(rel) if rel else None
+        out["fp32_vs_fp64_max_rel_diff"] = worst
         log(args, f"fp64 plain {real64 / dt64:.3e}/s; fp32 within tolerance {agree}/{len(keys) * len(cfgs)}")
+        # the same FP64 work batched (separates the precision gain from the batching gain)
+        b64 = sw.swarm_batch_create([h.h for h in h64], jobs, {"use_graph": 1, **{k: v for k, v in opts.items()
+                                                                                 if k != "use_graph"}})
+        sw.swarm_batch_launch(b64)
+        ms64 = sw.swarm_batch_wait(b64)
+        sw.swarm_batch_destroy(b64)
+        out["fp64_batched"] = {"value": real64 / (ms64 * 1e-3), "unit": "real collisions/s",
+                               "device_ms": ms64}
+        del h64
+
     if args.serve_seconds > 0 and args.serve_rate > 0:
         out["serving"] = serve(sw, args)
         out["p50_latency_s"] = out["serving"]["p50_latency_s"]

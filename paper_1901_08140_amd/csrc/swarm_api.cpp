@@ -55,8 +55,10 @@ DeviceInfo& device_info() {
   return info;
 }
 
+// Dynamic LDS of the swarm kernels: the total-rate pairs of the G grid nodes plus one
+// padding entry in front.
 size_t lds_bytes_for(int precision, int G) {
-  return static_cast<size_t>(G) * (precision == SWARM_FP32_MIXED ? sizeof(float2) : sizeof(double2));
+  return static_cast<size_t>(G + 1) * (precision == SWARM_FP32_MIXED ? sizeof(float2) : sizeof(double2));
 }
 
 DevBuf::~DevBuf() { reset(); }
@@ -217,7 +219,8 @@ void make_items(const std::vector<int64_t>& n_e, const std::vector<int64_t>& n_c
   }
 }
 
-int default_block(int precision) { return precision == SWARM_FP32_MIXED ? 256 : 256; }
+// Default launch shape (the autotuner's usual pick on MI355X for the argon-like sweep).
+int default_block(int) { return 128; }
 
 swarm_launch_opts resolve_opts(const swarm_launch_opts* o, int precision) {
   swarm_launch_opts r{};
@@ -446,8 +449,13 @@ swarm_status swarm_run(swarm_t h, int64_t n_electrons, int64_t n_collisions, uin
   const int per_cu = swarm_kernel_max_blocks_per_cu(d.precision, h->has_b, trace, real, o.block_size, lds);
   if ((e = hipEventRecord(h->ev[0], s)) != hipSuccess) return hip_fail(e, "event");
   if (!real) {
+    // enough work items to give every resident work-group several of them
+    const int64_t slots = static_cast<int64_t>(dev.n_cu) * per_cu;
+    int64_t chunk = (n_electrons + 4 * slots - 1) / (4 * slots);
+    chunk = ((chunk + o.block_size - 1) / o.block_size) * o.block_size;
+    chunk = std::max<int64_t>(o.block_size, std::min<int64_t>(chunk, o.chunk));
     std::vector<WorkItem> items;
-    make_items({n_electrons}, {n_collisions}, o.chunk, items);
+    make_items({n_electrons}, {n_collisions}, chunk, items);
     if ((e = h->items.ensure(items.size() * sizeof(WorkItem) + 256)) != hipSuccess) return hip_fail(e, "work items");
     h->h_items = items;
     int32_t* d_ctr = reinterpret_cast<int32_t*>(static_cast<char*>(h->items.p) + items.size() * sizeof(WorkItem));

@@ -17,7 +17,12 @@ constexpr int kTally2 = 32;               // pass-2 accumulators
 constexpr uint32_t kMaxBlocks = 0x7fffffffu;   // per-electron cap on trial blocks
 
 // Lane states of the swarm kernels.
-enum : int { ST_ACTIVE = 0, ST_PENDING = 1, ST_IDLE = 2, ST_WAIT = 3, ST_DONE = 4, ST_STOPPED = 5 };
+// ACTIVE: drawing trials; PENDING: holds a real-collision candidate and draws its
+// scattering block in the next trial pass; READY: candidate and scattering words ready;
+// IDLE: needs an electron; WAIT: holds a secondary-queue slot; STOPPED: must store its
+// record or state; DONE: no more work.
+enum : int { ST_ACTIVE = 0, ST_PENDING = 1, ST_IDLE = 2, ST_WAIT = 3, ST_DONE = 4, ST_STOPPED = 5,
+             ST_READY = 6 };
 
 // Per-channel constants built on the device from the raw inputs.
 struct ChannelDev {
@@ -37,7 +42,7 @@ struct SavedState {
   double v[3];
   double sum_eps, sum_epsp;
   uint64_t id;
-  uint32_t block, k, k_start, G, D, n_forb, n_over, n_null;
+  uint32_t block, k, k_start, G, D, n_forb, n_over, n_first;
   uint32_t started, pad;
 };
 
@@ -115,6 +120,8 @@ struct InstanceDesc {
   double numax;
   float majorant_f, cT_f;     // cT_f = ln2 / nu' (flight time from log2)
   float c_eps_f, c_speed_f, speed0_f, az_f, omega_rev_f, bx_f, bz_f, vDy_f, apar_f;
+  float sceps_f, aze_f, apare_f, nup24_f, Pf_f, twoPf_f;   // FP32 energy-unit constants
+  double Pf_d, twoPf_d;
   int32_t built_ok;           // 1 after a successful build, -1 if a node has zero rate
   int32_t pad_;
 };

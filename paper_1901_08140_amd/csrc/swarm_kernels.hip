@@ -36,14 +36,18 @@ constexpr double kLn2 = 0.69314718055994530942;
 // ---------------------------------------------------------------------------------------
 struct W4 { uint32_t x, y, z, w; };
 
-__device__ __forceinline__ W4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                      uint32_t k0, uint32_t k1) {
+__device__ __forceinline__ uint32_t xor3_k(uint32_t a, uint32_t b, uint32_t k) { return a ^ b ^ k; }
+
+// Rounds 2..10 of Philox4x32-10 (the first round is done by the caller); k0, k1 are the
+// keys of round 2.
+__device__ __forceinline__ W4 philox_rounds9(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                            uint32_t k0, uint32_t k1) {
 #pragma unroll
-  for (int i = 0; i < 10; ++i) {
+  for (int i = 1; i < 10; ++i) {
     const uint64_t p0 = static_cast<uint64_t>(c0) * 0xD2511F53u;
     const uint64_t p1 = static_cast<uint64_t>(c2) * 0xCD9E8D57u;
-    const uint32_t n0 = static_cast<uint32_t>(p1 >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = static_cast<uint32_t>(p0 >> 32) ^ c3 ^ k1;
+    const uint32_t n0 = xor3_k(static_cast<uint32_t>(p1 >> 32), c1, k0);
+    const uint32_t n2 = xor3_k(static_cast<uint32_t>(p0 >> 32), c3, k1);
     c1 = static_cast<uint32_t>(p1);
     c3 = static_cast<uint32_t>(p0);
     c0 = n0;
@@ -54,6 +58,16 @@ __device__ __forceinline__ W4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
   return {c0, c1, c2, c3};
 }
 
+__device__ __forceinline__ W4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                      uint32_t k0, uint32_t k1) {
+  const uint64_t p0 = static_cast<uint64_t>(c0) * 0xD2511F53u;
+  const uint64_t p1 = static_cast<uint64_t>(c2) * 0xCD9E8D57u;
+  const uint32_t n0 = xor3_k(static_cast<uint32_t>(p1 >> 32), c1, k0);
+  const uint32_t n2 = xor3_k(static_cast<uint32_t>(p0 >> 32), c3, k1);
+  return philox_rounds9(n0, static_cast<uint32_t>(p1), n2, static_cast<uint32_t>(p0),
+                        k0 + 0x9E3779B9u, k1 + 0xBB67AE85u);
+}
+
 enum : uint32_t { TAG_TRIAL_HI = 0, TAG_TRIAL_LO = 1, TAG_SCAT_HI = 2, TAG_SCAT_LO = 3,
                   TAG_INIT_HI = 4, TAG_INIT_LO = 5, TAG_CHILD = 6 };
 
@@ -61,6 +75,24 @@ struct Key { uint32_t k0, k1; };
 
 __device__ __forceinline__ W4 draw(Key key, uint64_t id, uint32_t tag, uint32_t block) {
   return philox10(block, tag, static_cast<uint32_t>(id), static_cast<uint32_t>(id >> 32), key.k0, key.k1);
+}
+
+// The first Philox round of a trial block: counter word 2 (the electron id's low half)
+// is the same for every block of the electron, so its product is precomputed once per
+// electron (a = hi(M1 id_lo) ^ tag ^ k0, b = lo(M1 id_lo)); only M0 * block is new.
+struct TrialPre { uint32_t a, b, idhi; };
+
+__device__ __forceinline__ TrialPre trial_pre(Key key, uint64_t id, uint32_t tag) {
+  const uint64_t p1 = static_cast<uint64_t>(static_cast<uint32_t>(id)) * 0xCD9E8D57u;
+  return {static_cast<uint32_t>(p1 >> 32) ^ tag ^ key.k0, static_cast<uint32_t>(p1),
+          static_cast<uint32_t>(id >> 32)};
+}
+
+__device__ __forceinline__ W4 draw_trial(Key key, TrialPre pre, uint32_t block) {
+  const uint64_t p0 = static_cast<uint64_t>(block) * 0xD2511F53u;
+  const uint32_t n2 = xor3_k(static_cast<uint32_t>(p0 >> 32), pre.idhi, key.k1);
+  return philox_rounds9(pre.a, pre.b, n2, static_cast<uint32_t>(p0), key.k0 + 0x9E3779B9u,
+                        key.k1 + 0xBB67AE85u);
 }
 
 // Uniforms on [0,1).  FP64: 53 bits, the HI word on top of the upper 21 bits of the LO
@@ -293,6 +325,15 @@ __global__ void k_build_constants(InstanceDesc* desc) {
     d.bz_f = static_cast<float>(d.bz);
     d.vDy_f = static_cast<float>(d.vDy);
     d.apar_f = static_cast<float>(d.apar);
+    const double sc = sqrt(d.c_eps);
+    d.sceps_f = static_cast<float>(sc);
+    d.aze_f = static_cast<float>(d.az * sc);
+    d.apare_f = static_cast<float>(d.apar * sc);
+    d.nup24_f = d.majorant_f * 0x1.0p-24f;
+    d.Pf_d = static_cast<double>(1 << d.p_log2);
+    d.twoPf_d = 2.0 * d.Pf_d;
+    d.Pf_f = static_cast<float>(d.Pf_d);
+    d.twoPf_f = static_cast<float>(d.twoPf_d);
   }
 }
 
@@ -316,8 +357,13 @@ template <typename R>
 struct Consts {
   R nup, cT, c_eps, c_speed, speed0, az, omega, bx, bz, vDy, apar;
   R omega_rev;   // FP32 trial phase in revolutions
+  R aze, apare;  // accelerations in energy units (FP32: times sqrt(m/2e); FP64: plain)
+  R nup24;       // FP32: nu' 2^-24 (x = R nu' straight from the 24-bit integer)
+  R Pf, twoPf;   // grid points per octave, and twice that, as floating point
+  R sceps;       // FP32: sqrt(m/2e)
   bool magnetic; // B > 0 (kernels built for B may also serve B = 0 instances)
   int G, nc, off, p;
+  int off1;      // off - 1: index of the padded LDS table
   uint32_t n_coll, quantum;
   Key key;
   const typename Pair<R>::T* cum;
@@ -340,11 +386,19 @@ __device__ __forceinline__ Consts<R> load_consts(const InstanceDesc& d) {
     c.cum = reinterpret_cast<const typename Pair<R>::T*>(d.cum32);
     c.off = (127 + d.emin) << d.p_log2;
   }
+  if constexpr (sizeof(R) == 8) {
+    c.aze = d.az; c.apare = d.apar; c.nup24 = 0.0; c.sceps = 1.0;
+    c.Pf = d.Pf_d; c.twoPf = d.twoPf_d;
+  } else {
+    c.aze = d.aze_f; c.apare = d.apare_f; c.nup24 = d.nup24_f; c.sceps = d.sceps_f;
+    c.Pf = d.Pf_f; c.twoPf = d.twoPf_f;
+  }
   c.magnetic = d.B > 0.0;
   c.G = d.G; c.nc = d.nc; c.p = d.p_log2;
   c.n_coll = d.n_collisions; c.quantum = d.quantum;
   c.key = {static_cast<uint32_t>(d.seed), static_cast<uint32_t>(d.seed >> 32)};
   c.chan = d.chan;
+  c.off1 = c.off - 1;
   return c;
 }
 
@@ -358,21 +412,41 @@ struct Lane {
   R u0x, u0y, u0z;          // B != 0: v0 - (v0.b) b - vD
   R w0x, w0y, w0z;          // B != 0: b x u0
   R Bc, Bs;                 // B != 0: 2 vD.u0, 2 vD.w0
+  R e_q0, e_vz, e_vpar, e_Bc, e_Bs;  // the same in energy units (FP32 scaled by m/2e)
   double se, sep;           // sums of energies before / after real collisions
   uint64_t id;
   int64_t rec;              // record slot
-  uint32_t block, k, k_start, k_stop, G, D, nforb, nover, nnull, flags;
+  uint32_t block, k, k_start, k_stop, G, D, nforb, nover, flags;
+  uint32_t nfirst;          // blocks whose first trial was not null (real or forbidden)
   int state;
   int trace_slot, n_ev;
   R p_eps, p_x;             // pending real-collision candidate: energy and x = R nu'
   uint32_t p_sub, p_block;
+  TrialPre pre_hi, pre_lo;  // first-round Philox terms of the trial streams
+  W4 sh, sl;                // scattering block k (SCAT_HI / SCAT_LO words)
 };
 
-// Velocity-dependent constants of the flight that starts at the anchor.
+template <typename R>
+__device__ __forceinline__ void set_id(Lane<R>& L, const Consts<R>& C, uint64_t id) {
+  L.id = id;
+  L.pre_hi = trial_pre(C.key, id, TAG_TRIAL_HI);
+  if constexpr (sizeof(R) == 8) L.pre_lo = trial_pre(C.key, id, TAG_TRIAL_LO);
+}
+
+// Velocity-dependent constants of the flight that starts at the anchor.  FP32 keeps the
+// quantities the per-trial energy needs in energy units (velocities times sqrt(m/2e)),
+// so that eps = |v(T)|^2 m/2e costs no extra multiplication per trial.
 template <typename R, bool HB>
 __device__ __forceinline__ void set_anchor(Lane<R>& L, const Consts<R>& C) {
   if (!HB || !C.magnetic) {
     L.q0 = L.vx * L.vx + L.vy * L.vy;
+    if constexpr (sizeof(R) == 4) {
+      L.e_q0 = C.c_eps * L.q0;
+      L.e_vz = C.sceps * L.vz;
+    } else {
+      L.e_q0 = L.q0;
+      L.e_vz = L.vz;
+    }
   } else {
     L.vpar = L.vx * C.bx + L.vz * C.bz;
     L.u0x = (L.vx - C.bx * L.vpar);
@@ -384,15 +458,28 @@ __device__ __forceinline__ void set_anchor(Lane<R>& L, const Consts<R>& C) {
     L.q0 = C.vDy * C.vDy + (L.u0x * L.u0x + L.u0y * L.u0y + L.u0z * L.u0z);
     L.Bc = R(2) * C.vDy * L.u0y;
     L.Bs = R(2) * C.vDy * L.w0y;
+    if constexpr (sizeof(R) == 4) {
+      L.e_q0 = C.c_eps * L.q0;
+      L.e_Bc = C.c_eps * L.Bc;
+      L.e_Bs = C.c_eps * L.Bs;
+      L.e_vpar = C.sceps * L.vpar;
+    } else {
+      L.e_q0 = L.q0;
+      L.e_Bc = L.Bc;
+      L.e_Bs = L.Bs;
+      L.e_vpar = L.vpar;
+    }
   }
 }
 
-// |v(T)|^2 during free flight (classical motion in uniform E and B).
+// Energy (eV) during free flight, eps = (m/2e) |v(T)|^2 (classical motion in uniform E
+// and B).
 template <typename R, bool HB>
-__device__ __forceinline__ R speed2_at(const Lane<R>& L, const Consts<R>& C, R T) {
+__device__ __forceinline__ R energy_at(const Lane<R>& L, const Consts<R>& C, R T) {
   if (!HB || !C.magnetic) {
-    const R vz = fma_(C.az, T, L.vz);
-    return fma_(vz, vz, L.q0);
+    const R vz = fma_(C.aze, T, L.e_vz);
+    if constexpr (sizeof(R) == 4) return fmaf(vz, vz, L.e_q0);
+    else return C.c_eps * fma(vz, vz, L.e_q0);
   } else {
     R s, c;
     if constexpr (sizeof(R) == 4) {
@@ -402,9 +489,31 @@ __device__ __forceinline__ R speed2_at(const Lane<R>& L, const Consts<R>& C, R T
     } else {
       sincos(C.omega * T, &s, &c);
     }
-    const R vp = fma_(C.apar, T, L.vpar);
-    return fma_(vp, vp, fma_(L.Bs, s, fma_(L.Bc, c, L.q0)));
+    const R vp = fma_(C.apare, T, L.e_vpar);
+    const R v2 = fma_(vp, vp, fma_(L.e_Bs, s, fma_(L.e_Bc, c, L.e_q0)));
+    if constexpr (sizeof(R) == 4) return v2;
+    else return C.c_eps * v2;
   }
+}
+
+// Total rate at eps from the LDS table, which is padded with an (F[0], 0) entry in front:
+// entry g+1 holds node g, entry 0 serves energies below the grid and entry G (the top
+// node, whose difference is zero) energies at or above 2^emax, so the clamped index needs
+// no select on the weight.  Index and weight are exact: the node index comes from the
+// exponent and leading mantissa bits, w = frac((2 mant - 1) P).
+__device__ __forceinline__ float lds_rate(const float2* __restrict__ s_nu, float eps, const Consts<float>& C) {
+  const uint32_t b = __float_as_uint(eps);
+  const int gi = min(max(static_cast<int>(b >> (23 - C.p)) - C.off1, 0), C.G);
+  const float w = __builtin_amdgcn_fractf(fmaf(__builtin_amdgcn_frexp_mantf(eps), C.twoPf, -C.Pf));
+  const float2 q = s_nu[gi];
+  return fmaf(w, q.y, q.x);
+}
+__device__ __forceinline__ double lds_rate(const double2* __restrict__ s_nu, double eps, const Consts<double>& C) {
+  const uint32_t hi = static_cast<uint32_t>(static_cast<uint64_t>(__double_as_longlong(eps)) >> 32);
+  const int gi = min(max(static_cast<int>(hi >> (20 - C.p)) - C.off1, 0), C.G);
+  const double w = __builtin_amdgcn_fract(fma(__builtin_amdgcn_frexp_mant(eps), C.twoPf, -C.Pf));
+  const double2 q = s_nu[gi];
+  return q.x + w * q.y;
 }
 
 // Velocity and displacement after a flight of duration T from the anchor (the same
@@ -467,10 +576,10 @@ __device__ __forceinline__ void init_primary(Lane<R>& L, const Consts<R>& C, uin
   L.vz = C.speed0 * nz;
   L.rx = L.ry = L.rz = 0.0;
   L.t = 0.0;
-  L.id = id;
+  set_id(L, C, id);
   L.k = L.k_start = 0;
   L.block = 0;
-  L.G = L.D = L.nforb = L.nover = L.nnull = L.flags = 0;
+  L.G = L.D = L.nforb = L.nover = L.nfirst = L.flags = 0;
   L.se = L.sep = 0.0;
   L.T = R(0);
   set_anchor<R, HB>(L, C);
@@ -488,7 +597,9 @@ __device__ __forceinline__ void write_record(const InstanceDesc& d, const Lane<R
   r.n_forbidden = L.nforb;
   r.n_over = L.nover;
   r.pad = 0;
-  r.n_null = L.nnull;
+  // null trials: two per block, less the unused second trials (first trial not null),
+  // less the real collisions and forbidden picks of this electron
+  r.n_null = 2ull * L.block - L.nfirst - (L.k - L.k_start) - L.nforb;
   r.blocks = L.block;
   r.r[0] = L.rx; r.r[1] = L.ry; r.r[2] = L.rz;
   r.t = L.t;
@@ -507,7 +618,7 @@ __device__ __forceinline__ void save_state(const InstanceDesc& d, const Lane<R>&
   s.sum_epsp = L.sep;
   s.id = L.id;
   s.block = L.block; s.k = L.k; s.k_start = L.k_start; s.G = L.G; s.D = L.D;
-  s.n_forb = L.nforb; s.n_over = L.nover; s.n_null = L.nnull;
+  s.n_forb = L.nforb; s.n_over = L.nover; s.n_first = L.nfirst;
   s.started = 1; s.pad = L.flags;
   d.saved[e] = s;
 }
@@ -519,9 +630,9 @@ __device__ __forceinline__ void load_state(const InstanceDesc& d, Lane<R>& L, co
   L.t = s.t;
   L.vx = static_cast<R>(s.v[0]); L.vy = static_cast<R>(s.v[1]); L.vz = static_cast<R>(s.v[2]);
   L.se = s.sum_eps; L.sep = s.sum_epsp;
-  L.id = s.id;
+  set_id(L, C, s.id);
   L.block = s.block; L.k = s.k; L.k_start = s.k_start; L.G = s.G; L.D = s.D;
-  L.nforb = s.n_forb; L.nover = s.n_over; L.nnull = s.n_null; L.flags = s.pad;
+  L.nforb = s.n_forb; L.nover = s.n_over; L.nfirst = s.n_first; L.flags = s.pad;
   L.T = R(0);
   set_anchor<R, HB>(L, C);
 }
@@ -557,34 +668,54 @@ __device__ __forceinline__ void trace_event(const InstanceDesc& d, Lane<R>& L, i
 // eq. null_fraction for the real/null test with x = R nu' < nu(eps)).  A non-null
 // outcome of the first trial leaves the second unused.  The total rate comes from the
 // LDS pair table.
+// Lanes that hold a real-collision candidate (PENDING) run the same Philox instructions
+// with the counter of their scattering block (k, SCAT) instead of a trial block: they
+// would be masked off here anyway, so the scattering words cost the wave nothing and the
+// collision phase needs no generator call of its own.  The streams are unchanged.
 template <typename R, bool HB>
 __device__ __forceinline__ void trial_block(Lane<R>& L, const Consts<R>& C,
                                             const typename Pair<R>::T* __restrict__ s_nu) {
-  if (L.block >= kMaxBlocks) {
+  const bool waiting = L.state == ST_PENDING;
+  if (!waiting && L.block >= kMaxBlocks) {
     L.flags |= 4u;
     L.state = ST_STOPPED;    // stopped at the cap: recorded and flagged
     return;
   }
-  const W4 h = draw(C.key, L.id, TAG_TRIAL_HI, L.block);
+  const uint32_t ctr = waiting ? L.k : L.block;
+  TrialPre ph = L.pre_hi;
+  if (waiting) ph.a ^= (TAG_TRIAL_HI ^ TAG_SCAT_HI);
+  const W4 h = draw_trial(C.key, ph, ctr);
   W4 l = {0, 0, 0, 0};
-  if constexpr (sizeof(R) == 8) l = draw(C.key, L.id, TAG_TRIAL_LO, L.block);
+  if constexpr (sizeof(R) == 8) {
+    TrialPre pl = L.pre_lo;
+    if (waiting) pl.a ^= (TAG_TRIAL_LO ^ TAG_SCAT_LO);
+    l = draw_trial(C.key, pl, ctr);
+  }
+  if (waiting) {
+    L.sh = h;
+    L.sl = l;
+    L.state = ST_READY;
+    return;
+  }
   const uint32_t blk = L.block;
   L.block = blk + 1;
 #pragma unroll
   for (int sub = 0; sub < 2; ++sub) {
     const uint32_t hf = sub ? h.z : h.x, hr = sub ? h.w : h.y;
     const uint32_t lf = sub ? l.z : l.x, lr = sub ? l.w : l.y;
-    const R uf = uni(hf, lf, R(0));
-    const R ur = uni(hr, lr, R(0));
-    const R T = L.T + flight(uf, C.cT);
+    R T, x;
+    if constexpr (sizeof(R) == 4) {
+      // u = (hf >> 8) 2^-24: -ln(1-u)/nu' = (24 - log2(2^24 - (hf >> 8))) ln2/nu'
+      const float l2 = __builtin_amdgcn_logf(static_cast<float>(0x1000000u - (hf >> 8)));
+      T = fmaf(l2 - 24.0f, -C.cT, L.T);
+      x = static_cast<float>(hr >> 8) * C.nup24;    // = u_r nu' exactly
+    } else {
+      T = L.T + flight(uni(hf, lf, R(0)), C.cT);
+      x = uni(hr, lr, R(0)) * C.nup;
+    }
     L.T = T;
-    const R eps = C.c_eps * speed2_at<R, HB>(L, C, T);
-    int g;
-    R w;
-    bool over;
-    grid_pos(eps, C.off, C.p, C.G, &g, &w, &over);
-    const R nu = lerp_pair(s_nu[g], w);
-    const R x = ur * C.nup;
+    const R eps = energy_at<R, HB>(L, C, T);
+    const R nu = lds_rate(s_nu, eps, C);
     if (x < nu) {
       L.state = ST_PENDING;
       L.p_eps = eps;
@@ -593,7 +724,6 @@ __device__ __forceinline__ void trial_block(Lane<R>& L, const Consts<R>& C,
       L.p_block = blk;
       return;
     }
-    L.nnull += 1;
   }
 }
 
@@ -610,6 +740,7 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
   *spawn = false;
   const R eps = L.p_eps;
   const R x = L.p_x;
+  L.nfirst += L.p_sub == 0 ? 1u : 0u;
   int g;
   R w;
   bool over;
@@ -641,9 +772,8 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
     }
   }
   if (over) L.nover += 1;
-  const W4 h = draw(C.key, L.id, TAG_SCAT_HI, L.k);
-  W4 l = {0, 0, 0, 0};
-  if constexpr (sizeof(R) == 8) l = draw(C.key, L.id, TAG_SCAT_LO, L.k);
+  const W4 h = L.sh;        // scattering block k, drawn while the candidate waited
+  const W4 l = L.sl;
   R nx, ny, nz;
   iso_dir<R>(uni(h.x, l.x, R(0)), uni(h.y, l.y, R(0)), &nx, &ny, &nz);
   const R v2 = vx * vx + vy * vy + vz * vz;
@@ -734,7 +864,11 @@ __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restr
     if (inst != cur_inst) {
       const PT* src = reinterpret_cast<const PT*>(sizeof(R) == 8 ? static_cast<const void*>(d.nu64)
                                                                  : static_cast<const void*>(d.nu32));
-      for (int g = threadIdx.x; g < d.G; g += blockDim.x) s_nu[g] = src[g];
+      for (int g = threadIdx.x; g <= d.G; g += blockDim.x) {
+        PT q = src[g > 0 ? g - 1 : 0];
+        if (g == 0) q.y = 0;
+        s_nu[g] = q;
+      }
       cur_inst = inst;
     }
     if (threadIdx.x == 0) s_next = 0;
@@ -766,15 +900,18 @@ __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restr
           L.state = ST_DONE;
         }
       }
-      if (L.state == ST_ACTIVE) trial_block<R, HB>(L, C, s_nu);
-      const uint64_t pend = __ballot(L.state == ST_PENDING);
-      const uint64_t act = __ballot(L.state == ST_ACTIVE);
-      if (pend != 0 && (__popcll(pend) >= pend_trig || act == 0)) {
-        if (L.state == ST_PENDING) {
-          bool spawn;
-          ChildState child;
-          if (real_collision<R, HB, TR, false>(d, L, C, &spawn, &child) == RC_STOP) L.state = ST_STOPPED;
-        }
+      // Trial phase: random-number blocks until enough lanes of the wave wait on a
+      // real-collision candidate (or none can go on), then serve them together.
+      for (;;) {
+        if (L.state == ST_ACTIVE || L.state == ST_PENDING) trial_block<R, HB>(L, C, s_nu);
+        const uint64_t ready = __ballot(L.state == ST_READY);
+        const uint64_t busy = __ballot(L.state == ST_ACTIVE || L.state == ST_PENDING);
+        if (busy == 0 || __popcll(ready) >= pend_trig) break;
+      }
+      if (L.state == ST_READY) {
+        bool spawn;
+        ChildState child;
+        if (real_collision<R, HB, TR, false>(d, L, C, &spawn, &child) == RC_STOP) L.state = ST_STOPPED;
       }
       // An electron that stopped leaves its final record (budget reached or block cap) or
       // its resumable state (end of the launch's quantum).
@@ -811,7 +948,11 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
   {
     const PT* src = reinterpret_cast<const PT*>(sizeof(R) == 8 ? static_cast<const void*>(d.nu64)
                                                                : static_cast<const void*>(d.nu32));
-    for (int g = threadIdx.x; g < d.G; g += blockDim.x) s_nu[g] = src[g];
+    for (int g = threadIdx.x; g <= d.G; g += blockDim.x) {
+      PT q = src[g > 0 ? g - 1 : 0];
+      if (g == 0) q.y = 0;
+      s_nu[g] = q;
+    }
   }
   __syncthreads();
   const Consts<R> C = load_consts<R>(d);
@@ -858,11 +999,11 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
           L.rx = cs.r[0]; L.ry = cs.r[1]; L.rz = cs.r[2];
           L.t = cs.t;
           L.vx = static_cast<R>(cs.v[0]); L.vy = static_cast<R>(cs.v[1]); L.vz = static_cast<R>(cs.v[2]);
-          L.id = cs.id;
+          set_id(L, C, cs.id);
           L.k = L.k_start = cs.k;
           L.k_stop = C.n_coll;
           L.block = 0;
-          L.G = L.D = L.nforb = L.nover = L.nnull = L.flags = 0;
+          L.G = L.D = L.nforb = L.nover = L.nfirst = L.flags = 0;
           L.se = L.sep = 0.0;
           L.T = R(0);
           L.rec = N + slot;
@@ -881,13 +1022,17 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
         if (live == 0) L.state = ST_DONE;
       }
     }
-    if (L.state == ST_ACTIVE) trial_block<R, HB>(L, C, s_nu);
-    const uint64_t pend = __ballot(L.state == ST_PENDING);
-    const uint64_t act = __ballot(L.state == ST_ACTIVE);
-    if (pend != 0 && (__popcll(pend) >= pend_trig || act == 0)) {
+    uint64_t ready;
+    for (;;) {
+      if (L.state == ST_ACTIVE || L.state == ST_PENDING) trial_block<R, HB>(L, C, s_nu);
+      ready = __ballot(L.state == ST_READY);
+      const uint64_t busy = __ballot(L.state == ST_ACTIVE || L.state == ST_PENDING);
+      if (busy == 0 || __popcll(ready) >= pend_trig) break;
+    }
+    if (ready != 0) {
       bool spawn = false;
       ChildState child;
-      if (L.state == ST_PENDING) {
+      if (L.state == ST_READY) {
         if (real_collision<R, HB, TR, true>(d, L, C, &spawn, &child) == RC_STOP) L.state = ST_STOPPED;
       }
       // append the secondaries of this wave: one reservation, ranks from the lane mask
@@ -921,7 +1066,8 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
       atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->live), static_cast<unsigned long long>(-1ll));
       L.state = ST_IDLE;
     }
-    const uint64_t busy = __ballot(L.state == ST_ACTIVE || L.state == ST_PENDING || L.state == ST_IDLE);
+    const uint64_t busy = __ballot(L.state == ST_ACTIVE || L.state == ST_PENDING || L.state == ST_READY ||
+                                   L.state == ST_IDLE);
     if (busy == 0) {
       if (__ballot(L.state != ST_DONE) == 0) break;
       __builtin_amdgcn_s_sleep(32);
