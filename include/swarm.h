@@ -108,7 +108,8 @@ typedef struct {
 typedef struct {
   uint64_t id;             /* primaries: index; secondaries: 2^63 | hash of (parent, k) */
   uint32_t flags;          /* 1 finished (made all its real collisions), 2 attached,
-                              4 stopped at the per-electron trial-block cap (2^31 - 1) */
+                              4 stopped at the per-electron trial-block cap (2^31 - 1),
+                              8 stopped because the run exceeded its capacity */
   uint32_t k_start;        /* real collisions inherited from the lineage at birth */
   uint32_t k_end;          /* real-collision count when the electron stopped */
   uint32_t G, D;           /* ionisations and attachments made by this electron */
@@ -164,8 +165,10 @@ swarm_status swarm_create(const swarm_component* comps, int32_t n_comps,
 /* Simulate n_electrons primaries (ids 0..n-1) at the origin, each until it has made
  * n_collisions real collisions (the paper's I; section "Determination of swarm
  * attributes"), with the given seed.  Synchronous.  In REAL mode secondaries inherit the
- * parent's count.  Returns SWARM_ERR_CAPACITY (results kept, dropped electrons counted)
- * if REAL growth exceeds the capacity.  Previous results of the handle are replaced. */
+ * parent's count.  If REAL growth exceeds the capacity the run stops early and returns
+ * SWARM_ERR_CAPACITY: the secondaries that did not fit are counted (n_dropped), electrons
+ * still running are recorded with flag 8, and the tallies cover the finished ones.
+ * Previous results of the handle are replaced. */
 swarm_status swarm_run(swarm_t h, int64_t n_electrons, int64_t n_collisions, uint64_t seed);
 
 /* Tallies of the last run (computed by deterministic fixed-order device reductions). */

@@ -430,6 +430,7 @@ swarm_status swarm_run(swarm_t h, int64_t n_electrons, int64_t n_collisions, uin
     d.child_ready = static_cast<uint32_t*>(h->ready.p);
     if ((e = launch_fill_u32(d.child_ready, 0u, child_cap, s)) != hipSuccess) return hip_fail(e, "clearing flags");
   }
+  if (real && (e = launch_mark_empty(d.records, capacity, s)) != hipSuccess) return hip_fail(e, "clearing records");
   const bool trace = h->n_trace > 0;
   d.trace_ids = trace ? static_cast<const uint64_t*>(h->trace_ids.p) : nullptr;
   d.n_trace = h->n_trace;
@@ -507,14 +508,22 @@ swarm_status swarm_tallies(swarm_t h, swarm_tallies_t* out) {
 swarm_status swarm_records(swarm_t h, swarm_record* out, int64_t max_records, int64_t* n_out) {
   if (!h || !n_out) return fail(SWARM_ERR_INVALID_ARG, "NULL argument");
   if (!h->have_run) return fail(SWARM_ERR_STATE, "no completed run");
-  *n_out = h->n_records;
-  const int64_t n = std::min(max_records, h->n_records);
-  if (out && n > 0) {
-    hipError_t e = hipMemcpyAsync(out, h->desc.records, static_cast<size_t>(n) * sizeof(swarm_record),
+  // Slots of secondaries that a run stopped early never simulated are empty (id all ones)
+  // and are left out: *n_out counts the electrons that have a record.
+  std::vector<swarm_record> all(static_cast<size_t>(h->n_records));
+  if (h->n_records > 0) {
+    hipError_t e = hipMemcpyAsync(all.data(), h->desc.records, all.size() * sizeof(swarm_record),
                                   hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(e, "copying records");
   }
+  int64_t n = 0;
+  for (const swarm_record& r : all) {
+    if (r.id == ~0ull) continue;
+    if (out && n < max_records) out[n] = r;
+    ++n;
+  }
+  *n_out = n;
   return SWARM_OK;
 }
 

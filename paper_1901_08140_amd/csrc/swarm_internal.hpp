@@ -143,6 +143,7 @@ struct TallyTile {
 // Launchers implemented in swarm_kernels.hip.
 hipError_t launch_build(InstanceDesc* d_desc, const InstanceDesc& h_desc, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_mark_empty(swarm_record* r, int64_t n, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
 hipError_t launch_swarm_dummy(const InstanceDesc* d_desc, const WorkItem* d_items, int32_t n_items,
                               int32_t* d_item_counter, int precision, bool has_b, bool trace,

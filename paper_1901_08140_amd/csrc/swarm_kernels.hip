@@ -337,6 +337,16 @@ __global__ void k_build_constants(InstanceDesc* desc) {
   }
 }
 
+// Mark record slots as empty (id = all ones): real-secondaries runs that stop early leave
+// slots of queued secondaries unwritten, and the reductions skip empty slots.
+__global__ void k_mark_empty(swarm_record* r, int64_t n) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    r[i].id = ~0ull;
+    r[i].flags = 0u;
+  }
+}
+
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x)
@@ -1059,12 +1069,24 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
         }
       }
     }
+    // Once the queue has overflowed the run's result is an error: stop every electron at
+    // its current anchor (flag 8) and take no new work, so the launch ends promptly.
+    const bool abort_run = __hip_atomic_load(&ctr->dropped, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    if (abort_run) {
+      if (L.state == ST_ACTIVE || L.state == ST_PENDING || L.state == ST_READY) {
+        L.flags |= 8u;
+        L.state = ST_STOPPED;
+      } else if (L.state == ST_IDLE || L.state == ST_WAIT) {
+        L.state = ST_DONE;
+        prim_left = false;
+      }
+    }
     if (L.state == ST_STOPPED) {
-      if (L.k >= C.n_coll && !(L.flags & 2u)) L.flags |= 1u;   // attached electrons are not finished
+      if (L.k >= C.n_coll && !(L.flags & 10u)) L.flags |= 1u;   // attached or aborted: not finished
       write_record(d, L);
       atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->n_done), 1ull);
       atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->live), static_cast<unsigned long long>(-1ll));
-      L.state = ST_IDLE;
+      L.state = abort_run ? ST_DONE : ST_IDLE;
     }
     const uint64_t busy = __ballot(L.state == ST_ACTIVE || L.state == ST_PENDING || L.state == ST_READY ||
                                    L.state == ST_IDLE);
@@ -1121,6 +1143,7 @@ __global__ void __launch_bounds__(kTallyThreads) k_tally1(const InstanceDesc* __
   for (int q = 0; q < kTally1; ++q) a[q] = 0.0;
   for (int64_t j = threadIdx.x; j < tt.count; j += kTallyThreads) {
     const swarm_record r = d.records[tt.first + j];
+    if (r.id == ~0ull) continue;   // empty slot
     const double kr = static_cast<double>(r.k_end) - static_cast<double>(r.k_start);
     a[T1_NREC] += 1.0;
     a[T1_KREAL] += kr;
@@ -1197,6 +1220,7 @@ __global__ void __launch_bounds__(kTallyThreads) k_tally2(const InstanceDesc* __
   for (int q = 0; q < kTally2; ++q) a[q] = 0.0;
   for (int64_t j = threadIdx.x; j < tt.count; j += kTallyThreads) {
     const swarm_record r = d.records[tt.first + j];
+    if (r.id == ~0ull) continue;   // empty slot
     const double kr = static_cast<double>(r.k_end) - static_cast<double>(r.k_start);
     if (kr > 0.0) {
       const double pe = r.sum_eps / kr - mpe, pep = r.sum_epsp / kr - mpep;
@@ -1316,6 +1340,13 @@ hipError_t launch_build(InstanceDesc* d_desc, const InstanceDesc& h, hipStream_t
   const int64_t n = static_cast<int64_t>(h.G) * h.nc;
   hipLaunchKernelGGL(k_build_pairs, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, d_desc);
   hipLaunchKernelGGL(k_build_constants, dim3(1), dim3(256), 0, s, d_desc);
+  return hipGetLastError();
+}
+
+hipError_t launch_mark_empty(swarm_record* r, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_mark_empty, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, r, n);
   return hipGetLastError();
 }
 
