@@ -431,6 +431,8 @@ struct Lane {
   int state;
   int trace_slot, n_ev;
   R p_eps, p_x;             // pending real-collision candidate: energy and x = R nu'
+  int p_gi;                 // its padded grid index (node + 1, clamped to [0, G])
+  R p_w;                    // and interpolation weight
   uint32_t p_sub, p_block;
   TrialPre pre_hi, pre_lo;  // first-round Philox terms of the trial streams
   W4 sh, sl;                // scattering block k (SCAT_HI / SCAT_LO words)
@@ -511,18 +513,24 @@ __device__ __forceinline__ R energy_at(const Lane<R>& L, const Consts<R>& C, R T
 // node, whose difference is zero) energies at or above 2^emax, so the clamped index needs
 // no select on the weight.  Index and weight are exact: the node index comes from the
 // exponent and leading mantissa bits, w = frac((2 mant - 1) P).
-__device__ __forceinline__ float lds_rate(const float2* __restrict__ s_nu, float eps, const Consts<float>& C) {
+__device__ __forceinline__ float lds_rate(const float2* __restrict__ s_nu, float eps, const Consts<float>& C,
+                                         int* gi_out, float* w_out) {
   const uint32_t b = __float_as_uint(eps);
   const int gi = min(max(static_cast<int>(b >> (23 - C.p)) - C.off1, 0), C.G);
   const float w = __builtin_amdgcn_fractf(fmaf(__builtin_amdgcn_frexp_mantf(eps), C.twoPf, -C.Pf));
   const float2 q = s_nu[gi];
+  *gi_out = gi;
+  *w_out = w;
   return fmaf(w, q.y, q.x);
 }
-__device__ __forceinline__ double lds_rate(const double2* __restrict__ s_nu, double eps, const Consts<double>& C) {
+__device__ __forceinline__ double lds_rate(const double2* __restrict__ s_nu, double eps, const Consts<double>& C,
+                                          int* gi_out, double* w_out) {
   const uint32_t hi = static_cast<uint32_t>(static_cast<uint64_t>(__double_as_longlong(eps)) >> 32);
   const int gi = min(max(static_cast<int>(hi >> (20 - C.p)) - C.off1, 0), C.G);
   const double w = __builtin_amdgcn_fract(fma(__builtin_amdgcn_frexp_mant(eps), C.twoPf, -C.Pf));
   const double2 q = s_nu[gi];
+  *gi_out = gi;
+  *w_out = w;
   return q.x + w * q.y;
 }
 
@@ -725,9 +733,13 @@ __device__ __forceinline__ void trial_block(Lane<R>& L, const Consts<R>& C,
     }
     L.T = T;
     const R eps = energy_at<R, HB>(L, C, T);
-    const R nu = lds_rate(s_nu, eps, C);
+    int gi;
+    R w;
+    const R nu = lds_rate(s_nu, eps, C, &gi, &w);
     if (x < nu) {
       L.state = ST_PENDING;
+      L.p_gi = gi;
+      L.p_w = w;
       L.p_eps = eps;
       L.p_x = x;
       L.p_sub = sub;
@@ -751,10 +763,11 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
   const R eps = L.p_eps;
   const R x = L.p_x;
   L.nfirst += L.p_sub == 0 ? 1u : 0u;
-  int g;
-  R w;
-  bool over;
-  grid_pos(eps, C.off, C.p, C.G, &g, &w, &over);
+  // node and weight of the candidate (entry 0 of the padded index is below the grid, entry
+  // G at or above its top; both use a constant value there)
+  const bool over = L.p_gi >= C.G;
+  const int g = min(max(L.p_gi - 1, 0), C.G - 1);
+  const R w = (L.p_gi >= 1 && !over) ? L.p_w : R(0);
   const typename Pair<R>::T* row = C.cum + static_cast<int64_t>(g) * C.nc;
   int lo = 0, hi = C.nc - 1;
   while (lo < hi) {
@@ -799,7 +812,9 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
   } else if (ch.kind == SWARM_ATTACHMENT) {
     epsp = R(0);                                                       // plastic collision
   } else {
-    const R ratio = thr / eps;
+    R ratio;
+    if constexpr (sizeof(R) == 4) ratio = thr * __builtin_amdgcn_rcpf(eps);
+    else ratio = thr / eps;
     const R root = sqrt_(fmax(R(0), R(1) - c_mM * ratio));
     epsp = eps * (R(1) - c_M * ratio + c_ela * (root * cos_t - R(1)));  // eq. delta_energy_ine
   }
