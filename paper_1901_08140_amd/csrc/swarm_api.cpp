@@ -56,9 +56,13 @@ DeviceInfo& device_info() {
 }
 
 // Dynamic LDS of the swarm kernels: the total-rate pairs of the G grid nodes plus one
-// padding entry in front.
-size_t lds_bytes_for(int precision, int G) {
-  return static_cast<size_t>(G + 1) * (precision == SWARM_FP32_MIXED ? sizeof(float2) : sizeof(double2));
+// padding entry in front, then (16-byte aligned) the nc channel descriptors.
+int lds_channel_offset(int precision, int G) {
+  const size_t b = static_cast<size_t>(G + 1) * (precision == SWARM_FP32_MIXED ? sizeof(float2) : sizeof(double2));
+  return static_cast<int>((b + 15) & ~static_cast<size_t>(15));
+}
+size_t lds_bytes_for(int precision, int G, int nc) {
+  return static_cast<size_t>(lds_channel_offset(precision, G)) + static_cast<size_t>(nc) * sizeof(ChannelDev);
 }
 
 DevBuf::~DevBuf() { reset(); }
@@ -445,7 +449,8 @@ swarm_status swarm_run(swarm_t h, int64_t n_electrons, int64_t n_collisions, uin
   if ((e = hipMemcpyAsync(d.ctr, &rc, sizeof(rc), hipMemcpyHostToDevice, s)) != hipSuccess) return hip_fail(e, "counters");
   if ((e = sync_desc_to_device(h)) != hipSuccess) return hip_fail(e, "descriptor");
   const swarm_launch_opts& o = h->opts;
-  const size_t lds = lds_bytes_for(d.precision, d.G);
+  const size_t lds = lds_bytes_for(d.precision, d.G, d.nc);
+  const int ch_off = lds_channel_offset(d.precision, d.G);
   DeviceInfo& dev = device_info();
   const int per_cu = swarm_kernel_max_blocks_per_cu(d.precision, h->has_b, trace, real, o.block_size, lds);
   if ((e = hipEventRecord(h->ev[0], s)) != hipSuccess) return hip_fail(e, "event");
@@ -465,12 +470,12 @@ swarm_status swarm_run(swarm_t h, int64_t n_electrons, int64_t n_collisions, uin
     if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(d_ctr), 0u, 1, s)) != hipSuccess) return hip_fail(e, "item counter");
     const int grid = std::max(1, std::min<int>(static_cast<int>(items.size()), dev.n_cu * per_cu));
     if ((e = launch_swarm_dummy(h->d_desc, static_cast<const WorkItem*>(h->items.p), static_cast<int32_t>(items.size()),
-                                d_ctr, d.precision, h->has_b, trace, o.block_size, grid, o.pending_trigger, lds, s)) != hipSuccess)
+                                d_ctr, d.precision, h->has_b, trace, o.block_size, grid, o.pending_trigger, lds, ch_off, s)) != hipSuccess)
       return hip_fail(e, "swarm kernel launch");
   } else {
     const int64_t want = (n_electrons + o.block_size - 1) / o.block_size;
     const int grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want * 4, static_cast<int64_t>(dev.n_cu) * per_cu)));
-    if ((e = launch_swarm_real(h->d_desc, d.precision, h->has_b, trace, o.block_size, grid, o.pending_trigger, lds, s)) != hipSuccess)
+    if ((e = launch_swarm_real(h->d_desc, d.precision, h->has_b, trace, o.block_size, grid, o.pending_trigger, lds, ch_off, s)) != hipSuccess)
       return hip_fail(e, "swarm kernel launch");
   }
   if ((e = hipEventRecord(h->ev[1], s)) != hipSuccess) return hip_fail(e, "event");

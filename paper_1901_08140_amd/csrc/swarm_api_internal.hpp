@@ -42,7 +42,8 @@ struct TallyPlan {
 
 swarm_status fail(swarm_status st, const char* fmt, ...);
 swarm_status hip_fail(hipError_t e, const char* what);
-size_t lds_bytes_for(int precision, int G);
+int lds_channel_offset(int precision, int G);
+size_t lds_bytes_for(int precision, int G, int nc);
 void make_items(const std::vector<int64_t>& n_e, const std::vector<int64_t>& n_c, int64_t chunk,
                 std::vector<WorkItem>& items);
 swarm_launch_opts resolve_opts(const swarm_launch_opts* o, int precision);

@@ -25,6 +25,7 @@ struct swarm_batch {
   swarm_launch_opts opts{};
   int grid = 1;
   size_t lds = 0;
+  int ch_off = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -55,7 +56,7 @@ hipError_t enqueue(swarm_batch* b) {
   if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(item_counter(b)), 0u, 1, b->stream)) != hipSuccess) return e;
   if ((e = launch_swarm_dummy(static_cast<const InstanceDesc*>(b->descs.p), static_cast<const WorkItem*>(b->items.p),
                               static_cast<int32_t>(b->h_items.size()), item_counter(b), b->precision, b->magnetic,
-                              false, b->opts.block_size, b->grid, b->opts.pending_trigger, b->lds, b->stream)) != hipSuccess)
+                              false, b->opts.block_size, b->grid, b->opts.pending_trigger, b->lds, b->ch_off, b->stream)) != hipSuccess)
     return e;
   return b->tally.launch(static_cast<const InstanceDesc*>(b->descs.p), b->stream);
 }
@@ -71,7 +72,7 @@ swarm_status swarm_batch_create(swarm_t* handles, const swarm_job* jobs, int32_t
   if (!handles || !jobs || n <= 0) return fail(SWARM_ERR_INVALID_ARG, "empty batch");
   auto b = std::make_unique<swarm_batch>();
   b->precision = handles[0] ? handles[0]->desc.precision : 0;
-  int G = 0;
+  int G = 0, n_ch = 0;
   for (int i = 0; i < n; ++i) {
     swarm* h = handles[i];
     if (!h) return fail(SWARM_ERR_INVALID_ARG, "handle %d is NULL", i);
@@ -85,6 +86,7 @@ swarm_status swarm_batch_create(swarm_t* handles, const swarm_job* jobs, int32_t
       if (handles[j] == h) return fail(SWARM_ERR_INVALID_ARG, "handle %d appears twice", i);
     b->magnetic |= h->has_b;
     G = std::max(G, h->desc.G);
+    n_ch = std::max(n_ch, h->desc.nc);
     b->hs.push_back(h);
     b->jobs.push_back(jobs[i]);
   }
@@ -126,7 +128,8 @@ swarm_status swarm_batch_create(swarm_t* handles, const swarm_job* jobs, int32_t
                           b->stream)) != hipSuccess)
     return hip_fail(e, "uploading batch");
   if ((e = b->tally.prepare(ne, b->stream)) != hipSuccess) return hip_fail(e, "tally plan");
-  b->lds = lds_bytes_for(b->precision, G);
+  b->lds = lds_bytes_for(b->precision, G, n_ch);
+  b->ch_off = lds_channel_offset(b->precision, G);
   const int per_cu = swarm_kernel_max_blocks_per_cu(b->precision, b->magnetic, false, false, b->opts.block_size, b->lds);
   b->grid = std::max(1, std::min<int>(static_cast<int>(b->h_items.size()), device_info().n_cu * per_cu));
   if ((e = hipStreamSynchronize(b->stream)) != hipSuccess) return hip_fail(e, "uploading batch");

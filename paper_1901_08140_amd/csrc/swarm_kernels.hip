@@ -36,7 +36,10 @@ constexpr double kLn2 = 0.69314718055994530942;
 // ---------------------------------------------------------------------------------------
 struct W4 { uint32_t x, y, z, w; };
 
-__device__ __forceinline__ uint32_t xor3_k(uint32_t a, uint32_t b, uint32_t k) { return a ^ b ^ k; }
+// a ^ b ^ k in one gfx950 three-input bitwise operation (truth table 0x96 = odd parity)
+__device__ __forceinline__ uint32_t xor3_k(uint32_t a, uint32_t b, uint32_t k) {
+  return __builtin_amdgcn_bitop3_b32(a, b, k, 0x96);
+}
 
 // Rounds 2..10 of Philox4x32-10 (the first round is done by the caller); k0, k1 are the
 // keys of round 2.
@@ -373,7 +376,8 @@ struct Consts {
   R sceps;       // FP32: sqrt(m/2e)
   bool magnetic; // B > 0 (kernels built for B may also serve B = 0 instances)
   int G, nc, off, p;
-  int off1;      // off - 1: index of the padded LDS table
+  int off1;      // off - 1: raw index of entry 0 of the padded LDS table
+  int off1G;     // off1 + G: raw index of its last entry
   uint32_t n_coll, quantum;
   Key key;
   const typename Pair<R>::T* cum;
@@ -409,6 +413,7 @@ __device__ __forceinline__ Consts<R> load_consts(const InstanceDesc& d) {
   c.key = {static_cast<uint32_t>(d.seed), static_cast<uint32_t>(d.seed >> 32)};
   c.chan = d.chan;
   c.off1 = c.off - 1;
+  c.off1G = c.off1 + c.G;
   return c;
 }
 
@@ -431,9 +436,9 @@ struct Lane {
   int state;
   int trace_slot, n_ev;
   R p_eps, p_x;             // pending real-collision candidate: energy and x = R nu'
-  int p_gi;                 // its padded grid index (node + 1, clamped to [0, G])
+  int p_gi;                 // its raw table index (padded index + off1, see lds_rate)
   R p_w;                    // and interpolation weight
-  uint32_t p_sub, p_block;
+  uint32_t p_sub;            // 0/1: first or second trial of block `block - 1`
   TrialPre pre_hi, pre_lo;  // first-round Philox terms of the trial streams
   W4 sh, sl;                // scattering block k (SCAT_HI / SCAT_LO words)
 };
@@ -512,24 +517,25 @@ __device__ __forceinline__ R energy_at(const Lane<R>& L, const Consts<R>& C, R T
 // entry g+1 holds node g, entry 0 serves energies below the grid and entry G (the top
 // node, whose difference is zero) energies at or above 2^emax, so the clamped index needs
 // no select on the weight.  Index and weight are exact: the node index comes from the
-// exponent and leading mantissa bits, w = frac((2 mant - 1) P).
+// exponent and leading mantissa bits, and w = frac(2 P mant) = frac((2 mant - 1) P) (the
+// product by the power of two 2P is exact).  The raw index (exponent and leading mantissa
+// bits, clamped to [off1, off1 + G]) is returned; the padded index is raw - off1.
 __device__ __forceinline__ float lds_rate(const float2* __restrict__ s_nu, float eps, const Consts<float>& C,
-                                         int* gi_out, float* w_out) {
-  const uint32_t b = __float_as_uint(eps);
-  const int gi = min(max(static_cast<int>(b >> (23 - C.p)) - C.off1, 0), C.G);
-  const float w = __builtin_amdgcn_fractf(fmaf(__builtin_amdgcn_frexp_mantf(eps), C.twoPf, -C.Pf));
-  const float2 q = s_nu[gi];
-  *gi_out = gi;
+                                         int* raw_out, float* w_out) {
+  const int raw = min(max(static_cast<int>(__float_as_uint(eps) >> (23 - C.p)), C.off1), C.off1G);
+  const float w = __builtin_amdgcn_fractf(__builtin_amdgcn_frexp_mantf(eps) * C.twoPf);
+  const float2 q = s_nu[raw - C.off1];
+  *raw_out = raw;
   *w_out = w;
   return fmaf(w, q.y, q.x);
 }
 __device__ __forceinline__ double lds_rate(const double2* __restrict__ s_nu, double eps, const Consts<double>& C,
-                                          int* gi_out, double* w_out) {
+                                          int* raw_out, double* w_out) {
   const uint32_t hi = static_cast<uint32_t>(static_cast<uint64_t>(__double_as_longlong(eps)) >> 32);
-  const int gi = min(max(static_cast<int>(hi >> (20 - C.p)) - C.off1, 0), C.G);
-  const double w = __builtin_amdgcn_fract(fma(__builtin_amdgcn_frexp_mant(eps), C.twoPf, -C.Pf));
-  const double2 q = s_nu[gi];
-  *gi_out = gi;
+  const int raw = min(max(static_cast<int>(hi >> (20 - C.p)), C.off1), C.off1G);
+  const double w = __builtin_amdgcn_fract(__builtin_amdgcn_frexp_mant(eps) * C.twoPf);
+  const double2 q = s_nu[raw - C.off1];
+  *raw_out = raw;
   *w_out = w;
   return q.x + w * q.y;
 }
@@ -672,7 +678,7 @@ __device__ __forceinline__ void trace_event(const InstanceDesc& d, Lane<R>& L, i
   if constexpr (TR) {
     if (L.trace_slot >= 0 && L.n_ev < d.max_events) {
       swarm_event ev;
-      ev.id = L.id; ev.type = type; ev.channel = ch; ev.k = L.k; ev.block = L.p_block;
+      ev.id = L.id; ev.type = type; ev.channel = ch; ev.k = L.k; ev.block = L.block - 1u;
       ev.sub = L.p_sub; ev.pad = 0; ev.eps = static_cast<double>(eps);
       ev.epsp = static_cast<double>(epsp); ev.t = t; ev.r[0] = rx; ev.r[1] = ry; ev.r[2] = rz;
       d.trace_out[static_cast<int64_t>(L.trace_slot) * d.max_events + L.n_ev] = ev;
@@ -680,6 +686,27 @@ __device__ __forceinline__ void trace_event(const InstanceDesc& d, Lane<R>& L, i
       d.trace_count[L.trace_slot] = L.n_ev;
     }
   }
+}
+
+// One trial from the words (hf, lf) of the flight time and (hr, lr) of the real/null test:
+// the flight time grows by -ln(1-u)/nu' (eq. random_time), the energy at the new time is
+// looked up in the LDS rate table, and the trial is real when x = u_r nu' < nu(eps)
+// (eq. null_fraction).  Leaves eps, x and the table position in the candidate fields.
+template <typename R, bool HB>
+__device__ __forceinline__ bool one_trial(Lane<R>& L, const Consts<R>& C,
+                                          const typename Pair<R>::T* __restrict__ s_nu,
+                                          uint32_t hf, uint32_t hr, uint32_t lf, uint32_t lr) {
+  if constexpr (sizeof(R) == 4) {
+    // u = (hf >> 8) 2^-24: -ln(1-u)/nu' = (24 - log2(2^24 - (hf >> 8))) ln2/nu'
+    const float l2 = __builtin_amdgcn_logf(static_cast<float>(0x1000000u - (hf >> 8)));
+    L.T = fmaf(l2 - 24.0f, -C.cT, L.T);
+    L.p_x = static_cast<float>(hr >> 8) * C.nup24;    // = u_r nu' exactly
+  } else {
+    L.T = L.T + flight(uni(hf, lf, R(0)), C.cT);
+    L.p_x = uni(hr, lr, R(0)) * C.nup;
+  }
+  L.p_eps = energy_at<R, HB>(L, C, L.T);
+  return L.p_x < lds_rate(s_nu, L.p_eps, C, &L.p_gi, &L.p_w);
 }
 
 // One random-number block = two candidate trials (eq. random_time for the flight time,
@@ -715,41 +742,21 @@ __device__ __forceinline__ void trial_block(Lane<R>& L, const Consts<R>& C,
     L.state = ST_READY;
     return;
   }
-  const uint32_t blk = L.block;
-  L.block = blk + 1;
-#pragma unroll
-  for (int sub = 0; sub < 2; ++sub) {
-    const uint32_t hf = sub ? h.z : h.x, hr = sub ? h.w : h.y;
-    const uint32_t lf = sub ? l.z : l.x, lr = sub ? l.w : l.y;
-    R T, x;
-    if constexpr (sizeof(R) == 4) {
-      // u = (hf >> 8) 2^-24: -ln(1-u)/nu' = (24 - log2(2^24 - (hf >> 8))) ln2/nu'
-      const float l2 = __builtin_amdgcn_logf(static_cast<float>(0x1000000u - (hf >> 8)));
-      T = fmaf(l2 - 24.0f, -C.cT, L.T);
-      x = static_cast<float>(hr >> 8) * C.nup24;    // = u_r nu' exactly
-    } else {
-      T = L.T + flight(uni(hf, lf, R(0)), C.cT);
-      x = uni(hr, lr, R(0)) * C.nup;
-    }
-    L.T = T;
-    const R eps = energy_at<R, HB>(L, C, T);
-    int gi;
-    R w;
-    const R nu = lds_rate(s_nu, eps, C, &gi, &w);
-    if (x < nu) {
-      L.state = ST_PENDING;
-      L.p_gi = gi;
-      L.p_w = w;
-      L.p_eps = eps;
-      L.p_x = x;
-      L.p_sub = sub;
-      L.p_block = blk;
-      return;
-    }
+  L.block += 1;
+  // The trial writes the candidate fields of the lane directly: a lane that finds a real
+  // candidate becomes PENDING and stops writing them until it is served, so they need no
+  // copy, and the second trial runs only on the lanes whose first one was null.
+  bool hit = one_trial<R, HB>(L, C, s_nu, h.x, h.y, l.x, l.y);
+  L.p_sub = 0;
+  if (!hit) {
+    hit = one_trial<R, HB>(L, C, s_nu, h.z, h.w, l.z, l.w);
+    L.p_sub = 1;
   }
+  if (hit) L.state = ST_PENDING;
 }
 
 // Outcome of serving a pending candidate.
+constexpr int kScanChannels = 8;   // up to this many channels, selection scans the whole row
 enum : int { RC_CONTINUE = 0, RC_STOP = 1 };
 
 // A pending candidate: channel selection (min c with x < C_c(eps)), the kinematic onset
@@ -765,16 +772,33 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
   L.nfirst += L.p_sub == 0 ? 1u : 0u;
   // node and weight of the candidate (entry 0 of the padded index is below the grid, entry
   // G at or above its top; both use a constant value there)
-  const bool over = L.p_gi >= C.G;
-  const int g = min(max(L.p_gi - 1, 0), C.G - 1);
-  const R w = (L.p_gi >= 1 && !over) ? L.p_w : R(0);
+  const int gi = L.p_gi - C.off1;
+  const bool over = gi >= C.G;
+  const int g = min(max(gi - 1, 0), C.G - 1);
+  const R w = (gi >= 1 && !over) ? L.p_w : R(0);
   const typename Pair<R>::T* row = C.cum + static_cast<int64_t>(g) * C.nc;
-  int lo = 0, hi = C.nc - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (x < lerp_pair(row[mid], w)) hi = mid; else lo = mid + 1;
+  int lo;
+  if (C.nc <= kScanChannels) {
+    // few channels: fetch the whole row at once (one memory round trip) and take the
+    // first c with x < C_c(eps) by a backward scan; the last channel needs no test
+    typename Pair<R>::T q[kScanChannels - 1];
+#pragma unroll
+    for (int c = 0; c < kScanChannels - 1; ++c)
+      if (c < C.nc - 1) q[c] = row[c];
+    lo = C.nc - 1;
+#pragma unroll
+    for (int c = kScanChannels - 2; c >= 0; --c)
+      if (c < C.nc - 1 && x < lerp_pair(q[c], w)) lo = c;
+  } else {
+    // many channels: bisection on the running sums, which do not decrease with c
+    lo = 0;
+    int hi = C.nc - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (x < lerp_pair(row[mid], w)) hi = mid; else lo = mid + 1;
+    }
   }
-  const ChannelDev ch = C.chan[lo];
+  const ChannelDev ch = C.chan[lo];     // channel descriptors are staged in LDS
   R vx, vy, vz;
   double rx, ry, rz;
   move_full<R, HB>(L, C, L.T, &vx, &vy, &vz, &rx, &ry, &rz);
@@ -871,10 +895,12 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
 template <typename R, bool HB, bool TR>
 __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restrict__ descs,
                                                      const WorkItem* __restrict__ items, int n_items,
-                                                     int* __restrict__ item_ctr, int pend_trig) {
+                                                     int* __restrict__ item_ctr, int pend_trig,
+                                                     int ch_off) {
   using PT = typename Pair<R>::T;
   extern __shared__ __align__(16) unsigned char smem[];
   PT* s_nu = reinterpret_cast<PT*>(smem);
+  ChannelDev* s_ch = reinterpret_cast<ChannelDev*>(smem + ch_off);
   __shared__ int s_item;
   __shared__ int s_next;
   int cur_inst = -1;
@@ -894,11 +920,13 @@ __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restr
         if (g == 0) q.y = 0;
         s_nu[g] = q;
       }
+      for (int c = threadIdx.x; c < d.nc; c += blockDim.x) s_ch[c] = d.chan[c];
       cur_inst = inst;
     }
     if (threadIdx.x == 0) s_next = 0;
     __syncthreads();
-    const Consts<R> C = load_consts<R>(d);
+    Consts<R> C = load_consts<R>(d);
+    C.chan = s_ch;
     const int64_t count = wi.count;
     Lane<R> L;
     L.state = ST_IDLE;
@@ -965,10 +993,12 @@ __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restr
 // reaches 0); idle waves sleep between polls and give up after a bounded number of polls.
 // ---------------------------------------------------------------------------------------
 template <typename R, bool HB, bool TR>
-__global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restrict__ desc, int pend_trig) {
+__global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restrict__ desc, int pend_trig,
+                                                    int ch_off) {
   using PT = typename Pair<R>::T;
   extern __shared__ __align__(16) unsigned char smem[];
   PT* s_nu = reinterpret_cast<PT*>(smem);
+  ChannelDev* s_ch = reinterpret_cast<ChannelDev*>(smem + ch_off);
   const InstanceDesc& d = *desc;
   {
     const PT* src = reinterpret_cast<const PT*>(sizeof(R) == 8 ? static_cast<const void*>(d.nu64)
@@ -978,9 +1008,11 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
       if (g == 0) q.y = 0;
       s_nu[g] = q;
     }
+    for (int c = threadIdx.x; c < d.nc; c += blockDim.x) s_ch[c] = d.chan[c];
   }
   __syncthreads();
-  const Consts<R> C = load_consts<R>(d);
+  Consts<R> C = load_consts<R>(d);
+  C.chan = s_ch;
   RunCounters* ctr = d.ctr;
   const int64_t N = d.n_electrons;
   const int64_t child_cap = d.capacity - N;
@@ -1382,18 +1414,18 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s) {
 hipError_t launch_swarm_dummy(const InstanceDesc* d_desc, const WorkItem* d_items, int32_t n_items,
                               int32_t* d_item_counter, int precision, bool has_b, bool trace,
                               int block_size, int grid, int pending_trigger, size_t lds_bytes,
-                              hipStream_t s) {
+                              int ch_off, hipStream_t s) {
   void* fn = pick_kernel(precision, has_b, trace, false);
   void* args[] = {const_cast<InstanceDesc**>(&d_desc), const_cast<WorkItem**>(&d_items), &n_items,
-                  &d_item_counter, &pending_trigger};
+                  &d_item_counter, &pending_trigger, &ch_off};
   return hipLaunchKernel(fn, dim3(grid), dim3(block_size), args, lds_bytes, s);
 }
 
 hipError_t launch_swarm_real(const InstanceDesc* d_desc, int precision, bool has_b, bool trace,
                              int block_size, int grid, int pending_trigger, size_t lds_bytes,
-                             hipStream_t s) {
+                             int ch_off, hipStream_t s) {
   void* fn = pick_kernel(precision, has_b, trace, true);
-  void* args[] = {const_cast<InstanceDesc**>(&d_desc), &pending_trigger};
+  void* args[] = {const_cast<InstanceDesc**>(&d_desc), &pending_trigger, &ch_off};
   return hipLaunchKernel(fn, dim3(grid), dim3(block_size), args, lds_bytes, s);
 }
 

@@ -222,7 +222,7 @@ void scheduler(swarm_server* s) {
     }
     descs.clear();
     std::vector<int64_t> ne, nc;
-    int G = 0;
+    int G = 0, n_ch = 0;
     bool magnetic = false;
     for (auto& r : act) {
       InstanceDesc d = r->h->desc;
@@ -231,6 +231,7 @@ void scheduler(swarm_server* s) {
       ne.push_back(r->n_e);
       nc.push_back(r->n_c);
       G = std::max(G, d.G);
+      n_ch = std::max(n_ch, d.nc);
       magnetic |= r->h->has_b;
       r->epochs += 1;
     }
@@ -240,7 +241,8 @@ void scheduler(swarm_server* s) {
     bool ok = (e = s->descs.ensure(descs.size() * sizeof(InstanceDesc))) == hipSuccess &&
               (e = s->items.ensure(items.size() * sizeof(WorkItem) + 256)) == hipSuccess;
     int32_t* item_ctr = ok ? reinterpret_cast<int32_t*>(static_cast<char*>(s->items.p) + items.size() * sizeof(WorkItem)) : nullptr;
-    const size_t lds = lds_bytes_for(s->p.precision, G);
+    const size_t lds = lds_bytes_for(s->p.precision, G, n_ch);
+    const int ch_off = lds_channel_offset(s->p.precision, G);
     if (ok) ok = (e = hipMemcpyAsync(s->descs.p, descs.data(), descs.size() * sizeof(InstanceDesc), hipMemcpyHostToDevice, s->compute)) == hipSuccess &&
                  (e = hipMemcpyAsync(s->items.p, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, s->compute)) == hipSuccess &&
                  (e = launch_fill_u32(reinterpret_cast<uint32_t*>(item_ctr), 0u, 1, s->compute)) == hipSuccess &&
@@ -250,7 +252,7 @@ void scheduler(swarm_server* s) {
       const int grid = std::max(1, std::min<int>(static_cast<int>(items.size()), device_info().n_cu * per_cu));
       ok = (e = launch_swarm_dummy(static_cast<const InstanceDesc*>(s->descs.p), static_cast<const WorkItem*>(s->items.p),
                                    static_cast<int32_t>(items.size()), item_ctr, s->p.precision, magnetic, false,
-                                   o.block_size, grid, o.pending_trigger, lds, s->compute)) == hipSuccess &&
+                                   o.block_size, grid, o.pending_trigger, lds, ch_off, s->compute)) == hipSuccess &&
            (e = hipEventRecord(ev1, s->compute)) == hipSuccess;
     }
     // while the epoch runs, prepare the requests that arrived meanwhile
