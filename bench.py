@@ -26,15 +26,16 @@ sys.path.insert(0, ROOT)
 
 # Algorithmic VALU work per unit, in lane-instruction slots of the FP32-mixed path with
 # B = 0 (full-rate VALU instruction = 1 slot; transcendentals log/sqrt/rsqrt/sin/cos = 2, as
-# measured on gfx950; 32x32->64 integer multiply-add = 1, also measured full rate).
-# Trial (52): half a Philox4x32-10 call (20 multiply-adds + 40 xors per call), the flight
-# time from the 24-bit uniform (6 + log), x = R nu' (3), |v(T)|^2 m/2e (2 FMA), octave-grid
-# position from the bits (8), interpolated rate and compare (2).  Real collision (133): one
-# Philox call for the scattering block (60), channel search over the running sums (12),
-# onset compare in FP64 (8), isotropic direction (16), cos(theta) (6), energy transfer (3),
-# FP64 energy sums, position and time (16), new velocity (6), next-flight constants (4).
-OPS_PER_TRIAL = 52
-OPS_PER_REAL = 133
+# measured on gfx950; 32x32->64 integer multiply-add = 1, also measured full rate; a
+# three-input xor = 1, gfx950 has it as one instruction).
+# Trial (42): half a Philox4x32-10 call (20 multiply-adds + 20 three-input xors per call),
+# the flight time from the 24-bit uniform (5 + log), x = R nu' (3), |v(T)|^2 m/2e (2 FMA),
+# octave-grid position from the bits (8), interpolated rate and compare (2).  Real collision
+# (113): one Philox call for the scattering block (40), channel search over the running sums
+# (12), onset compare in FP64 (8), isotropic direction (16), cos(theta) (6), energy transfer
+# (3), FP64 energy sums, position and time (16), new velocity (6), next-flight constants (4).
+OPS_PER_TRIAL = 42
+OPS_PER_REAL = 113
 PEAK_LANE_OPS = 256 * 64 * 2.4e9      # 256 CUs x 64 FP32 lanes/clock x 2.4 GHz = 3.93e13 /s
 
 
