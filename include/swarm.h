@@ -61,6 +61,21 @@ typedef enum { SWARM_FP64 = 0, SWARM_FP32_MIXED = 1 } swarm_precision;
  * REAL appends the ejected electron as a new swarm member and removes attached ones. */
 typedef enum { SWARM_DUMMY = 0, SWARM_REAL = 1 } swarm_secondaries;
 
+/* Trial frequency nu' of the null-collision loop (section "Trial frequency strategies").
+ * CONSTANT: one nu' for the whole run, the table maximum (LazyTrialFrequency) or the
+ * user's fixed value (FixedTrialFrequency); the method is exact.  VARIABLE: the paper's
+ * VariableTrialFrequency, per electron nu' = (1 + zeta) nu(eps) at its current energy,
+ * capped at the constant value; renewed after every `trial_grace` trials (from the energy
+ * after the trial that used up the count: the trial's energy after a null or forbidden
+ * pick, the energy after the collision after a real one) and after every fail.  A fail is
+ * a trial at which nu(eps) > nu': the electron returns to the state right after its last
+ * real collision, takes nu' = (1 + zeta) nu(eps) from the rate that failed, restarts the
+ * grace count, and the fail ends its random-number block like a real collision.  The first
+ * nu' of an electron comes from the energy it was created with.  This strategy trades
+ * exactness for fewer null trials: returning to the last real collision after a fail
+ * favours flights that did not gain energy. */
+typedef enum { SWARM_TRIAL_CONSTANT = 0, SWARM_TRIAL_VARIABLE = 1 } swarm_trial_strategy;
+
 /* One cross-section table: n_points >= 2 strictly increasing energies (> 0, eV) and
  * cross-sections (>= 0, finite, m^2).  Extended outside the points as in section
  * "Extension of the cross-section tables" (elastic: constant to the left; inelastic:
@@ -101,6 +116,9 @@ typedef struct {
   int64_t capacity;        /* REAL mode: maximum number of electrons (primaries plus
                               secondaries) of one run; 0 = 64 x n_electrons */
   void* stream;            /* hipStream_t or NULL */
+  int32_t trial_strategy;  /* swarm_trial_strategy */
+  double trial_zeta;       /* VARIABLE: the overhead zeta > 0; 0 = default 0.25 */
+  int64_t trial_grace;     /* VARIABLE: trials between renewals, 1 .. 2^31 - 1; 0 = 5000 */
 } swarm_params;
 
 /* Per-electron result record (one per electron that existed in the run), as stored on
@@ -115,7 +133,7 @@ typedef struct {
   uint32_t G, D;           /* ionisations and attachments made by this electron */
   uint32_t n_forbidden;    /* channel picks below the inelastic onset (treated as null) */
   uint32_t n_over;         /* real collisions above the top of the rate grid */
-  uint32_t pad;
+  uint32_t n_fail;         /* fails of the variable trial frequency (0 otherwise) */
   uint64_t n_null;         /* null trials */
   uint64_t blocks;         /* random-number blocks used (two candidate trials each) */
   double r[3], t;
@@ -125,7 +143,7 @@ typedef struct {
 /* One traced event (real collision or forbidden channel pick) of a traced electron. */
 typedef struct {
   uint64_t id;
-  int32_t type;            /* 1 real, 2 forbidden */
+  int32_t type;            /* 1 real, 2 forbidden, 3 fail (channel -1) */
   int32_t channel;
   uint32_t k, block, sub, pad;   /* real index before the event, trial block, 0/1 in block */
   double eps, epsp, t, r[3];     /* energy before/after (eV), time and position after */
@@ -139,7 +157,7 @@ typedef struct { double value, stat_sigma, spread; } swarm_stat;
  *   (d.z)^2/(2t), D_T = (1/N) sum |d_perp|^2/(4t);  sigma = (1/N) sum 2|d| (and the L, T
  *   parts);  alpha = (1/N) sum G_n/z_n, eta = (1/N) sum D_n/z_n (z along -z).
  * Over all electrons: mean energies before/after real collisions; counts; efficiency =
- * real/(real + null + forbidden).  spread = sample standard deviation of the per-electron
+ * real/(real + null + forbidden + fail).  spread = sample standard deviation of the per-electron
  * quantity (the paper's printed +-), stat_sigma = spread/sqrt(N). */
 typedef struct {
   swarm_stat W, Wx, Wy, Wz, mean_energy, mean_energy_after;

@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 RECORD_DTYPE = np.dtype({
-    "names": ["id", "flags", "k_start", "k_end", "G", "D", "n_forbidden", "n_over", "pad",
+    "names": ["id", "flags", "k_start", "k_end", "G", "D", "n_forbidden", "n_over", "n_fail",
               "n_null", "blocks", "r", "t", "sum_eps", "sum_epsp"],
     "formats": ["<u8", "<u4", "<u4", "<u4", "<u4", "<u4", "<u4", "<u4", "<u4",
                 "<u8", "<u8", ("<f8", (3,)), "<f8", "<f8", "<f8"],
@@ -32,7 +32,8 @@ EVENT_DTYPE = np.dtype({
     "itemsize": 80,
 })
 FLAG_FINISHED, FLAG_ATTACHED, FLAG_STUCK = 1, 2, 4
-EV_REAL, EV_FORBIDDEN = 1, 2
+EV_REAL, EV_FORBIDDEN, EV_FAIL = 1, 2, 3
+CONSTANT_TRIAL, VARIABLE_TRIAL = 0, 1
 TRIAL_HI, TRIAL_LO, SCAT_HI, SCAT_LO, INIT_HI, INIT_LO, CHILD_ID = range(7)
 
 
@@ -53,7 +54,8 @@ class _Params(ctypes.Structure):
                 ("T_K", ctypes.c_double), ("init_energy_eV", ctypes.c_double),
                 ("secondaries", ctypes.c_int32), ("grid_P", ctypes.c_int32),
                 ("grid_emin", ctypes.c_int32), ("grid_emax", ctypes.c_int32),
-                ("user_majorant", ctypes.c_double)]
+                ("user_majorant", ctypes.c_double), ("trial_strategy", ctypes.c_int32),
+                ("trial_zeta", ctypes.c_double), ("trial_grace", ctypes.c_int64)]
 
 
 _lib = None
@@ -150,7 +152,8 @@ class OracleModel:
 
     def __init__(self, components, E_V_per_m, B_T=0.0, B_angle_rad=0.0, N_per_m3=2.5e25,
                  T_K=293.0, init_energy_eV=0.1, secondaries=0, grid_P=64, grid_emin=-14,
-                 grid_emax=12, user_majorant=0.0):
+                 grid_emax=12, user_majorant=0.0, trial_strategy=0, trial_zeta=0.25,
+                 trial_grace=5000):
         L = lib()
         self._keep = []
         comps = (_Component * len(components))()
@@ -173,7 +176,8 @@ class OracleModel:
             comps[ci].n_channels = len(c.channels)
             comps[ci].channels = chs
         p = _Params(E_V_per_m, B_T, B_angle_rad, N_per_m3, T_K, init_energy_eV, secondaries,
-                    grid_P, grid_emin, grid_emax, user_majorant)
+                    grid_P, grid_emin, grid_emax, user_majorant, trial_strategy, trial_zeta,
+                    trial_grace)
         st = ctypes.c_int32(0)
         self.h = L.or_create(comps, len(components), ctypes.byref(p), ctypes.byref(st))
         if not self.h:
@@ -184,6 +188,9 @@ class OracleModel:
     @classmethod
     def from_config(cls, cfg, **kw):
         kw.setdefault("user_majorant", cfg.user_majorant)
+        kw.setdefault("trial_strategy", cfg.trial_strategy)
+        kw.setdefault("trial_zeta", cfg.trial_zeta)
+        kw.setdefault("trial_grace", cfg.trial_grace)
         return cls(cfg.components, cfg.E_V_per_m, cfg.B_T, cfg.B_angle_rad, cfg.N_per_m3, cfg.T_K,
                    cfg.init_energy_eV, cfg.secondaries, **kw)
 

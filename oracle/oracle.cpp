@@ -157,6 +157,9 @@ struct Params {
   int secondaries;  // 0 dummy (counted only), 1 real (children created / electrons removed)
   int grid_P, grid_emin, grid_emax;
   double user_majorant;
+  int trial_strategy;   // 0 constant nu' (lazy maximum or fixed), 1 variable (zeta, grace)
+  double zeta;          // variable: nu' = (1 + zeta) nu(eps)
+  int64_t grace;        // variable: trials between updates of nu'
 };
 
 struct Model {
@@ -258,11 +261,11 @@ double energy_after_inelastic(double eps, double eps_k, double cos_t, double M) 
 // ---------------------------------------------------------------------------------------
 constexpr uint32_t FLAG_FINISHED = 1, FLAG_ATTACHED = 2, FLAG_STUCK = 4;
 constexpr uint64_t kMaxBlocks = 0x7fffffffull;   // per-electron cap on trial blocks
-constexpr int EV_REAL = 1, EV_FORBIDDEN = 2;
+constexpr int EV_REAL = 1, EV_FORBIDDEN = 2, EV_FAIL = 3;
 
 struct Record {
   uint64_t id;
-  uint32_t flags, k_start, k_end, G, D, n_forbidden, n_over, pad;
+  uint32_t flags, k_start, k_end, G, D, n_forbidden, n_over, n_fail;
   uint64_t n_null, blocks;
   double r[3], t, sum_eps, sum_epsp;
 };
@@ -279,6 +282,7 @@ struct Electron {
   Vec3 r, v;
   double t;
   uint32_t k;
+  double eps_birth;   // energy it was created with (eV): the initial energy or eps'/2
 };
 
 struct RunCtx {
@@ -292,6 +296,11 @@ struct RunCtx {
   std::atomic<int>* capacity_error;
 };
 
+// The paper's VariableTrialFrequency (section "Trial frequency strategies"): a new trial
+// frequency nu' = (1 + zeta) nu(eps) from the total rate at the current energy.  It is
+// capped at the constant (lazy) maximum, which can never fail, so repeated fails end.
+double variable_nup(const Model& m, double nu) { return std::min((1.0 + m.p.zeta) * nu, m.majorant); }
+
 bool traced(const RunCtx& cx, uint64_t id) {
   return std::find(cx.trace_ids.begin(), cx.trace_ids.end(), id) != cx.trace_ids.end();
 }
@@ -303,7 +312,12 @@ Record simulate(const RunCtx& cx, const Electron& e0, std::vector<Electron>& chi
                 std::vector<Event>& events) {
   const Model& m = *cx.m;
   const int nc = static_cast<int>(m.ch.size());
-  const double nup = m.majorant;
+  // Trial frequency: constant (lazy maximum or the user's fixed value), or the variable
+  // strategy: the first value from the birth energy, then updated after every `grace`
+  // trials (from the energy after the trial that used up the grace) and after every fail.
+  const bool variable = m.p.trial_strategy == 1;
+  double nup = variable ? variable_nup(m, nu_total(m, e0.eps_birth)) : m.majorant;
+  int64_t grace = m.p.grace;
   Record rec{};
   rec.id = e0.id;
   rec.k_start = e0.k;
@@ -328,17 +342,40 @@ Record simulate(const RunCtx& cx, const Electron& e0, std::vector<Electron>& chi
     for (int sub = 0; sub < 2; ++sub) {
       const double u_f = uniform53(hi.w[2 * sub], lo.w[2 * sub]);
       const double u_r = uniform53(hi.w[2 * sub + 1], lo.w[2 * sub + 1]);
-      // Flight time against the constant trial frequency nu' (eq. random_time).
+      // Flight time against the trial frequency nu' (eq. random_time).
       T += -std::log(1.0 - u_f) / nup;
       Vec3 vT;
       move(m, r, v, T, nullptr, &vT);
       const double eps = energy_eV(vT);
+      bool over = false;
+      const double nu = nu_total(m, eps, &over);
+      if (variable && nu > nup) {
+        // Fail: nu(eps) <= nu' does not hold just before the candidate.  The electron goes
+        // back to the state of its last real collision (the anchor: T = 0), a new nu' comes
+        // from the rate that failed, and the grace count restarts.  The fail uses up its
+        // trial and ends the block.
+        ++rec.n_fail;
+        if (tr && n_ev < cx.max_events) {
+          Event ev{};
+          ev.id = e0.id; ev.type = EV_FAIL; ev.channel = -1; ev.k = k;
+          ev.block = blk; ev.sub = sub; ev.eps = eps; ev.epsp = eps;
+          ev.t = t + T; ev.r[0] = r.x; ev.r[1] = r.y; ev.r[2] = r.z;
+          events.push_back(ev);
+          ++n_ev;
+        }
+        T = 0.0;
+        nup = variable_nup(m, nu);
+        grace = m.p.grace;
+        break;
+      }
       // Null test (eq. null_fraction): null when R > nu(eps)/nu'; here real iff
       // R nu' < nu(eps) (strict), with the same R choosing the channel below.
       const double x = u_r * nup;
-      bool over = false;
-      const double nu = nu_total(m, eps, &over);
-      if (!(x < nu)) { ++rec.n_null; continue; }
+      if (!(x < nu)) {
+        ++rec.n_null;
+        if (variable && --grace == 0) { nup = variable_nup(m, nu); grace = m.p.grace; }
+        continue;
+      }
       int c = 0;
       while (c < nc - 1 && !(x < interp(m, &m.C[static_cast<size_t>(c) * m.G], eps, nullptr))) ++c;
       const Channel& chn = m.ch[c];
@@ -347,6 +384,7 @@ Record simulate(const RunCtx& cx, const Electron& e0, std::vector<Electron>& chi
           eps < chn.threshold_eV * ((kMe + M) / M)) {
         // Kinematically forbidden just above threshold (grid smearing): treated as null.
         ++rec.n_forbidden;
+        if (variable && --grace == 0) { nup = variable_nup(m, nu); grace = m.p.grace; }
         if (tr && n_ev < cx.max_events) {
           Event ev{};
           ev.id = e0.id; ev.type = EV_FORBIDDEN; ev.channel = c; ev.k = k;
@@ -389,6 +427,7 @@ Record simulate(const RunCtx& cx, const Electron& e0, std::vector<Electron>& chi
           child.k = k + 1;
           child.v = scale(iso_direction(uniform53(sh.w[2], sl.w[2]), uniform53(sh.w[3], sl.w[3])),
                           speed_from_energy(epsp));
+          child.eps_birth = epsp;
           const int64_t n_created = cx.created->fetch_add(1) + 1;
           if (n_created > cx.capacity) {
             cx.capacity_error->store(1);
@@ -414,6 +453,7 @@ Record simulate(const RunCtx& cx, const Electron& e0, std::vector<Electron>& chi
       t += T;
       T = 0.0;
       v = scale(n, speed_from_energy(epsp));
+      if (variable && --grace == 0) { nup = variable_nup(m, nu_total(m, epsp)); grace = m.p.grace; }
       break;
     }
   }
@@ -435,6 +475,7 @@ Electron primary(const Model& m, uint64_t seed, uint64_t id) {
   e.k = 0;
   e.v = scale(iso_direction(uniform53(hi.w[0], lo.w[0]), uniform53(hi.w[1], lo.w[1])),
               speed_from_energy(m.p.eps0));
+  e.eps_birth = m.p.eps0;
   return e;
 }
 
@@ -455,7 +496,8 @@ struct or_channel { int32_t kind; double threshold_eV; int32_t n_points; const d
                     const double* sigma_m2; };
 struct or_component { double mass_amu; double fraction; int32_t n_channels; const or_channel* channels; };
 struct or_params { double E_V_per_m, B_T, B_angle_rad, N_per_m3, T_K, init_energy_eV;
-                   int32_t secondaries, grid_P, grid_emin, grid_emax; double user_majorant; };
+                   int32_t secondaries, grid_P, grid_emin, grid_emax; double user_majorant;
+                   int32_t trial_strategy; double trial_zeta; int64_t trial_grace; };
 
 enum { OR_OK = 0, OR_INVALID = -1, OR_CAPACITY = -3 };
 
@@ -477,10 +519,14 @@ void* or_create(const or_component* comps, int32_t n_comps, const or_params* p, 
   if (!(p->N_per_m3 > 0.0) || !(p->E_V_per_m >= 0.0) || !(p->B_T >= 0.0) || !(p->init_energy_eV >= 0.0))
     return nullptr;
   if (p->grid_P <= 0 || (p->grid_P & (p->grid_P - 1)) != 0 || p->grid_emax <= p->grid_emin) return nullptr;
+  if (p->trial_strategy < 0 || p->trial_strategy > 1) return nullptr;
+  if (p->trial_strategy == 1 && (!(p->trial_zeta > 0.0) || !std::isfinite(p->trial_zeta) || p->trial_grace < 1))
+    return nullptr;
   double fsum = 0.0;
   auto* m = new Model();
   m->p = {p->E_V_per_m, p->B_T, p->B_angle_rad, p->N_per_m3, p->T_K, p->init_energy_eV,
-          p->secondaries, p->grid_P, p->grid_emin, p->grid_emax, p->user_majorant};
+          p->secondaries, p->grid_P, p->grid_emin, p->grid_emax, p->user_majorant,
+          p->trial_strategy, p->trial_zeta, p->trial_grace};
   for (int k = 0; k < n_comps; ++k) {
     const or_component& c = comps[k];
     if (!(c.mass_amu > 0.0) || !(c.fraction >= 0.0) || c.n_channels <= 0) { delete m; return nullptr; }

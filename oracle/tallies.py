@@ -38,7 +38,8 @@ def tallies(records):
     out["n_real"] = K_real
     out["n_null"] = K_null
     out["n_forbidden"] = K_forb
-    out["n_fail"] = 0
+    K_fail = int(rec["n_fail"].astype(np.int64).sum())
+    out["n_fail"] = K_fail
     out["n_over"] = int(rec["n_over"].astype(np.int64).sum())
     out["n_electrons"] = int(len(rec))
     out["n_finished"] = int(fin.sum())
@@ -47,8 +48,9 @@ def tallies(records):
     out["n_created"] = int((rec["id"] >> np.uint64(63) != 0).sum())
     out["n_ionizations"] = int(rec["G"].astype(np.int64).sum())
     out["n_attachments"] = int(rec["D"].astype(np.int64).sum())
-    trials = K_real + K_null + K_forb
-    # Efficiency: real / (real + null + fail); forbidden events count as null trials.
+    trials = K_real + K_null + K_forb + K_fail
+    # Efficiency (section "Trial frequency strategies"): real / (real + null + fail);
+    # forbidden events count as null trials.
     out["efficiency"] = K_real / trials if trials else float("nan")
 
     # Mean energies before and after the collisions: plain means over every real collision.

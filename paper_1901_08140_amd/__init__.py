@@ -23,6 +23,7 @@ SWARM_ERR_DEVICE, SWARM_ERR_STATE, SWARM_PENDING = -4, -5, 1
 SWARM_ELASTIC, SWARM_EXCITATION, SWARM_IONIZATION, SWARM_ATTACHMENT = 0, 1, 2, 3
 SWARM_FP64, SWARM_FP32_MIXED = 0, 1
 SWARM_DUMMY, SWARM_REAL = 0, 1
+SWARM_TRIAL_CONSTANT, SWARM_TRIAL_VARIABLE = 0, 1
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1901_08140_amd/build.py`")
@@ -46,7 +47,8 @@ class swarm_params(ctypes.Structure):
     _fields_ = [("E_V_per_m", _d), ("B_T", _d), ("B_angle_rad", _d), ("N_per_m3", _d), ("T_K", _d),
                 ("init_energy_eV", _d), ("precision", _i32), ("secondaries", _i32),
                 ("grid_points_per_octave", _i32), ("grid_min_exp2", _i32), ("grid_max_exp2", _i32),
-                ("user_majorant", _d), ("capacity", _i64), ("stream", _vp)]
+                ("user_majorant", _d), ("capacity", _i64), ("stream", _vp),
+                ("trial_strategy", _i32), ("trial_zeta", _d), ("trial_grace", _i64)]
 
 
 class swarm_stat(ctypes.Structure):
@@ -85,7 +87,7 @@ class swarm_request_info(ctypes.Structure):
 
 
 RECORD_DTYPE = np.dtype({
-    "names": ["id", "flags", "k_start", "k_end", "G", "D", "n_forbidden", "n_over", "pad",
+    "names": ["id", "flags", "k_start", "k_end", "G", "D", "n_forbidden", "n_over", "n_fail",
               "n_null", "blocks", "r", "t", "sum_eps", "sum_epsp"],
     "formats": ["<u8", "<u4", "<u4", "<u4", "<u4", "<u4", "<u4", "<u4", "<u4",
                 "<u8", "<u8", ("<f8", (3,)), "<f8", "<f8", "<f8"],
@@ -178,19 +180,24 @@ class _Marshalled:
 
 def make_params(E_V_per_m, B_T=0.0, B_angle_rad=0.0, N_per_m3=2.5e25, T_K=293.0, init_energy_eV=0.1,
                 precision=SWARM_FP64, secondaries=SWARM_DUMMY, grid_points_per_octave=0, grid_min_exp2=0,
-                grid_max_exp2=0, user_majorant=0.0, capacity=0, stream=None):
+                grid_max_exp2=0, user_majorant=0.0, capacity=0, stream=None,
+                trial_strategy=0, trial_zeta=0.0, trial_grace=0):
     p = swarm_params()
     p.E_V_per_m, p.B_T, p.B_angle_rad, p.N_per_m3, p.T_K = E_V_per_m, B_T, B_angle_rad, N_per_m3, T_K
     p.init_energy_eV, p.precision, p.secondaries = init_energy_eV, int(precision), int(secondaries)
     p.grid_points_per_octave, p.grid_min_exp2, p.grid_max_exp2 = grid_points_per_octave, grid_min_exp2, grid_max_exp2
     p.user_majorant, p.capacity = user_majorant, int(capacity)
     p.stream = _stream_handle(stream)
+    p.trial_strategy, p.trial_zeta, p.trial_grace = int(trial_strategy), float(trial_zeta), int(trial_grace)
     return p
 
 
 def params_from_config(cfg, precision=SWARM_FP64, **kw):
     """swarm_params of a synth.SwarmConfig."""
     kw.setdefault("user_majorant", cfg.user_majorant)
+    kw.setdefault("trial_strategy", getattr(cfg, "trial_strategy", 0))
+    kw.setdefault("trial_zeta", getattr(cfg, "trial_zeta", 0.0))
+    kw.setdefault("trial_grace", getattr(cfg, "trial_grace", 0))
     return make_params(cfg.E_V_per_m, cfg.B_T, cfg.B_angle_rad, cfg.N_per_m3, cfg.T_K, cfg.init_energy_eV,
                        precision, cfg.secondaries, **kw)
 

@@ -104,6 +104,14 @@ swarm_status validate(const swarm_component* comps, int32_t n_comps, const swarm
   if (!(p->user_majorant >= 0.0) || !std::isfinite(p->user_majorant))
     return fail(SWARM_ERR_INVALID_ARG, "user majorant must be >= 0");
   if (p->capacity < 0) return fail(SWARM_ERR_INVALID_ARG, "capacity must be >= 0");
+  if (p->trial_strategy != SWARM_TRIAL_CONSTANT && p->trial_strategy != SWARM_TRIAL_VARIABLE)
+    return fail(SWARM_ERR_INVALID_ARG, "unknown trial strategy %d", p->trial_strategy);
+  if (p->trial_strategy == SWARM_TRIAL_VARIABLE) {
+    if (!(p->trial_zeta >= 0.0) || !std::isfinite(p->trial_zeta))
+      return fail(SWARM_ERR_INVALID_ARG, "trial zeta must be finite and > 0 (0 = default)");
+    if (p->trial_grace < 0 || p->trial_grace > 0x7fffffffLL)
+      return fail(SWARM_ERR_INVALID_ARG, "trial grace must be in [1, 2^31 - 1] (0 = default)");
+  }
   const int P = p->grid_points_per_octave ? p->grid_points_per_octave : 64;
   if (P <= 0 || P > 1024 || (P & (P - 1)) != 0)
     return fail(SWARM_ERR_INVALID_ARG, "grid points per octave must be a power of two <= 1024");
@@ -309,6 +317,9 @@ swarm_status swarm_create(const swarm_component* comps, int32_t n_comps, const s
   d.precision = params->precision; d.secondaries = params->secondaries;
   d.E = params->E_V_per_m; d.B = params->B_T; d.B_angle = params->B_angle_rad; d.N = params->N_per_m3;
   d.eps0 = params->init_energy_eV; d.user_majorant = params->user_majorant;
+  d.trial_strategy = params->trial_strategy;
+  d.trial_zeta = params->trial_zeta > 0.0 ? params->trial_zeta : 0.25;
+  d.trial_grace = static_cast<uint32_t>(params->trial_grace > 0 ? params->trial_grace : 5000);
   h->has_b = params->B_T > 0.0;
   // one arena for the raw inputs and the tables
   auto al = [](size_t n) { return (n + 255) & ~size_t(255); };
@@ -452,7 +463,8 @@ swarm_status swarm_run(swarm_t h, int64_t n_electrons, int64_t n_collisions, uin
   const size_t lds = lds_bytes_for(d.precision, d.G, d.nc);
   const int ch_off = lds_channel_offset(d.precision, d.G);
   DeviceInfo& dev = device_info();
-  const int per_cu = swarm_kernel_max_blocks_per_cu(d.precision, h->has_b, trace, real, o.block_size, lds);
+  const bool var = d.trial_strategy == SWARM_TRIAL_VARIABLE;
+  const int per_cu = swarm_kernel_max_blocks_per_cu(d.precision, h->has_b, trace, real, var, o.block_size, lds);
   if ((e = hipEventRecord(h->ev[0], s)) != hipSuccess) return hip_fail(e, "event");
   if (!real) {
     // enough work items to give every resident work-group several of them
@@ -470,12 +482,12 @@ swarm_status swarm_run(swarm_t h, int64_t n_electrons, int64_t n_collisions, uin
     if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(d_ctr), 0u, 1, s)) != hipSuccess) return hip_fail(e, "item counter");
     const int grid = std::max(1, std::min<int>(static_cast<int>(items.size()), dev.n_cu * per_cu));
     if ((e = launch_swarm_dummy(h->d_desc, static_cast<const WorkItem*>(h->items.p), static_cast<int32_t>(items.size()),
-                                d_ctr, d.precision, h->has_b, trace, o.block_size, grid, o.pending_trigger, lds, ch_off, s)) != hipSuccess)
+                                d_ctr, d.precision, h->has_b, trace, var, o.block_size, grid, o.pending_trigger, lds, ch_off, s)) != hipSuccess)
       return hip_fail(e, "swarm kernel launch");
   } else {
     const int64_t want = (n_electrons + o.block_size - 1) / o.block_size;
     const int grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want * 4, static_cast<int64_t>(dev.n_cu) * per_cu)));
-    if ((e = launch_swarm_real(h->d_desc, d.precision, h->has_b, trace, o.block_size, grid, o.pending_trigger, lds, ch_off, s)) != hipSuccess)
+    if ((e = launch_swarm_real(h->d_desc, d.precision, h->has_b, trace, var, o.block_size, grid, o.pending_trigger, lds, ch_off, s)) != hipSuccess)
       return hip_fail(e, "swarm kernel launch");
   }
   if ((e = hipEventRecord(h->ev[1], s)) != hipSuccess) return hip_fail(e, "event");

@@ -17,6 +17,7 @@ struct swarm_batch {
   std::vector<swarm_job> jobs;
   int precision = 0;
   bool magnetic = false;
+  bool variable = false;   // some instance uses the variable trial frequency
   hipStream_t stream = nullptr;
   DevBuf descs, items;
   std::vector<InstanceDesc> h_descs;
@@ -56,7 +57,7 @@ hipError_t enqueue(swarm_batch* b) {
   if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(item_counter(b)), 0u, 1, b->stream)) != hipSuccess) return e;
   if ((e = launch_swarm_dummy(static_cast<const InstanceDesc*>(b->descs.p), static_cast<const WorkItem*>(b->items.p),
                               static_cast<int32_t>(b->h_items.size()), item_counter(b), b->precision, b->magnetic,
-                              false, b->opts.block_size, b->grid, b->opts.pending_trigger, b->lds, b->ch_off, b->stream)) != hipSuccess)
+                              false, b->variable, b->opts.block_size, b->grid, b->opts.pending_trigger, b->lds, b->ch_off, b->stream)) != hipSuccess)
     return e;
   return b->tally.launch(static_cast<const InstanceDesc*>(b->descs.p), b->stream);
 }
@@ -85,6 +86,7 @@ swarm_status swarm_batch_create(swarm_t* handles, const swarm_job* jobs, int32_t
     for (int j = 0; j < i; ++j)
       if (handles[j] == h) return fail(SWARM_ERR_INVALID_ARG, "handle %d appears twice", i);
     b->magnetic |= h->has_b;
+    b->variable |= h->desc.trial_strategy == SWARM_TRIAL_VARIABLE;
     G = std::max(G, h->desc.G);
     n_ch = std::max(n_ch, h->desc.nc);
     b->hs.push_back(h);
@@ -130,7 +132,7 @@ swarm_status swarm_batch_create(swarm_t* handles, const swarm_job* jobs, int32_t
   if ((e = b->tally.prepare(ne, b->stream)) != hipSuccess) return hip_fail(e, "tally plan");
   b->lds = lds_bytes_for(b->precision, G, n_ch);
   b->ch_off = lds_channel_offset(b->precision, G);
-  const int per_cu = swarm_kernel_max_blocks_per_cu(b->precision, b->magnetic, false, false, b->opts.block_size, b->lds);
+  const int per_cu = swarm_kernel_max_blocks_per_cu(b->precision, b->magnetic, false, false, b->variable, b->opts.block_size, b->lds);
   b->grid = std::max(1, std::min<int>(static_cast<int>(b->h_items.size()), device_info().n_cu * per_cu));
   if ((e = hipStreamSynchronize(b->stream)) != hipSuccess) return hip_fail(e, "uploading batch");
   if (b->opts.use_graph) {

@@ -12,7 +12,7 @@ namespace swarm_impl {
 constexpr int kMaxTraceIds = 256;
 constexpr int kTallyTile = 2048;          // records per tally work-group (fixed: determinism)
 constexpr int kTallyThreads = 256;
-constexpr int kTally1 = 24;               // pass-1 accumulators
+constexpr int kTally1 = 25;               // pass-1 accumulators
 constexpr int kTally2 = 32;               // pass-2 accumulators
 constexpr uint32_t kMaxBlocks = 0x7fffffffu;   // per-electron cap on trial blocks
 
@@ -44,6 +44,8 @@ struct SavedState {
   uint64_t id;
   uint32_t block, k, k_start, G, D, n_forb, n_over, n_first;
   uint32_t started, pad;
+  double nup;                 // trial frequency in use (variable strategy)
+  uint32_t grace, n_fail;     // trials left before its next update; fails so far
 };
 
 // Child electron waiting in the real-secondaries queue.
@@ -52,6 +54,7 @@ struct ChildState {
   double v[3];
   uint64_t id;
   uint32_t k, pad;
+  double eps_birth;           // energy it was created with (eV), for its first trial frequency
 };
 
 // Device counters of one instance's run.
@@ -75,6 +78,9 @@ struct InstanceDesc {
   int32_t n_raw_channels;
   int32_t precision, secondaries;
   double E, B, B_angle, N, eps0, user_majorant;
+  int32_t trial_strategy;     // SWARM_TRIAL_CONSTANT or SWARM_TRIAL_VARIABLE
+  uint32_t trial_grace;       // variable: trials between updates of nu'
+  double trial_zeta;          // variable: nu' = (1 + zeta) nu(eps)
   const double* raw_e;        // concatenated raw energies
   const double* raw_s;        // concatenated raw cross-sections
   const int32_t* raw_off;     // per channel: first point
@@ -147,16 +153,16 @@ hipError_t launch_mark_empty(swarm_record* r, int64_t n, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
 hipError_t launch_swarm_dummy(const InstanceDesc* d_desc, const WorkItem* d_items, int32_t n_items,
                               int32_t* d_item_counter, int precision, bool has_b, bool trace,
-                              int block_size, int grid, int pending_trigger, size_t lds_bytes,
+                              bool var, int block_size, int grid, int pending_trigger, size_t lds_bytes,
                               int ch_off, hipStream_t s);
 hipError_t launch_swarm_real(const InstanceDesc* d_desc, int precision, bool has_b, bool trace,
-                             int block_size, int grid, int pending_trigger, size_t lds_bytes,
+                             bool var, int block_size, int grid, int pending_trigger, size_t lds_bytes,
                              int ch_off, hipStream_t s);
 hipError_t launch_tallies(const InstanceDesc* d_desc, const TallyTile* d_tiles, int32_t n_tiles,
                           const int32_t* d_tile_base, const int64_t* d_nrec, int32_t n_inst,
                           double* d_part1, double* d_part2, double* d_tot1,
                           swarm_tallies_t* d_out, hipStream_t s);
-int swarm_kernel_max_blocks_per_cu(int precision, bool has_b, bool trace, bool real, int block_size,
+int swarm_kernel_max_blocks_per_cu(int precision, bool has_b, bool trace, bool real, bool var, int block_size,
                                    size_t lds_bytes);
 
 }  // namespace swarm_impl

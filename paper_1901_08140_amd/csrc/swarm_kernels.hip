@@ -374,7 +374,11 @@ struct Consts {
   R nup24;       // FP32: nu' 2^-24 (x = R nu' straight from the 24-bit integer)
   R Pf, twoPf;   // grid points per octave, and twice that, as floating point
   R sceps;       // FP32: sqrt(m/2e)
+  R zeta1;       // variable trial frequency: 1 + zeta
+  R eps0;        // initial energy of the primaries (eV)
   bool magnetic; // B > 0 (kernels built for B may also serve B = 0 instances)
+  bool variable; // variable trial frequency (otherwise the constant nu' above)
+  uint32_t grace0;
   int G, nc, off, p;
   int off1;      // off - 1: raw index of entry 0 of the padded LDS table
   int off1G;     // off1 + G: raw index of its last entry
@@ -408,6 +412,10 @@ __device__ __forceinline__ Consts<R> load_consts(const InstanceDesc& d) {
     c.Pf = d.Pf_f; c.twoPf = d.twoPf_f;
   }
   c.magnetic = d.B > 0.0;
+  c.variable = d.trial_strategy == SWARM_TRIAL_VARIABLE;
+  c.grace0 = d.trial_grace;
+  c.zeta1 = static_cast<R>(1.0 + d.trial_zeta);
+  c.eps0 = static_cast<R>(d.eps0);
   c.G = d.G; c.nc = d.nc; c.p = d.p_log2;
   c.n_coll = d.n_collisions; c.quantum = d.quantum;
   c.key = {static_cast<uint32_t>(d.seed), static_cast<uint32_t>(d.seed >> 32)};
@@ -422,6 +430,9 @@ struct Lane {
   double rx, ry, rz, t;     // anchor (state right after the last real collision), FP64
   R vx, vy, vz;             // anchor velocity
   R T;                      // flight time since the anchor
+  R nup, cT, nup24;         // trial frequency nu', flight-time scale (FP32 ln2/nu', FP64
+                            // 1/nu') and FP32 nu' 2^-24
+  uint32_t grace, nfail;    // variable strategy: trials left before nu' is renewed; fails
   R q0;                     // B = 0: vx^2 + vy^2;  B != 0: |vD|^2 + |u0|^2
   R vpar;                   // B != 0: v0 . b
   R u0x, u0y, u0z;          // B != 0: v0 - (v0.b) b - vD
@@ -540,6 +551,55 @@ __device__ __forceinline__ double lds_rate(const double2* __restrict__ s_nu, dou
   return q.x + w * q.y;
 }
 
+// Total rate at eps (no table position needed).
+template <typename R>
+__device__ __forceinline__ R rate_at(const typename Pair<R>::T* __restrict__ s_nu, R eps, const Consts<R>& C) {
+  int raw;
+  R w;
+  return lds_rate(s_nu, eps, C, &raw, &w);
+}
+
+// Trial frequency of a lane.  The constant strategy (the paper's LazyTrialFrequency or a
+// fixed value) uses the instance's nu'.  The variable strategy (section "Trial frequency
+// strategies", VariableTrialFrequency) sets nu' = (1 + zeta) nu(eps) from the total rate at
+// the current energy, capped at the constant value, which can never fail; it is renewed
+// after every `grace` trials and after every fail.
+template <typename R>
+__device__ __forceinline__ void constant_trial_frequency(Lane<R>& L, const Consts<R>& C) {
+  L.nup = C.nup;
+  L.cT = C.cT;
+  L.nup24 = C.nup24;
+}
+template <typename R>
+__device__ __forceinline__ void apply_trial_frequency(Lane<R>& L, const Consts<R>& C, R v) {
+  L.nup = v;
+  if constexpr (sizeof(R) == 4) {
+    L.cT = 0.693147180559945309f / v;
+    L.nup24 = v * 0x1.0p-24f;
+  } else {
+    L.cT = 1.0 / v;
+    L.nup24 = 0.0;
+  }
+}
+template <typename R>
+__device__ __forceinline__ void variable_trial_frequency(Lane<R>& L, const Consts<R>& C, R nu) {
+  const R v = C.zeta1 * nu;
+  if (v < C.nup) apply_trial_frequency(L, C, v);
+  else constant_trial_frequency(L, C);     // at the cap: exactly the constant strategy
+  L.grace = C.grace0;
+}
+// VAR: the kernel is built for instances that may use the variable strategy.  Kernels
+// built without it keep nu' in the instance constants and carry no per-lane frequency.
+template <typename R, bool VAR>
+__device__ __forceinline__ void start_trial_frequency(Lane<R>& L, const Consts<R>& C,
+                                                      const typename Pair<R>::T* __restrict__ s_nu, R eps) {
+  L.nfail = 0;
+  if constexpr (VAR) {
+    if (C.variable) variable_trial_frequency(L, C, rate_at<R>(s_nu, eps, C));
+    else constant_trial_frequency(L, C);
+  }
+}
+
 // Velocity and displacement after a flight of duration T from the anchor (the same
 // equations of motion, written per component).
 template <typename R, bool HB>
@@ -588,8 +648,9 @@ __device__ __forceinline__ void move_full(const Lane<R>& L, const Consts<R>& C, 
 }
 
 // Start a primary: at the origin, energy eps0, isotropic direction from the INIT stream.
-template <typename R, bool HB>
-__device__ __forceinline__ void init_primary(Lane<R>& L, const Consts<R>& C, uint64_t id) {
+template <typename R, bool HB, bool VAR>
+__device__ __forceinline__ void init_primary(Lane<R>& L, const Consts<R>& C,
+                                             const typename Pair<R>::T* __restrict__ s_nu, uint64_t id) {
   const W4 h = draw(C.key, id, TAG_INIT_HI, 0);
   W4 l = {0, 0, 0, 0};
   if constexpr (sizeof(R) == 8) l = draw(C.key, id, TAG_INIT_LO, 0);
@@ -607,6 +668,7 @@ __device__ __forceinline__ void init_primary(Lane<R>& L, const Consts<R>& C, uin
   L.se = L.sep = 0.0;
   L.T = R(0);
   set_anchor<R, HB>(L, C);
+  start_trial_frequency<R, VAR>(L, C, s_nu, C.eps0);
 }
 
 template <typename R>
@@ -620,10 +682,10 @@ __device__ __forceinline__ void write_record(const InstanceDesc& d, const Lane<R
   r.D = L.D;
   r.n_forbidden = L.nforb;
   r.n_over = L.nover;
-  r.pad = 0;
+  r.n_fail = L.nfail;
   // null trials: two per block, less the unused second trials (first trial not null),
-  // less the real collisions and forbidden picks of this electron
-  r.n_null = 2ull * L.block - L.nfirst - (L.k - L.k_start) - L.nforb;
+  // less the real collisions, forbidden picks and fails of this electron
+  r.n_null = 2ull * L.block - L.nfirst - (L.k - L.k_start) - L.nforb - L.nfail;
   r.blocks = L.block;
   r.r[0] = L.rx; r.r[1] = L.ry; r.r[2] = L.rz;
   r.t = L.t;
@@ -632,8 +694,9 @@ __device__ __forceinline__ void write_record(const InstanceDesc& d, const Lane<R
   d.records[L.rec] = r;
 }
 
-template <typename R>
-__device__ __forceinline__ void save_state(const InstanceDesc& d, const Lane<R>& L, int64_t e) {
+template <typename R, bool VAR>
+__device__ __forceinline__ void save_state(const InstanceDesc& d, const Lane<R>& L, const Consts<R>& C,
+                                           int64_t e) {
   SavedState s;
   s.r[0] = L.rx; s.r[1] = L.ry; s.r[2] = L.rz;
   s.t = L.t;
@@ -644,10 +707,13 @@ __device__ __forceinline__ void save_state(const InstanceDesc& d, const Lane<R>&
   s.block = L.block; s.k = L.k; s.k_start = L.k_start; s.G = L.G; s.D = L.D;
   s.n_forb = L.nforb; s.n_over = L.nover; s.n_first = L.nfirst;
   s.started = 1; s.pad = L.flags;
+  s.nup = static_cast<double>(VAR ? L.nup : C.nup);
+  s.grace = VAR ? L.grace : 0u;
+  s.n_fail = L.nfail;
   d.saved[e] = s;
 }
 
-template <typename R, bool HB>
+template <typename R, bool HB, bool VAR>
 __device__ __forceinline__ void load_state(const InstanceDesc& d, Lane<R>& L, const Consts<R>& C, int64_t e) {
   const SavedState s = d.saved[e];
   L.rx = s.r[0]; L.ry = s.r[1]; L.rz = s.r[2];
@@ -658,6 +724,14 @@ __device__ __forceinline__ void load_state(const InstanceDesc& d, Lane<R>& L, co
   L.block = s.block; L.k = s.k; L.k_start = s.k_start; L.G = s.G; L.D = s.D;
   L.nforb = s.n_forb; L.nover = s.n_over; L.nfirst = s.n_first; L.flags = s.pad;
   L.T = R(0);
+  if constexpr (VAR) {
+    // the same derived values as when nu' was set (at the cap: the constant strategy's)
+    const R v = static_cast<R>(s.nup);
+    if (C.variable && v < C.nup) apply_trial_frequency(L, C, v);
+    else constant_trial_frequency(L, C);
+    L.grace = s.grace;
+  }
+  L.nfail = s.n_fail;
   set_anchor<R, HB>(L, C);
 }
 
@@ -692,21 +766,29 @@ __device__ __forceinline__ void trace_event(const InstanceDesc& d, Lane<R>& L, i
 // the flight time grows by -ln(1-u)/nu' (eq. random_time), the energy at the new time is
 // looked up in the LDS rate table, and the trial is real when x = u_r nu' < nu(eps)
 // (eq. null_fraction).  Leaves eps, x and the table position in the candidate fields.
-template <typename R, bool HB>
+template <typename R, bool HB, bool VAR>
 __device__ __forceinline__ bool one_trial(Lane<R>& L, const Consts<R>& C,
                                           const typename Pair<R>::T* __restrict__ s_nu,
                                           uint32_t hf, uint32_t hr, uint32_t lf, uint32_t lr) {
   if constexpr (sizeof(R) == 4) {
     // u = (hf >> 8) 2^-24: -ln(1-u)/nu' = (24 - log2(2^24 - (hf >> 8))) ln2/nu'
     const float l2 = __builtin_amdgcn_logf(static_cast<float>(0x1000000u - (hf >> 8)));
-    L.T = fmaf(l2 - 24.0f, -C.cT, L.T);
-    L.p_x = static_cast<float>(hr >> 8) * C.nup24;    // = u_r nu' exactly
+    L.T = fmaf(l2 - 24.0f, -(VAR ? L.cT : C.cT), L.T);
+    L.p_x = static_cast<float>(hr >> 8) * (VAR ? L.nup24 : C.nup24);    // = u_r nu' exactly
   } else {
-    L.T = L.T + flight(uni(hf, lf, R(0)), C.cT);
-    L.p_x = uni(hr, lr, R(0)) * C.nup;
+    L.T = L.T + flight(uni(hf, lf, R(0)), VAR ? L.cT : C.cT);
+    L.p_x = uni(hr, lr, R(0)) * (VAR ? L.nup : C.nup);
   }
   L.p_eps = energy_at<R, HB>(L, C, L.T);
-  return L.p_x < lds_rate(s_nu, L.p_eps, C, &L.p_gi, &L.p_w);
+  const R nu = lds_rate(s_nu, L.p_eps, C, &L.p_gi, &L.p_w);
+  // Not null when x < nu.  That includes nu > nu' (then x < nu' < nu), a fail of the
+  // variable strategy, which the collision phase tells apart.
+  const bool hit = L.p_x < nu;
+  if (VAR && C.variable) {
+    L.grace -= 1u;
+    if (!hit && L.grace == 0u) variable_trial_frequency(L, C, nu);   // renewed after a null
+  }
+  return hit;
 }
 
 // One random-number block = two candidate trials (eq. random_time for the flight time,
@@ -717,7 +799,7 @@ __device__ __forceinline__ bool one_trial(Lane<R>& L, const Consts<R>& C,
 // with the counter of their scattering block (k, SCAT) instead of a trial block: they
 // would be masked off here anyway, so the scattering words cost the wave nothing and the
 // collision phase needs no generator call of its own.  The streams are unchanged.
-template <typename R, bool HB>
+template <typename R, bool HB, bool VAR>
 __device__ __forceinline__ void trial_block(Lane<R>& L, const Consts<R>& C,
                                             const typename Pair<R>::T* __restrict__ s_nu) {
   const bool waiting = L.state == ST_PENDING;
@@ -746,10 +828,10 @@ __device__ __forceinline__ void trial_block(Lane<R>& L, const Consts<R>& C,
   // The trial writes the candidate fields of the lane directly: a lane that finds a real
   // candidate becomes PENDING and stops writing them until it is served, so they need no
   // copy, and the second trial runs only on the lanes whose first one was null.
-  bool hit = one_trial<R, HB>(L, C, s_nu, h.x, h.y, l.x, l.y);
+  bool hit = one_trial<R, HB, VAR>(L, C, s_nu, h.x, h.y, l.x, l.y);
   L.p_sub = 0;
   if (!hit) {
-    hit = one_trial<R, HB>(L, C, s_nu, h.z, h.w, l.z, l.w);
+    hit = one_trial<R, HB, VAR>(L, C, s_nu, h.z, h.w, l.z, l.w);
     L.p_sub = 1;
   }
   if (hit) L.state = ST_PENDING;
@@ -763,13 +845,29 @@ enum : int { RC_CONTINUE = 0, RC_STOP = 1 };
 // check, isotropic scattering with Fraser-Mathieson energy transfer, ionisation and
 // attachment, then the anchor moves to the collision point.  Returns RC_STOP when the
 // electron has reached its stop count or was removed.
-template <typename R, bool HB, bool TR, bool REAL>
+template <typename R, bool HB, bool TR, bool REAL, bool VAR>
 __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L, const Consts<R>& C,
+                                              const typename Pair<R>::T* __restrict__ s_nu,
                                               bool* spawn, ChildState* child) {
   *spawn = false;
   const R eps = L.p_eps;
   const R x = L.p_x;
   L.nfirst += L.p_sub == 0 ? 1u : 0u;
+  R nu_eps = R(0);
+  if (VAR && C.variable) {
+    // the total rate the trial compared with (same table entry and weight)
+    nu_eps = lerp_pair(s_nu[L.p_gi - C.off1], L.p_w);
+    if (nu_eps > L.nup) {
+      // Fail: nu(eps) <= nu' does not hold.  Back to the state of the last real collision
+      // (the anchor: T = 0), a new nu' from the rate that failed, the grace count restarts.
+      L.nfail += 1u;
+      trace_event<R, TR>(d, L, 3, -1, eps, eps, L.t + static_cast<double>(L.T), L.rx, L.ry, L.rz);
+      L.T = R(0);
+      variable_trial_frequency(L, C, nu_eps);
+      L.state = ST_ACTIVE;
+      return RC_CONTINUE;
+    }
+  }
   // node and weight of the candidate (entry 0 of the padded index is below the grid, entry
   // G at or above its top; both use a constant value there)
   const int gi = L.p_gi - C.off1;
@@ -814,6 +912,7 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
     if (e64 < ch.onset) {
       L.nforb += 1;
       trace_event<R, TR>(d, L, 2, lo, eps, eps, L.t + static_cast<double>(L.T), L.rx, L.ry, L.rz);
+      if (VAR && C.variable && L.grace == 0u) variable_trial_frequency(L, C, nu_eps);   // as after a null
       L.state = ST_ACTIVE;
       return RC_CONTINUE;
     }
@@ -859,6 +958,7 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
       child->id = (static_cast<uint64_t>(cw.x) | (static_cast<uint64_t>(cw.y) << 32)) | (1ull << 63);
       child->k = L.k + 1;
       child->pad = 0;
+      child->eps_birth = static_cast<double>(epsp);
       *spawn = true;
     }
   } else if (ch.kind == SWARM_ATTACHMENT) {
@@ -874,6 +974,8 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
   L.T = R(0);
   const R sp = C.c_speed * sqrt_(epsp);
   L.vx = sp * nx; L.vy = sp * ny; L.vz = sp * nz;
+  // renewed after a real collision: from the energy after it
+  if (VAR && C.variable && L.grace == 0u) variable_trial_frequency(L, C, rate_at<R>(s_nu, epsp, C));
   if (removed) {
     L.flags |= 2u;
     return RC_STOP;
@@ -892,7 +994,7 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
 // wait (or no lane can make progress otherwise), which keeps the costly collision code
 // from running for one lane at a time.
 // ---------------------------------------------------------------------------------------
-template <typename R, bool HB, bool TR>
+template <typename R, bool HB, bool TR, bool VAR>
 __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restrict__ descs,
                                                      const WorkItem* __restrict__ items, int n_items,
                                                      int* __restrict__ item_ctr, int pend_trig,
@@ -940,8 +1042,8 @@ __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restr
           const uint32_t started = d.saved != nullptr ? d.saved[ei].started : 0u;
           if (started != 2u) {          // 2: finished in an earlier launch
             L.rec = ei;
-            if (started == 1u) load_state<R, HB>(d, L, C, ei);
-            else init_primary<R, HB>(L, C, static_cast<uint64_t>(ei));
+            if (started == 1u) load_state<R, HB, VAR>(d, L, C, ei);
+            else init_primary<R, HB, VAR>(L, C, s_nu, static_cast<uint64_t>(ei));
             L.k_stop = C.quantum ? min(C.n_coll, L.k + C.quantum) : C.n_coll;
             if constexpr (TR) {
               L.trace_slot = find_trace<TR>(d, L.id);
@@ -956,7 +1058,7 @@ __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restr
       // Trial phase: random-number blocks until enough lanes of the wave wait on a
       // real-collision candidate (or none can go on), then serve them together.
       for (;;) {
-        if (L.state == ST_ACTIVE || L.state == ST_PENDING) trial_block<R, HB>(L, C, s_nu);
+        if (L.state == ST_ACTIVE || L.state == ST_PENDING) trial_block<R, HB, VAR>(L, C, s_nu);
         const uint64_t ready = __ballot(L.state == ST_READY);
         const uint64_t busy = __ballot(L.state == ST_ACTIVE || L.state == ST_PENDING);
         if (busy == 0 || __popcll(ready) >= pend_trig) break;
@@ -964,7 +1066,7 @@ __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restr
       if (L.state == ST_READY) {
         bool spawn;
         ChildState child;
-        if (real_collision<R, HB, TR, false>(d, L, C, &spawn, &child) == RC_STOP) L.state = ST_STOPPED;
+        if (real_collision<R, HB, TR, false, VAR>(d, L, C, s_nu, &spawn, &child) == RC_STOP) L.state = ST_STOPPED;
       }
       // An electron that stopped leaves its final record (budget reached or block cap) or
       // its resumable state (end of the launch's quantum).
@@ -975,7 +1077,7 @@ __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restr
           atomicAdd(reinterpret_cast<unsigned long long*>(&d.ctr->n_done), 1ull);
           if (d.saved != nullptr) d.saved[L.rec].started = 2u;
         } else {
-          save_state(d, L, L.rec);
+          save_state<R, VAR>(d, L, C, L.rec);
         }
         L.state = ST_IDLE;
       }
@@ -992,7 +1094,7 @@ __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restr
 // after its state is written.  The kernel ends when every electron has stopped (`live`
 // reaches 0); idle waves sleep between polls and give up after a bounded number of polls.
 // ---------------------------------------------------------------------------------------
-template <typename R, bool HB, bool TR>
+template <typename R, bool HB, bool TR, bool VAR>
 __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restrict__ desc, int pend_trig,
                                                     int ch_off) {
   using PT = typename Pair<R>::T;
@@ -1028,7 +1130,7 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
     if (L.state == ST_IDLE && prim_left) {
       const uint64_t e = atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->prim_next), 1ull);
       if (static_cast<int64_t>(e) < N) {
-        init_primary<R, HB>(L, C, e);
+        init_primary<R, HB, VAR>(L, C, s_nu, e);
         L.rec = static_cast<int64_t>(e);
         L.k_stop = C.n_coll;
         if constexpr (TR) {
@@ -1065,6 +1167,7 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
           L.T = R(0);
           L.rec = N + slot;
           set_anchor<R, HB>(L, C);
+          start_trial_frequency<R, VAR>(L, C, s_nu, static_cast<R>(cs.eps_birth));
           if constexpr (TR) {
             L.trace_slot = find_trace<TR>(d, L.id);
             L.n_ev = 0;
@@ -1081,7 +1184,7 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
     }
     uint64_t ready;
     for (;;) {
-      if (L.state == ST_ACTIVE || L.state == ST_PENDING) trial_block<R, HB>(L, C, s_nu);
+      if (L.state == ST_ACTIVE || L.state == ST_PENDING) trial_block<R, HB, VAR>(L, C, s_nu);
       ready = __ballot(L.state == ST_READY);
       const uint64_t busy = __ballot(L.state == ST_ACTIVE || L.state == ST_PENDING);
       if (busy == 0 || __popcll(ready) >= pend_trig) break;
@@ -1090,7 +1193,7 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
       bool spawn = false;
       ChildState child;
       if (L.state == ST_READY) {
-        if (real_collision<R, HB, TR, true>(d, L, C, &spawn, &child) == RC_STOP) L.state = ST_STOPPED;
+        if (real_collision<R, HB, TR, true, VAR>(d, L, C, s_nu, &spawn, &child) == RC_STOP) L.state = ST_STOPPED;
       }
       // append the secondaries of this wave: one reservation, ranks from the lane mask
       const uint64_t sm = __ballot(spawn);
@@ -1171,7 +1274,7 @@ __device__ __forceinline__ void block_sum(double* vals, int nq, double* s_red) {
 enum {
   T1_NF = 0, T1_VX, T1_VY, T1_VZ, T1_AG, T1_AD, T1_ZH, T1_GF, T1_DF,
   T1_KREAL, T1_KNULL, T1_KFORB, T1_KOVER, T1_NATT, T1_NSTUCK, T1_NCREATED, T1_GALL, T1_DALL,
-  T1_SE, T1_SEP, T1_NK, T1_PE, T1_PEP, T1_NREC
+  T1_SE, T1_SEP, T1_NK, T1_PE, T1_PEP, T1_NREC, T1_KFAIL
 };
 // pass-2 accumulator indices
 enum {
@@ -1196,6 +1299,7 @@ __global__ void __launch_bounds__(kTallyThreads) k_tally1(const InstanceDesc* __
     a[T1_KREAL] += kr;
     a[T1_KNULL] += static_cast<double>(r.n_null);
     a[T1_KFORB] += static_cast<double>(r.n_forbidden);
+    a[T1_KFAIL] += static_cast<double>(r.n_fail);
     a[T1_KOVER] += static_cast<double>(r.n_over);
     a[T1_NATT] += (r.flags & 2u) ? 1.0 : 0.0;
     a[T1_NSTUCK] += (r.flags & 4u) ? 1.0 : 0.0;
@@ -1339,13 +1443,15 @@ __global__ void k_tally_final(const InstanceDesc* __restrict__ descs, const doub
   T.eta = mk_stat(a[T1_AD] / nf, b[T2_AD], nf);
   T.alpha_rate = a[T1_GF] / a[T1_ZH];
   T.eta_rate = a[T1_DF] / a[T1_ZH];
-  const double trials = kreal + a[T1_KNULL] + a[T1_KFORB];
+  // efficiency (section "Trial frequency strategies"): real / (real + null + fail), with
+  // forbidden picks counted as null trials
+  const double trials = kreal + a[T1_KNULL] + a[T1_KFORB] + a[T1_KFAIL];
   T.efficiency = kreal / trials;
   T.majorant = d.majorant;
   T.n_real = static_cast<int64_t>(kreal);
   T.n_null = static_cast<int64_t>(a[T1_KNULL]);
   T.n_forbidden = static_cast<int64_t>(a[T1_KFORB]);
-  T.n_fail = 0;
+  T.n_fail = static_cast<int64_t>(a[T1_KFAIL]);
   T.n_over = static_cast<int64_t>(a[T1_KOVER]);
   T.n_electrons = static_cast<int64_t>(a[T1_NREC]);
   T.n_finished = static_cast<int64_t>(nf);
@@ -1359,19 +1465,25 @@ __global__ void k_tally_final(const InstanceDesc* __restrict__ descs, const doub
 }
 
 template <typename R, bool HB, bool TR>
-void* dummy_fn() { return reinterpret_cast<void*>(&k_swarm_dummy<R, HB, TR>); }
+void* dummy_fn(bool var) {
+  return var ? reinterpret_cast<void*>(&k_swarm_dummy<R, HB, TR, true>)
+             : reinterpret_cast<void*>(&k_swarm_dummy<R, HB, TR, false>);
+}
 template <typename R, bool HB, bool TR>
-void* real_fn() { return reinterpret_cast<void*>(&k_swarm_real<R, HB, TR>); }
+void* real_fn(bool var) {
+  return var ? reinterpret_cast<void*>(&k_swarm_real<R, HB, TR, true>)
+             : reinterpret_cast<void*>(&k_swarm_real<R, HB, TR, false>);
+}
 
-void* pick_kernel(int precision, bool has_b, bool trace, bool real) {
+void* pick_kernel(int precision, bool has_b, bool trace, bool real, bool var) {
   const bool f32 = precision == SWARM_FP32_MIXED;
 #define SW_PICK(R)                                                                            \
   if (real) {                                                                                 \
-    if (has_b) return trace ? real_fn<R, true, true>() : real_fn<R, true, false>();           \
-    return trace ? real_fn<R, false, true>() : real_fn<R, false, false>();                    \
+    if (has_b) return trace ? real_fn<R, true, true>(var) : real_fn<R, true, false>(var);     \
+    return trace ? real_fn<R, false, true>(var) : real_fn<R, false, false>(var);              \
   }                                                                                           \
-  if (has_b) return trace ? dummy_fn<R, true, true>() : dummy_fn<R, true, false>();           \
-  return trace ? dummy_fn<R, false, true>() : dummy_fn<R, false, false>();
+  if (has_b) return trace ? dummy_fn<R, true, true>(var) : dummy_fn<R, true, false>(var);     \
+  return trace ? dummy_fn<R, false, true>(var) : dummy_fn<R, false, false>(var);
   if (f32) { SW_PICK(float) }
   SW_PICK(double)
 #undef SW_PICK
@@ -1413,18 +1525,18 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s) {
 
 hipError_t launch_swarm_dummy(const InstanceDesc* d_desc, const WorkItem* d_items, int32_t n_items,
                               int32_t* d_item_counter, int precision, bool has_b, bool trace,
-                              int block_size, int grid, int pending_trigger, size_t lds_bytes,
+                              bool var, int block_size, int grid, int pending_trigger, size_t lds_bytes,
                               int ch_off, hipStream_t s) {
-  void* fn = pick_kernel(precision, has_b, trace, false);
+  void* fn = pick_kernel(precision, has_b, trace, false, var);
   void* args[] = {const_cast<InstanceDesc**>(&d_desc), const_cast<WorkItem**>(&d_items), &n_items,
                   &d_item_counter, &pending_trigger, &ch_off};
   return hipLaunchKernel(fn, dim3(grid), dim3(block_size), args, lds_bytes, s);
 }
 
 hipError_t launch_swarm_real(const InstanceDesc* d_desc, int precision, bool has_b, bool trace,
-                             int block_size, int grid, int pending_trigger, size_t lds_bytes,
+                             bool var, int block_size, int grid, int pending_trigger, size_t lds_bytes,
                              int ch_off, hipStream_t s) {
-  void* fn = pick_kernel(precision, has_b, trace, true);
+  void* fn = pick_kernel(precision, has_b, trace, true, var);
   void* args[] = {const_cast<InstanceDesc**>(&d_desc), &pending_trigger, &ch_off};
   return hipLaunchKernel(fn, dim3(grid), dim3(block_size), args, lds_bytes, s);
 }
@@ -1442,10 +1554,10 @@ hipError_t launch_tallies(const InstanceDesc* d_desc, const TallyTile* d_tiles, 
   return hipGetLastError();
 }
 
-int swarm_kernel_max_blocks_per_cu(int precision, bool has_b, bool trace, bool real, int block_size,
+int swarm_kernel_max_blocks_per_cu(int precision, bool has_b, bool trace, bool real, bool var, int block_size,
                                    size_t lds_bytes) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pick_kernel(precision, has_b, trace, real),
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pick_kernel(precision, has_b, trace, real, var),
                                                    block_size, lds_bytes) != hipSuccess)
     return 1;
   return n > 0 ? n : 1;

@@ -223,7 +223,7 @@ void scheduler(swarm_server* s) {
     descs.clear();
     std::vector<int64_t> ne, nc;
     int G = 0, n_ch = 0;
-    bool magnetic = false;
+    bool magnetic = false, variable = false;
     for (auto& r : act) {
       InstanceDesc d = r->h->desc;
       d.quantum = static_cast<uint32_t>(std::min<int64_t>(q, 0xffffffffLL));
@@ -233,6 +233,7 @@ void scheduler(swarm_server* s) {
       G = std::max(G, d.G);
       n_ch = std::max(n_ch, d.nc);
       magnetic |= r->h->has_b;
+      variable |= d.trial_strategy == SWARM_TRIAL_VARIABLE;
       r->epochs += 1;
     }
     const swarm_launch_opts o = resolve_opts(&s->p.opts, s->p.precision);
@@ -248,10 +249,10 @@ void scheduler(swarm_server* s) {
                  (e = launch_fill_u32(reinterpret_cast<uint32_t*>(item_ctr), 0u, 1, s->compute)) == hipSuccess &&
                  (e = hipEventRecord(ev0, s->compute)) == hipSuccess;
     if (ok) {
-      const int per_cu = swarm_kernel_max_blocks_per_cu(s->p.precision, magnetic, false, false, o.block_size, lds);
+      const int per_cu = swarm_kernel_max_blocks_per_cu(s->p.precision, magnetic, false, false, variable, o.block_size, lds);
       const int grid = std::max(1, std::min<int>(static_cast<int>(items.size()), device_info().n_cu * per_cu));
       ok = (e = launch_swarm_dummy(static_cast<const InstanceDesc*>(s->descs.p), static_cast<const WorkItem*>(s->items.p),
-                                   static_cast<int32_t>(items.size()), item_ctr, s->p.precision, magnetic, false,
+                                   static_cast<int32_t>(items.size()), item_ctr, s->p.precision, magnetic, false, variable,
                                    o.block_size, grid, o.pending_trigger, lds, ch_off, s->compute)) == hipSuccess &&
            (e = hipEventRecord(ev1, s->compute)) == hipSuccess;
     }

@@ -3,7 +3,8 @@ import math
 
 import numpy as np
 
-INT_FIELDS = ["id", "flags", "k_start", "k_end", "G", "D", "n_forbidden", "n_over", "n_null", "blocks"]
+INT_FIELDS = ["id", "flags", "k_start", "k_end", "G", "D", "n_forbidden", "n_over", "n_fail", "n_null",
+              "blocks"]
 FLOAT_FIELDS = ["t", "sum_eps", "sum_epsp"]
 
 
