@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--collisions", type=int, default=20_000)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-variable", action="store_true",
+                    help="skip the leg with the variable trial frequency")
     ap.add_argument("--serve-rate", type=float, default=5.0)
     ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--autotune", action="store_true",
@@ -171,6 +173,41 @@ def serve(sw, args):
         sw.swarm_server_destroy(srv)
 
 
+def variable_leg(sw, args, cfgs, jobs, opts, tall_const, ms_const, zeta=0.25, grace=5000):
+    """The same batched FP32 step with the paper's variable trial frequency (per-electron
+    nu' = (1 + zeta) nu(eps), renewed every `grace` trials and after fails): throughput,
+    efficiency, fails, and how far its tallies move from the exact constant-frequency run."""
+    hv = [sw.Swarm.from_config(c.scaled(trial_strategy=1, trial_zeta=zeta, trial_grace=grace),
+                               sw.SWARM_FP32_MIXED) for c in cfgs]
+    b = sw.swarm_batch_create([h.h for h in hv], jobs, opts)
+    try:
+        sw.swarm_batch_launch(b)
+        sw.swarm_batch_wait(b)
+        ms = []
+        for _ in range(max(1, args.steps)):
+            sw.swarm_batch_launch(b)
+            ms.append(sw.swarm_batch_wait(b))
+        tv = [sw.swarm_batch_tallies(b, i) for i in range(len(cfgs))]
+    finally:
+        sw.swarm_batch_destroy(b)
+    avg = sum(ms) / len(ms)
+    real = sum(t["n_real"] for t in tv)
+    trials = sum(t["n_real"] + t["n_null"] + t["n_forbidden"] + t["n_fail"] for t in tv)
+    keys = ["W", "mean_energy", "mean_energy_after", "D", "DL", "DT", "alpha"]
+    agree = sum(agreement(a, c, keys) for a, c in zip(tv, tall_const))
+    shift = {}
+    for k in keys:
+        rel = [(a[k][0] - c[k][0]) / abs(c[k][0]) for a, c in zip(tv, tall_const)
+               if c[k][0] != 0 and math.isfinite(a[k][0]) and math.isfinite(c[k][0])]
+        shift[k] = {"min": min(rel), "max": max(rel)} if rel else None
+    return {"value": real / (avg * 1e-3), "unit": "real collisions/s", "device_ms_per_step": avg,
+            "zeta": zeta, "grace": grace, "efficiency": real / trials,
+            "fails_per_real": sum(t["n_fail"] for t in tv) / real,
+            "speedup_vs_constant": ms_const / avg,
+            "within_tolerance_of_constant": f"{agree}/{len(keys) * len(cfgs)}",
+            "rel_shift_vs_constant": shift}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -216,7 +253,7 @@ def main():
     tall32 = [sw.swarm_batch_tallies(batch, i) for i in range(len(cfgs))]
     sw.swarm_batch_destroy(batch)
     real_per_step = sum(t["n_real"] for t in tall32)
-    trials_per_step = sum(t["n_real"] + t["n_null"] + t["n_forbidden"] for t in tall32)
+    trials_per_step = sum(t["n_real"] + t["n_null"] + t["n_forbidden"] + t["n_fail"] for t in tall32)
     value = real_per_step * args.steps / wall
     avg_ms = sum(dev_ms) / len(dev_ms)
     ops = trials_per_step * OPS_PER_TRIAL + real_per_step * OPS_PER_REAL
@@ -238,6 +275,9 @@ def main():
                      "kernel": "k_swarm_dummy<float,false,false>",
                      "ops_per_trial": OPS_PER_TRIAL, "ops_per_real": OPS_PER_REAL},
     }
+    if not args.no_variable:
+        out["fp32_batched_variable"] = variable_leg(sw, args, cfgs, jobs, opts, tall32, avg_ms)
+        log(args, "variable trial frequency", out["fp32_batched_variable"])
     if not args.no_fp64:
         # the plain FP64 form: one swarm per launch, default launch shape
         h64 = [sw.Swarm.from_config(c, sw.SWARM_FP64) for c in cfgs]

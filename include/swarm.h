@@ -234,6 +234,9 @@ typedef struct {
   int32_t chunk;           /* electrons per work item (multiple of block_size) */
   int32_t pending_trigger; /* lanes waiting on a real collision before the wave serves them (1..64) */
   int32_t use_graph;       /* capture the launch in a hipGraph and replay it */
+  int32_t service_waves;   /* 0: every wave serves its own candidates; n >= 1: pooled schedule,
+                              n waves of each work-group serve the candidates of the others at
+                              full width (n < block_size/64; traced runs use the per-wave one) */
 } swarm_launch_opts;
 
 typedef struct swarm_batch* swarm_batch_t;

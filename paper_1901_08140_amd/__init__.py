@@ -73,7 +73,8 @@ class swarm_job(ctypes.Structure):
 
 
 class swarm_launch_opts(ctypes.Structure):
-    _fields_ = [("block_size", _i32), ("chunk", _i32), ("pending_trigger", _i32), ("use_graph", _i32)]
+    _fields_ = [("block_size", _i32), ("chunk", _i32), ("pending_trigger", _i32), ("use_graph", _i32),
+                ("service_waves", _i32)]
 
 
 class swarm_server_params(ctypes.Structure):

@@ -57,12 +57,16 @@ DeviceInfo& device_info() {
 
 // Dynamic LDS of the swarm kernels: the total-rate pairs of the G grid nodes plus one
 // padding entry in front, then (16-byte aligned) the nc channel descriptors.
-int lds_channel_offset(int precision, int G) {
+// With the pooled schedule the candidate pool (64 slots per service wave) follows.
+LdsLayout lds_layout(int precision, int G, int nc, int service_waves) {
+  auto al = [](size_t n) { return (n + 15) & ~static_cast<size_t>(15); };
+  LdsLayout l;
   const size_t b = static_cast<size_t>(G + 1) * (precision == SWARM_FP32_MIXED ? sizeof(float2) : sizeof(double2));
-  return static_cast<int>((b + 15) & ~static_cast<size_t>(15));
-}
-size_t lds_bytes_for(int precision, int G, int nc) {
-  return static_cast<size_t>(lds_channel_offset(precision, G)) + static_cast<size_t>(nc) * sizeof(ChannelDev);
+  l.ch_off = static_cast<int>(al(b));
+  l.pool_off = static_cast<int>(al(static_cast<size_t>(l.ch_off) + static_cast<size_t>(nc) * sizeof(ChannelDev)));
+  l.bytes = static_cast<size_t>(l.pool_off);
+  if (service_waves > 0) l.bytes += static_cast<size_t>(64 * service_waves) * swarm_pool_slot_bytes(precision);
+  return l;
 }
 
 DevBuf::~DevBuf() { reset(); }
@@ -243,6 +247,7 @@ swarm_launch_opts resolve_opts(const swarm_launch_opts* o, int precision) {
   r.block_size = std::max(64, std::min(1024, (r.block_size / 64) * 64));
   r.chunk = std::max(r.block_size, (r.chunk / r.block_size) * r.block_size);
   r.pending_trigger = std::max(1, std::min(64, r.pending_trigger));
+  r.service_waves = o ? std::max(0, std::min(r.block_size / 64 - 1, o->service_waves)) : 0;
   return r;
 }
 
@@ -460,11 +465,13 @@ swarm_status swarm_run(swarm_t h, int64_t n_electrons, int64_t n_collisions, uin
   if ((e = hipMemcpyAsync(d.ctr, &rc, sizeof(rc), hipMemcpyHostToDevice, s)) != hipSuccess) return hip_fail(e, "counters");
   if ((e = sync_desc_to_device(h)) != hipSuccess) return hip_fail(e, "descriptor");
   const swarm_launch_opts& o = h->opts;
-  const size_t lds = lds_bytes_for(d.precision, d.G, d.nc);
-  const int ch_off = lds_channel_offset(d.precision, d.G);
+  const int svc = trace || real ? 0 : o.service_waves;
+  const LdsLayout ll = lds_layout(d.precision, d.G, d.nc, svc);
+  const size_t lds = ll.bytes;
+  const int ch_off = ll.ch_off;
   DeviceInfo& dev = device_info();
   const bool var = d.trial_strategy == SWARM_TRIAL_VARIABLE;
-  const int per_cu = swarm_kernel_max_blocks_per_cu(d.precision, h->has_b, trace, real, var, o.block_size, lds);
+  const int per_cu = swarm_kernel_max_blocks_per_cu(d.precision, h->has_b, trace, real, var, svc, o.block_size, lds);
   if ((e = hipEventRecord(h->ev[0], s)) != hipSuccess) return hip_fail(e, "event");
   if (!real) {
     // enough work items to give every resident work-group several of them
@@ -482,7 +489,8 @@ swarm_status swarm_run(swarm_t h, int64_t n_electrons, int64_t n_collisions, uin
     if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(d_ctr), 0u, 1, s)) != hipSuccess) return hip_fail(e, "item counter");
     const int grid = std::max(1, std::min<int>(static_cast<int>(items.size()), dev.n_cu * per_cu));
     if ((e = launch_swarm_dummy(h->d_desc, static_cast<const WorkItem*>(h->items.p), static_cast<int32_t>(items.size()),
-                                d_ctr, d.precision, h->has_b, trace, var, o.block_size, grid, o.pending_trigger, lds, ch_off, s)) != hipSuccess)
+                                d_ctr, d.precision, h->has_b, trace, var, svc, o.block_size, grid, o.pending_trigger, lds, ch_off,
+                                ll.pool_off, s)) != hipSuccess)
       return hip_fail(e, "swarm kernel launch");
   } else {
     const int64_t want = (n_electrons + o.block_size - 1) / o.block_size;

@@ -42,8 +42,12 @@ struct TallyPlan {
 
 swarm_status fail(swarm_status st, const char* fmt, ...);
 swarm_status hip_fail(hipError_t e, const char* what);
-int lds_channel_offset(int precision, int G);
-size_t lds_bytes_for(int precision, int G, int nc);
+// Dynamic LDS of a swarm launch: rate pairs, channel descriptors, candidate pool.
+struct LdsLayout {
+  size_t bytes;
+  int ch_off, pool_off;
+};
+LdsLayout lds_layout(int precision, int G, int nc, int service_waves);
 void make_items(const std::vector<int64_t>& n_e, const std::vector<int64_t>& n_c, int64_t chunk,
                 std::vector<WorkItem>& items);
 swarm_launch_opts resolve_opts(const swarm_launch_opts* o, int precision);

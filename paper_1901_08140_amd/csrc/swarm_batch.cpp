@@ -26,7 +26,7 @@ struct swarm_batch {
   swarm_launch_opts opts{};
   int grid = 1;
   size_t lds = 0;
-  int ch_off = 0;
+  int ch_off = 0, pool_off = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -57,7 +57,8 @@ hipError_t enqueue(swarm_batch* b) {
   if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(item_counter(b)), 0u, 1, b->stream)) != hipSuccess) return e;
   if ((e = launch_swarm_dummy(static_cast<const InstanceDesc*>(b->descs.p), static_cast<const WorkItem*>(b->items.p),
                               static_cast<int32_t>(b->h_items.size()), item_counter(b), b->precision, b->magnetic,
-                              false, b->variable, b->opts.block_size, b->grid, b->opts.pending_trigger, b->lds, b->ch_off, b->stream)) != hipSuccess)
+                              false, b->variable, b->opts.service_waves, b->opts.block_size, b->grid,
+                              b->opts.pending_trigger, b->lds, b->ch_off, b->pool_off, b->stream)) != hipSuccess)
     return e;
   return b->tally.launch(static_cast<const InstanceDesc*>(b->descs.p), b->stream);
 }
@@ -130,9 +131,12 @@ swarm_status swarm_batch_create(swarm_t* handles, const swarm_job* jobs, int32_t
                           b->stream)) != hipSuccess)
     return hip_fail(e, "uploading batch");
   if ((e = b->tally.prepare(ne, b->stream)) != hipSuccess) return hip_fail(e, "tally plan");
-  b->lds = lds_bytes_for(b->precision, G, n_ch);
-  b->ch_off = lds_channel_offset(b->precision, G);
-  const int per_cu = swarm_kernel_max_blocks_per_cu(b->precision, b->magnetic, false, false, b->variable, b->opts.block_size, b->lds);
+  const LdsLayout ll = lds_layout(b->precision, G, n_ch, b->opts.service_waves);
+  b->lds = ll.bytes;
+  b->ch_off = ll.ch_off;
+  b->pool_off = ll.pool_off;
+  const int per_cu = swarm_kernel_max_blocks_per_cu(b->precision, b->magnetic, false, false, b->variable,
+                                                    b->opts.service_waves, b->opts.block_size, b->lds);
   b->grid = std::max(1, std::min<int>(static_cast<int>(b->h_items.size()), device_info().n_cu * per_cu));
   if ((e = hipStreamSynchronize(b->stream)) != hipSuccess) return hip_fail(e, "uploading batch");
   if (b->opts.use_graph) {

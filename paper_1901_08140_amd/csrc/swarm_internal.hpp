@@ -19,10 +19,12 @@ constexpr uint32_t kMaxBlocks = 0x7fffffffu;   // per-electron cap on trial bloc
 // Lane states of the swarm kernels.
 // ACTIVE: drawing trials; PENDING: holds a real-collision candidate and draws its
 // scattering block in the next trial pass; READY: candidate and scattering words ready;
-// IDLE: needs an electron; WAIT: holds a secondary-queue slot; STOPPED: must store its
-// record or state; DONE: no more work.
+// IDLE: needs an electron; WAIT: holds a secondary-queue slot (or, in the pooled
+// schedule, has its candidate in the work-group pool); CAND: pooled schedule, holds a
+// candidate not yet in the pool; STOPPED: must store its record or state; DONE: no more
+// work.
 enum : int { ST_ACTIVE = 0, ST_PENDING = 1, ST_IDLE = 2, ST_WAIT = 3, ST_DONE = 4, ST_STOPPED = 5,
-             ST_READY = 6 };
+             ST_READY = 6, ST_CAND = 7 };
 
 // Per-channel constants built on the device from the raw inputs.
 struct ChannelDev {
@@ -151,10 +153,12 @@ hipError_t launch_build(InstanceDesc* d_desc, const InstanceDesc& h_desc, hipStr
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_mark_empty(swarm_record* r, int64_t n, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
+// service_waves > 0 (and no trace): the pooled schedule, pool at LDS offset pool_off.
 hipError_t launch_swarm_dummy(const InstanceDesc* d_desc, const WorkItem* d_items, int32_t n_items,
                               int32_t* d_item_counter, int precision, bool has_b, bool trace,
-                              bool var, int block_size, int grid, int pending_trigger, size_t lds_bytes,
-                              int ch_off, hipStream_t s);
+                              bool var, int service_waves, int block_size, int grid, int pending_trigger,
+                              size_t lds_bytes, int ch_off, int pool_off, hipStream_t s);
+size_t swarm_pool_slot_bytes(int precision);
 hipError_t launch_swarm_real(const InstanceDesc* d_desc, int precision, bool has_b, bool trace,
                              bool var, int block_size, int grid, int pending_trigger, size_t lds_bytes,
                              int ch_off, hipStream_t s);
@@ -162,7 +166,8 @@ hipError_t launch_tallies(const InstanceDesc* d_desc, const TallyTile* d_tiles, 
                           const int32_t* d_tile_base, const int64_t* d_nrec, int32_t n_inst,
                           double* d_part1, double* d_part2, double* d_tot1,
                           swarm_tallies_t* d_out, hipStream_t s);
-int swarm_kernel_max_blocks_per_cu(int precision, bool has_b, bool trace, bool real, bool var, int block_size,
+int swarm_kernel_max_blocks_per_cu(int precision, bool has_b, bool trace, bool real, bool var,
+                                   int service_waves, int block_size,
                                    size_t lds_bytes);
 
 }  // namespace swarm_impl

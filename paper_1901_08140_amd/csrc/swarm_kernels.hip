@@ -1088,6 +1088,284 @@ __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restr
 }
 
 // ---------------------------------------------------------------------------------------
+// Pooled dummy-mode kernel.  The same per-electron work as k_swarm_dummy, scheduled so that
+// collision code runs at full wave width.  A work-group has trial waves and service waves.
+// A round has three barriers.  Before the first, the owning lanes take back the electrons
+// served in the previous round (so no slot is reused before it has been read).  Between the
+// first and the second each trial wave runs one random-number block on its electrons, and
+// lanes that found a real-collision candidate copy their state into a pool in LDS (one slot
+// per candidate, at most 64 per service wave; the others retry in the next round).  Between
+// the second and the third the service waves draw the scattering words, serve the pool, one
+// full wave per 64 candidates, and write the outcome back into the slots.  Only the schedule differs from k_swarm_dummy:
+// the streams and the per-electron arithmetic are the same, so the results are identical.
+// ---------------------------------------------------------------------------------------
+
+// Pool layout: structure of arrays over `cap` slots (doubles, then working-precision
+// values, then 32-bit words), so that consecutive lanes touch consecutive LDS words.
+enum : int { PD_RX = 0, PD_RY, PD_RZ, PD_T, PD_SE, PD_SEP, kPoolD };
+enum : int { PR_VX = 0, PR_VY, PR_VZ, PR_TT, PR_EPS, PR_X, PR_W, PR_NUP, kPoolR };
+enum : int { PU_GI = 0, PU_SUB, PU_NFIRST, PU_NFORB, PU_NOVER, PU_G, PU_D, PU_K, PU_KSTOP, PU_FLAGS,
+             PU_STATE, PU_GRACE, PU_NFAIL, PU_IDLO, PU_IDHI, kPoolU };
+
+template <typename R>
+struct Pool {
+  double* d;
+  R* r;
+  uint32_t* u;
+  int cap;
+  __device__ double& D(int f, int s) const { return d[f * cap + s]; }
+  __device__ R& V(int f, int s) const { return r[f * cap + s]; }
+  __device__ uint32_t& U(int f, int s) const { return u[f * cap + s]; }
+};
+
+// Owner -> pool: the candidate and everything the collision code reads or updates.
+template <typename R, bool VAR>
+__device__ __forceinline__ void pool_put(const Pool<R>& P, int s, const Lane<R>& L) {
+  P.D(PD_RX, s) = L.rx; P.D(PD_RY, s) = L.ry; P.D(PD_RZ, s) = L.rz; P.D(PD_T, s) = L.t;
+  P.D(PD_SE, s) = L.se; P.D(PD_SEP, s) = L.sep;
+  P.V(PR_VX, s) = L.vx; P.V(PR_VY, s) = L.vy; P.V(PR_VZ, s) = L.vz; P.V(PR_TT, s) = L.T;
+  P.V(PR_EPS, s) = L.p_eps; P.V(PR_X, s) = L.p_x; P.V(PR_W, s) = L.p_w;
+  P.U(PU_GI, s) = static_cast<uint32_t>(L.p_gi); P.U(PU_SUB, s) = L.p_sub;
+  P.U(PU_NFIRST, s) = L.nfirst; P.U(PU_NFORB, s) = L.nforb; P.U(PU_NOVER, s) = L.nover;
+  P.U(PU_G, s) = L.G; P.U(PU_D, s) = L.D; P.U(PU_K, s) = L.k; P.U(PU_KSTOP, s) = L.k_stop;
+  P.U(PU_FLAGS, s) = L.flags; P.U(PU_NFAIL, s) = L.nfail;
+  P.U(PU_IDLO, s) = static_cast<uint32_t>(L.id); P.U(PU_IDHI, s) = static_cast<uint32_t>(L.id >> 32);
+  if constexpr (VAR) {
+    P.V(PR_NUP, s) = L.nup;
+    P.U(PU_GRACE, s) = L.grace;
+  }
+}
+
+// Per-lane trial frequency from a stored nu' (at the cap: the constant strategy's values).
+template <typename R, bool VAR>
+__device__ __forceinline__ void restore_trial_frequency(Lane<R>& L, const Consts<R>& C, R v) {
+  if constexpr (VAR) {
+    if (C.variable && v < C.nup) apply_trial_frequency(L, C, v);
+    else constant_trial_frequency(L, C);
+  }
+}
+
+// Service lane <- pool: a lane state complete enough for real_collision.
+template <typename R, bool HB, bool VAR>
+__device__ __forceinline__ void pool_take(const Pool<R>& P, int s, Lane<R>& S, const Consts<R>& C) {
+  S.rx = P.D(PD_RX, s); S.ry = P.D(PD_RY, s); S.rz = P.D(PD_RZ, s); S.t = P.D(PD_T, s);
+  S.se = P.D(PD_SE, s); S.sep = P.D(PD_SEP, s);
+  S.vx = P.V(PR_VX, s); S.vy = P.V(PR_VY, s); S.vz = P.V(PR_VZ, s); S.T = P.V(PR_TT, s);
+  S.p_eps = P.V(PR_EPS, s); S.p_x = P.V(PR_X, s); S.p_w = P.V(PR_W, s);
+  S.p_gi = static_cast<int>(P.U(PU_GI, s)); S.p_sub = P.U(PU_SUB, s);
+  S.nfirst = P.U(PU_NFIRST, s); S.nforb = P.U(PU_NFORB, s); S.nover = P.U(PU_NOVER, s);
+  S.G = P.U(PU_G, s); S.D = P.U(PU_D, s); S.k = P.U(PU_K, s); S.k_stop = P.U(PU_KSTOP, s);
+  S.flags = P.U(PU_FLAGS, s); S.nfail = P.U(PU_NFAIL, s);
+  S.id = static_cast<uint64_t>(P.U(PU_IDLO, s)) | (static_cast<uint64_t>(P.U(PU_IDHI, s)) << 32);
+  if constexpr (VAR) {
+    restore_trial_frequency<R, VAR>(S, C, P.V(PR_NUP, s));
+    S.grace = P.U(PU_GRACE, s);
+  }
+  S.trace_slot = -1;
+  S.n_ev = 0;
+  set_anchor<R, HB>(S, C);
+  // the scattering block k of this electron (the stream the per-wave schedule draws while
+  // the candidate waits)
+  S.sh = draw(C.key, S.id, TAG_SCAT_HI, S.k);
+  if constexpr (sizeof(R) == 8) S.sl = draw(C.key, S.id, TAG_SCAT_LO, S.k);
+  else S.sl = W4{0, 0, 0, 0};
+}
+
+// Service lane -> pool: the outcome.
+template <typename R, bool VAR>
+__device__ __forceinline__ void pool_give(const Pool<R>& P, int s, const Lane<R>& S) {
+  P.D(PD_RX, s) = S.rx; P.D(PD_RY, s) = S.ry; P.D(PD_RZ, s) = S.rz; P.D(PD_T, s) = S.t;
+  P.D(PD_SE, s) = S.se; P.D(PD_SEP, s) = S.sep;
+  P.V(PR_VX, s) = S.vx; P.V(PR_VY, s) = S.vy; P.V(PR_VZ, s) = S.vz; P.V(PR_TT, s) = S.T;
+  P.U(PU_NFIRST, s) = S.nfirst; P.U(PU_NFORB, s) = S.nforb; P.U(PU_NOVER, s) = S.nover;
+  P.U(PU_G, s) = S.G; P.U(PU_D, s) = S.D; P.U(PU_K, s) = S.k; P.U(PU_FLAGS, s) = S.flags;
+  P.U(PU_STATE, s) = static_cast<uint32_t>(S.state); P.U(PU_NFAIL, s) = S.nfail;
+  if constexpr (VAR) {
+    P.V(PR_NUP, s) = S.nup;
+    P.U(PU_GRACE, s) = S.grace;
+  }
+}
+
+// Owner <- pool: take the served electron back.
+template <typename R, bool HB, bool VAR>
+__device__ __forceinline__ void pool_back(const Pool<R>& P, int s, Lane<R>& L, const Consts<R>& C) {
+  L.rx = P.D(PD_RX, s); L.ry = P.D(PD_RY, s); L.rz = P.D(PD_RZ, s); L.t = P.D(PD_T, s);
+  L.se = P.D(PD_SE, s); L.sep = P.D(PD_SEP, s);
+  L.vx = P.V(PR_VX, s); L.vy = P.V(PR_VY, s); L.vz = P.V(PR_VZ, s); L.T = P.V(PR_TT, s);
+  L.nfirst = P.U(PU_NFIRST, s); L.nforb = P.U(PU_NFORB, s); L.nover = P.U(PU_NOVER, s);
+  L.G = P.U(PU_G, s); L.D = P.U(PU_D, s); L.k = P.U(PU_K, s); L.flags = P.U(PU_FLAGS, s);
+  L.state = static_cast<int>(P.U(PU_STATE, s)); L.nfail = P.U(PU_NFAIL, s);
+  if constexpr (VAR) {
+    restore_trial_frequency<R, VAR>(L, C, P.V(PR_NUP, s));
+    L.grace = P.U(PU_GRACE, s);
+  }
+  set_anchor<R, HB>(L, C);
+}
+
+// One random-number block of an ACTIVE lane in the pooled schedule: a real candidate
+// leaves the lane in CAND (the scattering words are drawn by the service wave).
+template <typename R, bool HB, bool VAR>
+__device__ __forceinline__ void trial_block_pooled(Lane<R>& L, const Consts<R>& C,
+                                                   const typename Pair<R>::T* __restrict__ s_nu) {
+  if (L.block >= kMaxBlocks) {
+    L.flags |= 4u;
+    L.state = ST_STOPPED;
+    return;
+  }
+  const W4 h = draw_trial(C.key, L.pre_hi, L.block);
+  W4 l = {0, 0, 0, 0};
+  if constexpr (sizeof(R) == 8) l = draw_trial(C.key, L.pre_lo, L.block);
+  L.block += 1;
+  bool hit = one_trial<R, HB, VAR>(L, C, s_nu, h.x, h.y, l.x, l.y);
+  L.p_sub = 0;
+  if (!hit) {
+    hit = one_trial<R, HB, VAR>(L, C, s_nu, h.z, h.w, l.z, l.w);
+    L.p_sub = 1;
+  }
+  if (hit) L.state = ST_CAND;
+}
+
+template <typename R, bool HB, bool VAR>
+__global__ void __launch_bounds__(512) k_swarm_pooled(const InstanceDesc* __restrict__ descs,
+                                                      const WorkItem* __restrict__ items, int n_items,
+                                                      int* __restrict__ item_ctr, int n_service,
+                                                      int ch_off, int pool_off) {
+  using PT = typename Pair<R>::T;
+  extern __shared__ __align__(16) unsigned char smem[];
+  PT* s_nu = reinterpret_cast<PT*>(smem);
+  ChannelDev* s_ch = reinterpret_cast<ChannelDev*>(smem + ch_off);
+  __shared__ int s_item;
+  __shared__ int s_next;
+  __shared__ int s_ncand[2];   // pool slots asked for, by round parity
+  __shared__ int s_live[3];    // some electron of the item is not done, by round mod 3
+  const int wave = static_cast<int>(threadIdx.x) >> 6;
+  const int lane = static_cast<int>(threadIdx.x) & 63;
+  const int n_trial = static_cast<int>(blockDim.x >> 6) - n_service;
+  const bool server = wave >= n_trial;
+  Pool<R> P;
+  P.cap = 64 * n_service;
+  P.d = reinterpret_cast<double*>(smem + pool_off);
+  P.r = reinterpret_cast<R*>(P.d + kPoolD * P.cap);
+  P.u = reinterpret_cast<uint32_t*>(P.r + kPoolR * P.cap);
+  const uint64_t lane_lt = (1ull << lane) - 1ull;
+  int cur_inst = -1;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(item_ctr, 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
+    if (it >= n_items) break;
+    const WorkItem wi = items[it];
+    const int inst = __builtin_amdgcn_readfirstlane(wi.inst);
+    const InstanceDesc& d = descs[inst];
+    if (inst != cur_inst) {
+      const PT* src = reinterpret_cast<const PT*>(sizeof(R) == 8 ? static_cast<const void*>(d.nu64)
+                                                                 : static_cast<const void*>(d.nu32));
+      for (int g = threadIdx.x; g <= d.G; g += blockDim.x) {
+        PT q = src[g > 0 ? g - 1 : 0];
+        if (g == 0) q.y = 0;
+        s_nu[g] = q;
+      }
+      for (int c = threadIdx.x; c < d.nc; c += blockDim.x) s_ch[c] = d.chan[c];
+      cur_inst = inst;
+    }
+    if (threadIdx.x == 0) {
+      s_next = 0;
+      s_ncand[0] = s_ncand[1] = 0;
+      s_live[0] = s_live[1] = s_live[2] = 0;
+    }
+    __syncthreads();
+    Consts<R> C = load_consts<R>(d);
+    C.chan = s_ch;
+    if (server) {
+      // ---- service waves: two barriers per round, as the trial waves ----
+      for (int round = 0;; ++round) {
+        __syncthreads();
+        __syncthreads();
+        const int n = min(s_ncand[round & 1], P.cap);
+        if (threadIdx.x == n_trial * 64) {
+          s_ncand[(round + 1) & 1] = 0;
+          s_live[(round + 1) % 3] = 0;
+        }
+        const int s = (wave - n_trial) * 64 + lane;
+        if (s < n) {
+          Lane<R> S;
+          pool_take<R, HB, VAR>(P, s, S, C);
+          bool spawn;
+          ChildState child;
+          S.state = ST_ACTIVE;
+          if (real_collision<R, HB, false, false, VAR>(d, S, C, s_nu, &spawn, &child) == RC_STOP)
+            S.state = ST_STOPPED;
+          pool_give<R, VAR>(P, s, S);
+        }
+        __syncthreads();
+        if (s_live[round % 3] == 0) break;
+      }
+    } else {
+      // ---- trial waves ----
+      const int64_t count = wi.count;
+      Lane<R> L;
+      L.state = ST_IDLE;
+      L.trace_slot = -1;
+      L.n_ev = 0;
+      int slot = 0;
+      for (int round = 0;; ++round) {
+        if (L.state == ST_WAIT) pool_back<R, HB, VAR>(P, slot, L, C);   // served last round
+        if (L.state == ST_STOPPED) {
+          if (L.k >= C.n_coll || (L.flags & 4u)) {
+            if (L.k >= C.n_coll) L.flags |= 1u;
+            write_record(d, L);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&d.ctr->n_done), 1ull);
+            if (d.saved != nullptr) d.saved[L.rec].started = 2u;
+          } else {
+            save_state<R, VAR>(d, L, C, L.rec);
+          }
+          L.state = ST_IDLE;
+        }
+        if (L.state == ST_IDLE) {
+          const int e = atomicAdd(&s_next, 1);
+          if (e < count) {
+            const int64_t ei = wi.first + e;
+            const uint32_t started = d.saved != nullptr ? d.saved[ei].started : 0u;
+            if (started != 2u) {
+              L.rec = ei;
+              if (started == 1u) load_state<R, HB, VAR>(d, L, C, ei);
+              else init_primary<R, HB, VAR>(L, C, s_nu, static_cast<uint64_t>(ei));
+              L.k_stop = C.quantum ? min(C.n_coll, L.k + C.quantum) : C.n_coll;
+              L.state = ST_ACTIVE;
+            }
+          } else {
+            L.state = ST_DONE;
+          }
+        }
+        __syncthreads();      // every served electron is back: the pool slots are free
+        if (L.state == ST_ACTIVE) trial_block_pooled<R, HB, VAR>(L, C, s_nu);
+        // candidates into the pool: one LDS reservation per wave, ranks from the lane mask
+        const uint64_t m = __ballot(L.state == ST_CAND);
+        if (m != 0) {
+          const int leader = __ffsll(static_cast<long long>(m)) - 1;
+          int base = 0;
+          if (lane == leader) base = atomicAdd(&s_ncand[round & 1], __popcll(m));
+          base = __shfl(base, leader);
+          if (L.state == ST_CAND) {
+            const int s = base + static_cast<int>(__popcll(m & lane_lt));
+            if (s < P.cap) {
+              pool_put<R, VAR>(P, s, L);
+              slot = s;
+              L.state = ST_WAIT;
+            }
+          }
+        }
+        if (__ballot(L.state != ST_DONE) != 0 && lane == 0) s_live[round % 3] = 1;
+        __syncthreads();
+        __syncthreads();
+        if (s_live[round % 3] == 0) break;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------
 // Real-secondaries kernel (one instance).  Lanes take primaries from a global counter and
 // then secondaries from a queue.  A secondary is appended with one atomic per wave (ballot
 // of the ionising lanes, prefix rank from the lane mask) and published with a ready flag
@@ -1475,6 +1753,17 @@ void* real_fn(bool var) {
              : reinterpret_cast<void*>(&k_swarm_real<R, HB, TR, false>);
 }
 
+template <typename R, bool HB>
+void* pooled_fn(bool var) {
+  return var ? reinterpret_cast<void*>(&k_swarm_pooled<R, HB, true>)
+             : reinterpret_cast<void*>(&k_swarm_pooled<R, HB, false>);
+}
+
+void* pick_pooled(int precision, bool has_b, bool var) {
+  if (precision == SWARM_FP32_MIXED) return has_b ? pooled_fn<float, true>(var) : pooled_fn<float, false>(var);
+  return has_b ? pooled_fn<double, true>(var) : pooled_fn<double, false>(var);
+}
+
 void* pick_kernel(int precision, bool has_b, bool trace, bool real, bool var) {
   const bool f32 = precision == SWARM_FP32_MIXED;
 #define SW_PICK(R)                                                                            \
@@ -1523,10 +1812,22 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+size_t swarm_pool_slot_bytes(int precision) {
+  const size_t r = precision == SWARM_FP32_MIXED ? sizeof(float) : sizeof(double);
+  return kPoolD * sizeof(double) + kPoolR * r + kPoolU * sizeof(uint32_t);
+}
+
 hipError_t launch_swarm_dummy(const InstanceDesc* d_desc, const WorkItem* d_items, int32_t n_items,
                               int32_t* d_item_counter, int precision, bool has_b, bool trace,
-                              bool var, int block_size, int grid, int pending_trigger, size_t lds_bytes,
-                              int ch_off, hipStream_t s) {
+                              bool var, int service_waves, int block_size, int grid, int pending_trigger,
+                              size_t lds_bytes, int ch_off, int pool_off, hipStream_t s) {
+  if (service_waves > 0 && !trace) {
+    if (service_waves >= block_size / 64) return hipErrorInvalidValue;
+    void* fn = pick_pooled(precision, has_b, var);
+    void* args[] = {const_cast<InstanceDesc**>(&d_desc), const_cast<WorkItem**>(&d_items), &n_items,
+                    &d_item_counter, &service_waves, &ch_off, &pool_off};
+    return hipLaunchKernel(fn, dim3(grid), dim3(block_size), args, lds_bytes, s);
+  }
   void* fn = pick_kernel(precision, has_b, trace, false, var);
   void* args[] = {const_cast<InstanceDesc**>(&d_desc), const_cast<WorkItem**>(&d_items), &n_items,
                   &d_item_counter, &pending_trigger, &ch_off};
@@ -1554,10 +1855,12 @@ hipError_t launch_tallies(const InstanceDesc* d_desc, const TallyTile* d_tiles, 
   return hipGetLastError();
 }
 
-int swarm_kernel_max_blocks_per_cu(int precision, bool has_b, bool trace, bool real, bool var, int block_size,
-                                   size_t lds_bytes) {
+int swarm_kernel_max_blocks_per_cu(int precision, bool has_b, bool trace, bool real, bool var,
+                                   int service_waves, int block_size, size_t lds_bytes) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pick_kernel(precision, has_b, trace, real, var),
+  void* fn = service_waves > 0 && !trace && !real ? pick_pooled(precision, has_b, var)
+                                                  : pick_kernel(precision, has_b, trace, real, var);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn,
                                                    block_size, lds_bytes) != hipSuccess)
     return 1;
   return n > 0 ? n : 1;

@@ -242,18 +242,20 @@ void scheduler(swarm_server* s) {
     bool ok = (e = s->descs.ensure(descs.size() * sizeof(InstanceDesc))) == hipSuccess &&
               (e = s->items.ensure(items.size() * sizeof(WorkItem) + 256)) == hipSuccess;
     int32_t* item_ctr = ok ? reinterpret_cast<int32_t*>(static_cast<char*>(s->items.p) + items.size() * sizeof(WorkItem)) : nullptr;
-    const size_t lds = lds_bytes_for(s->p.precision, G, n_ch);
-    const int ch_off = lds_channel_offset(s->p.precision, G);
+    const LdsLayout ll = lds_layout(s->p.precision, G, n_ch, o.service_waves);
+    const size_t lds = ll.bytes;
     if (ok) ok = (e = hipMemcpyAsync(s->descs.p, descs.data(), descs.size() * sizeof(InstanceDesc), hipMemcpyHostToDevice, s->compute)) == hipSuccess &&
                  (e = hipMemcpyAsync(s->items.p, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, s->compute)) == hipSuccess &&
                  (e = launch_fill_u32(reinterpret_cast<uint32_t*>(item_ctr), 0u, 1, s->compute)) == hipSuccess &&
                  (e = hipEventRecord(ev0, s->compute)) == hipSuccess;
     if (ok) {
-      const int per_cu = swarm_kernel_max_blocks_per_cu(s->p.precision, magnetic, false, false, variable, o.block_size, lds);
+      const int per_cu = swarm_kernel_max_blocks_per_cu(s->p.precision, magnetic, false, false, variable,
+                                                        o.service_waves, o.block_size, lds);
       const int grid = std::max(1, std::min<int>(static_cast<int>(items.size()), device_info().n_cu * per_cu));
       ok = (e = launch_swarm_dummy(static_cast<const InstanceDesc*>(s->descs.p), static_cast<const WorkItem*>(s->items.p),
                                    static_cast<int32_t>(items.size()), item_ctr, s->p.precision, magnetic, false, variable,
-                                   o.block_size, grid, o.pending_trigger, lds, ch_off, s->compute)) == hipSuccess &&
+                                   o.service_waves, o.block_size, grid, o.pending_trigger, lds, ll.ch_off,
+                                   ll.pool_off, s->compute)) == hipSuccess &&
            (e = hipEventRecord(ev1, s->compute)) == hipSuccess;
     }
     // while the epoch runs, prepare the requests that arrived meanwhile
