@@ -217,19 +217,32 @@ hipError_t TallyPlan::launch(const InstanceDesc* d_descs, hipStream_t s) {
 
 // Work items of `chunk` electrons per instance, heaviest collision budgets first so that
 // the long items start early and the persistent grid drains evenly.
+// Work items: instances with the largest collision budgets first.  An item holds up to
+// `chunk` electrons; when `slots` (resident work-groups) is given, an instance's items are
+// cut smaller, down to one electron per lane (`block`), so that no item holds much more
+// than 1/slots of the launch's work (electrons x collisions) and a small launch still
+// spreads over the whole GPU.
 void make_items(const std::vector<int64_t>& n_e, const std::vector<int64_t>& n_c, int64_t chunk,
-                std::vector<WorkItem>& items) {
+                std::vector<WorkItem>& items, int64_t slots, int64_t block) {
   items.clear();
   std::vector<int> order(n_e.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = static_cast<int>(i);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n_c[a] > n_c[b]; });
+  double total = 0.0;
+  for (size_t i = 0; i < n_e.size(); ++i) total += static_cast<double>(n_e[i]) * static_cast<double>(n_c[i]);
   for (int i : order) {
-    for (int64_t f = 0; f < n_e[i]; f += chunk) {
+    int64_t ch = chunk;
+    if (slots > 0 && block > 0 && n_c[i] > 0) {
+      const double want = total / static_cast<double>(slots) / static_cast<double>(n_c[i]);
+      const int64_t w = (static_cast<int64_t>(std::min(want, 1e15)) + block - 1) / block * block;
+      ch = std::max(block, std::min(chunk, w));
+    }
+    for (int64_t f = 0; f < n_e[i]; f += ch) {
       WorkItem w;
       w.inst = i;
       w.pad = 0;
       w.first = f;
-      w.count = std::min<int64_t>(chunk, n_e[i] - f);
+      w.count = std::min<int64_t>(ch, n_e[i] - f);
       items.push_back(w);
     }
   }
@@ -480,7 +493,7 @@ swarm_status swarm_run(swarm_t h, int64_t n_electrons, int64_t n_collisions, uin
     chunk = ((chunk + o.block_size - 1) / o.block_size) * o.block_size;
     chunk = std::max<int64_t>(o.block_size, std::min<int64_t>(chunk, o.chunk));
     std::vector<WorkItem> items;
-    make_items({n_electrons}, {n_collisions}, chunk, items);
+    make_items({n_electrons}, {n_collisions}, chunk, items, 0, 0);
     if ((e = h->items.ensure(items.size() * sizeof(WorkItem) + 256)) != hipSuccess) return hip_fail(e, "work items");
     h->h_items = items;
     int32_t* d_ctr = reinterpret_cast<int32_t*>(static_cast<char*>(h->items.p) + items.size() * sizeof(WorkItem));

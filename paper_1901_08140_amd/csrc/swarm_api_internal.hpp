@@ -49,7 +49,7 @@ struct LdsLayout {
 };
 LdsLayout lds_layout(int precision, int G, int nc, int service_waves);
 void make_items(const std::vector<int64_t>& n_e, const std::vector<int64_t>& n_c, int64_t chunk,
-                std::vector<WorkItem>& items);
+                std::vector<WorkItem>& items, int64_t slots, int64_t block);
 swarm_launch_opts resolve_opts(const swarm_launch_opts* o, int precision);
 
 }  // namespace swarm_impl

@@ -123,7 +123,14 @@ swarm_status swarm_batch_create(swarm_t* handles, const swarm_job* jobs, int32_t
     ne.push_back(jobs[i].n_electrons);
     nc.push_back(jobs[i].n_collisions);
   }
-  make_items(ne, nc, b->opts.chunk, b->h_items);
+  const LdsLayout ll = lds_layout(b->precision, G, n_ch, b->opts.service_waves);
+  b->lds = ll.bytes;
+  b->ch_off = ll.ch_off;
+  b->pool_off = ll.pool_off;
+  const int per_cu = swarm_kernel_max_blocks_per_cu(b->precision, b->magnetic, false, false, b->variable,
+                                                    b->opts.service_waves, b->opts.block_size, b->lds);
+  const int64_t slots = static_cast<int64_t>(device_info().n_cu) * per_cu;
+  make_items(ne, nc, b->opts.chunk, b->h_items, slots, b->opts.block_size);
   if ((e = b->descs.ensure(n * sizeof(InstanceDesc))) != hipSuccess) return hip_fail(e, "descriptors");
   if ((e = b->items.ensure(b->h_items.size() * sizeof(WorkItem) + 256)) != hipSuccess) return hip_fail(e, "work items");
   if ((e = hipMemcpyAsync(b->descs.p, b->h_descs.data(), n * sizeof(InstanceDesc), hipMemcpyHostToDevice, b->stream)) != hipSuccess ||
@@ -131,12 +138,6 @@ swarm_status swarm_batch_create(swarm_t* handles, const swarm_job* jobs, int32_t
                           b->stream)) != hipSuccess)
     return hip_fail(e, "uploading batch");
   if ((e = b->tally.prepare(ne, b->stream)) != hipSuccess) return hip_fail(e, "tally plan");
-  const LdsLayout ll = lds_layout(b->precision, G, n_ch, b->opts.service_waves);
-  b->lds = ll.bytes;
-  b->ch_off = ll.ch_off;
-  b->pool_off = ll.pool_off;
-  const int per_cu = swarm_kernel_max_blocks_per_cu(b->precision, b->magnetic, false, false, b->variable,
-                                                    b->opts.service_waves, b->opts.block_size, b->lds);
   b->grid = std::max(1, std::min<int>(static_cast<int>(b->h_items.size()), device_info().n_cu * per_cu));
   if ((e = hipStreamSynchronize(b->stream)) != hipSuccess) return hip_fail(e, "uploading batch");
   if (b->opts.use_graph) {

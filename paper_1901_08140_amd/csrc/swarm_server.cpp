@@ -229,7 +229,7 @@ void scheduler(swarm_server* s) {
       d.quantum = static_cast<uint32_t>(std::min<int64_t>(q, 0xffffffffLL));
       descs.push_back(d);
       ne.push_back(r->n_e);
-      nc.push_back(r->n_c);
+      nc.push_back(std::min<int64_t>(q, r->n_c));   // this epoch's collisions per electron at most
       G = std::max(G, d.G);
       n_ch = std::max(n_ch, d.nc);
       magnetic |= r->h->has_b;
@@ -237,20 +237,20 @@ void scheduler(swarm_server* s) {
       r->epochs += 1;
     }
     const swarm_launch_opts o = resolve_opts(&s->p.opts, s->p.precision);
-    make_items(ne, nc, o.chunk, items);
+    const LdsLayout ll = lds_layout(s->p.precision, G, n_ch, o.service_waves);
+    const size_t lds = ll.bytes;
+    const int per_cu = swarm_kernel_max_blocks_per_cu(s->p.precision, magnetic, false, false, variable,
+                                                      o.service_waves, o.block_size, lds);
+    make_items(ne, nc, o.chunk, items, static_cast<int64_t>(device_info().n_cu) * per_cu, o.block_size);
     hipError_t e;
     bool ok = (e = s->descs.ensure(descs.size() * sizeof(InstanceDesc))) == hipSuccess &&
               (e = s->items.ensure(items.size() * sizeof(WorkItem) + 256)) == hipSuccess;
     int32_t* item_ctr = ok ? reinterpret_cast<int32_t*>(static_cast<char*>(s->items.p) + items.size() * sizeof(WorkItem)) : nullptr;
-    const LdsLayout ll = lds_layout(s->p.precision, G, n_ch, o.service_waves);
-    const size_t lds = ll.bytes;
     if (ok) ok = (e = hipMemcpyAsync(s->descs.p, descs.data(), descs.size() * sizeof(InstanceDesc), hipMemcpyHostToDevice, s->compute)) == hipSuccess &&
                  (e = hipMemcpyAsync(s->items.p, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, s->compute)) == hipSuccess &&
                  (e = launch_fill_u32(reinterpret_cast<uint32_t*>(item_ctr), 0u, 1, s->compute)) == hipSuccess &&
                  (e = hipEventRecord(ev0, s->compute)) == hipSuccess;
     if (ok) {
-      const int per_cu = swarm_kernel_max_blocks_per_cu(s->p.precision, magnetic, false, false, variable,
-                                                        o.service_waves, o.block_size, lds);
       const int grid = std::max(1, std::min<int>(static_cast<int>(items.size()), device_info().n_cu * per_cu));
       ok = (e = launch_swarm_dummy(static_cast<const InstanceDesc*>(s->descs.p), static_cast<const WorkItem*>(s->items.p),
                                    static_cast<int32_t>(items.size()), item_ctr, s->p.precision, magnetic, false, variable,
