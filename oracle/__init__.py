@@ -45,7 +45,8 @@ class _Channel(ctypes.Structure):
 
 class _Component(ctypes.Structure):
     _fields_ = [("mass_amu", ctypes.c_double), ("fraction", ctypes.c_double),
-                ("n_channels", ctypes.c_int32), ("channels", ctypes.POINTER(_Channel))]
+                ("n_channels", ctypes.c_int32), ("channels", ctypes.POINTER(_Channel)),
+                ("scattering", ctypes.c_int32), ("mt_over_el", ctypes.c_double)]
 
 
 class _Params(ctypes.Structure):
@@ -89,6 +90,10 @@ def lib():
             "or_move": (None, [vp, P(d), P(d), d, P(d), P(d)]),
             "or_energy_after": (d, [i32, d, d, d, d]),
             "or_const": (d, [i32]),
+            "or_xi_from_ratio": (d, [d]),
+            "or_mt_over_el_of_xi": (d, [d]),
+            "or_scatter_cos": (d, [i32, d, d, d]),
+            "or_rotate": (None, [P(d), d, d, P(d)]),
             "or_run": (vp, [vp, i64, i64, u64, i32, i64, P(u64), i32, i32, i64]),
             "or_run_status": (i32, [vp]),
             "or_run_count": (i64, [vp]),
@@ -137,6 +142,33 @@ def energy_after(kind, eps, eps_k, cos_t, mass_amu):
     return lib().or_energy_after(kind, eps, eps_k, cos_t, mass_amu)
 
 
+ISOTROPIC, SCREENED_COULOMB, CONSTANT_XI = 0, 1, 2
+
+
+def hartree_eV():
+    return lib().or_const(3)
+
+
+def xi_from_ratio(r):
+    return lib().or_xi_from_ratio(r)
+
+
+def mt_over_el_of_xi(xi):
+    return lib().or_mt_over_el_of_xi(xi)
+
+
+def scatter_cos(scattering, xi, eps_eV, u):
+    return lib().or_scatter_cos(scattering, xi, eps_eV, u)
+
+
+def rotate(d, cos_t, phi):
+    P = ctypes.POINTER(ctypes.c_double)
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    out = np.zeros(3)
+    lib().or_rotate(d.ctypes.data_as(P), cos_t, phi, out.ctypes.data_as(P))
+    return out
+
+
 class OracleRun:
     def __init__(self, records, events, status):
         self.records = records
@@ -175,6 +207,8 @@ class OracleModel:
             comps[ci].fraction = c.fraction
             comps[ci].n_channels = len(c.channels)
             comps[ci].channels = chs
+            comps[ci].scattering = int(getattr(c, "scattering", 0))
+            comps[ci].mt_over_el = float(getattr(c, "mt_over_el", 1.0))
         p = _Params(E_V_per_m, B_T, B_angle_rad, N_per_m3, T_K, init_energy_eV, secondaries,
                     grid_P, grid_emin, grid_emax, user_majorant, trial_strategy, trial_zeta,
                     trial_grace)

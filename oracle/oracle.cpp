@@ -16,9 +16,13 @@
 // elastic/inelastic energy formulas against exact two-body kinematics; the table
 // extension on power laws; the Maxwell-gas drift velocity eE/(m nu) and mean energy;
 // Drude drift with crossed B; diffusion and alpha/eta closed forms for constant rates;
-// channel-selection frequencies; the worked example's report identities.
+// channel-selection frequencies; the worked example's report identities; the variable trial
+// frequency's special cases (cap = constant method, constant rate, no field); anisotropic
+// scattering: quadrature of the sampled cos(theta) against sigma_mt/sigma_el and the
+// screened-Coulomb closed form, rotation geometry, the Maxwell drift eE/(m nu (1-<cos>)).
 // Parity unpinned by a closed form: diffusion magnitudes (sigma, sigma_L, sigma_T) and
-// tallies for the synthetic argon/CO2 tables; those rest on GPU-vs-oracle parity.
+// tallies for the synthetic argon/CO2 tables, and the fail sequences of the variable trial
+// frequency; those rest on GPU-vs-oracle parity.
 
 #include <algorithm>
 #include <atomic>
@@ -36,6 +40,7 @@ constexpr double kQe = 1.602176634e-19;     // C
 constexpr double kMe = 9.1093837015e-31;    // kg
 constexpr double kAmu = 1.66053906660e-27;  // kg
 constexpr double kPi = 3.14159265358979323846;
+constexpr double kHartreeEV = 27.211386245988;   // Hartree energy in eV (CODATA 2018)
 
 enum Kind { ELASTIC = 0, EXCITATION = 1, IONIZATION = 2, ATTACHMENT = 3 };
 
@@ -101,6 +106,22 @@ Vec3 iso_direction(double u_cos, double u_phi) {
   return {st * std::cos(ph), st * std::sin(ph), ct};
 }
 
+// Unit vector at angle theta (cos given) and azimuth phi about the unit vector d = (a, b, c),
+// by the usual rotation of direction cosines with s = sqrt(a^2 + b^2):
+//   (a cos + sin (a c cos phi - b sin phi)/s, b cos + sin (b c cos phi + a sin phi)/s,
+//    c cos - s sin cos phi);  for s = 0 (d along z): (sin cos phi, sin sin phi, c cos).
+Vec3 rotate_direction(Vec3 d, double cos_t, double phi) {
+  const double sin_t = std::sqrt(std::max(0.0, (1.0 - cos_t) * (1.0 + cos_t)));
+  const double cp = std::cos(phi), sp = std::sin(phi);
+  const double s = std::sqrt(d.x * d.x + d.y * d.y);
+  if (s > 0.0) {
+    return {d.x * cos_t + sin_t * (d.x * d.z * cp - d.y * sp) / s,
+            d.y * cos_t + sin_t * (d.y * d.z * cp + d.x * sp) / s,
+            d.z * cos_t - s * sin_t * cp};
+  }
+  return {sin_t * cp, sin_t * sp, d.z * cos_t};
+}
+
 // ---------------------------------------------------------------------------------------
 // Gas model.
 // ---------------------------------------------------------------------------------------
@@ -111,7 +132,42 @@ struct Channel {
   int component;
   double mass_kg;             // target mass M
   double density;             // n_k = fraction_k * N
+  int scattering;             // of its component: 0 isotropic, 1 screened Coulomb, 2 constant xi
+  double xi;                  // scattering 2: the anisotropy parameter
 };
+
+// Okhrimovskyy anisotropic scattering (section "Theoretical framework", eqs. collision_angle
+// and collision_angle_xi).  For molecular gases xi solves
+//   sigma_mt / sigma_el = (1 - xi)/(2 xi^2) ((1 + xi) ln((1 + xi)/(1 - xi)) - 2 xi),
+// whose right side falls from 1 (xi -> 0, isotropic) to 0 (xi -> 1, forward); the ratio of
+// the two cross-sections is taken constant per component (the tables here carry only the
+// momentum-transfer cross-section).  Bisection on (0, 1) in binary64.
+double mt_over_el_of_xi(double xi) {
+  if (xi <= 0.0) return 1.0;
+  return (1.0 - xi) / (2.0 * xi * xi) * ((1.0 + xi) * std::log((1.0 + xi) / (1.0 - xi)) - 2.0 * xi);
+}
+double xi_from_ratio(double r) {
+  if (r >= 1.0) return 0.0;
+  double lo = 0.0, hi = 1.0;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid == lo || mid == hi) break;
+    if (mt_over_el_of_xi(mid) > r) lo = mid; else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// cos(theta) of a scattering from a uniform u in [0,1): isotropic 1 - 2u; screened Coulomb
+// for atoms with eps in atomic units (eq. collision_angle); the xi form for molecules
+// (eq. collision_angle_xi).
+double scatter_cos(int scattering, double xi, double eps_eV, double u) {
+  if (scattering == 1) {
+    const double e = eps_eV / kHartreeEV;
+    return 1.0 - 2.0 * u / (1.0 + 8.0 * e * (1.0 - u));
+  }
+  if (scattering == 2) return 1.0 - 2.0 * u * (1.0 - xi) / (1.0 + xi * (1.0 - 2.0 * u));
+  return 1.0 - 2.0 * u;
+}
 
 // Raw cross-section with the paper's table extension (section "Extension of the
 // cross-section tables"):
@@ -401,9 +457,18 @@ Record simulate(const RunCtx& cx, const Electron& e0, std::vector<Electron>& chi
       move(m, r, v, T, &rT, nullptr);
       const Words sh = stream_block(cx.seed, e0.id, SCAT_HI, k);
       const Words sl = stream_block(cx.seed, e0.id, SCAT_LO, k);
-      const Vec3 n = iso_direction(uniform53(sh.w[0], sl.w[0]), uniform53(sh.w[1], sl.w[1]));
       const double v2 = dot(vT, vT);
-      const double cos_t = v2 > 0.0 ? dot(n, vT) / std::sqrt(v2) : 0.0;
+      Vec3 n;
+      double cos_t;
+      if (chn.scattering == 0 || !(v2 > 0.0)) {
+        // isotropic in the lab frame; theta is the angle to the incoming velocity
+        n = iso_direction(uniform53(sh.w[0], sl.w[0]), uniform53(sh.w[1], sl.w[1]));
+        cos_t = v2 > 0.0 ? dot(n, vT) / std::sqrt(v2) : 0.0;
+      } else {
+        // anisotropic: theta about the incoming direction, azimuth 2 pi u'
+        cos_t = scatter_cos(chn.scattering, chn.xi, eps, uniform53(sh.w[0], sl.w[0]));
+        n = rotate_direction(scale(vT, 1.0 / std::sqrt(v2)), cos_t, 2.0 * kPi * uniform53(sh.w[1], sl.w[1]));
+      }
       double epsp;
       if (chn.kind == ELASTIC) {
         epsp = energy_after_elastic(eps, cos_t, M);
@@ -494,7 +559,8 @@ extern "C" {
 
 struct or_channel { int32_t kind; double threshold_eV; int32_t n_points; const double* energy_eV;
                     const double* sigma_m2; };
-struct or_component { double mass_amu; double fraction; int32_t n_channels; const or_channel* channels; };
+struct or_component { double mass_amu; double fraction; int32_t n_channels; const or_channel* channels;
+                      int32_t scattering; double mt_over_el; };
 struct or_params { double E_V_per_m, B_T, B_angle_rad, N_per_m3, T_K, init_energy_eV;
                    int32_t secondaries, grid_P, grid_emin, grid_emax; double user_majorant;
                    int32_t trial_strategy; double trial_zeta; int64_t trial_grace; };
@@ -530,6 +596,9 @@ void* or_create(const or_component* comps, int32_t n_comps, const or_params* p, 
   for (int k = 0; k < n_comps; ++k) {
     const or_component& c = comps[k];
     if (!(c.mass_amu > 0.0) || !(c.fraction >= 0.0) || c.n_channels <= 0) { delete m; return nullptr; }
+    if (c.scattering < 0 || c.scattering > 2) { delete m; return nullptr; }
+    if (c.scattering == 2 && !(c.mt_over_el > 0.0 && c.mt_over_el <= 1.0)) { delete m; return nullptr; }
+    const double xi = c.scattering == 2 ? xi_from_ratio(c.mt_over_el) : 0.0;
     fsum += c.fraction;
     for (int j = 0; j < c.n_channels; ++j) {
       const or_channel& q = c.channels[j];
@@ -546,6 +615,8 @@ void* or_create(const or_component* comps, int32_t n_comps, const or_params* p, 
         if (i > 0 && !(ch.e[i] > ch.e[i - 1])) { delete m; return nullptr; }
       }
       ch.component = k;
+      ch.scattering = c.scattering;
+      ch.xi = xi;
       ch.mass_kg = c.mass_amu * kAmu;
       ch.density = c.fraction * p->N_per_m3;
       m->ch.push_back(std::move(ch));
@@ -647,11 +718,22 @@ double or_energy_after(int32_t kind, double eps, double eps_k, double cos_t, dou
   return energy_after_inelastic(eps, eps_k, cos_t, M);
 }
 
+double or_xi_from_ratio(double r) { return xi_from_ratio(r); }
+double or_mt_over_el_of_xi(double xi) { return mt_over_el_of_xi(xi); }
+double or_scatter_cos(int32_t scattering, double xi, double eps_eV, double u) {
+  return scatter_cos(scattering, xi, eps_eV, u);
+}
+void or_rotate(const double* d, double cos_t, double phi, double* out) {
+  const Vec3 n = rotate_direction({d[0], d[1], d[2]}, cos_t, phi);
+  out[0] = n.x; out[1] = n.y; out[2] = n.z;
+}
+
 double or_const(int32_t which) {
   switch (which) {
     case 0: return kQe;
     case 1: return kMe;
     case 2: return kAmu;
+    case 3: return kHartreeEV;
     default: return 0.0;
   }
 }

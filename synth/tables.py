@@ -37,9 +37,16 @@ class Component:
     fraction: float
     channels: list = field(default_factory=list)
     name: str = ""
+    scattering: int = 0          # 0 isotropic, 1 screened Coulomb (atomic), 2 constant xi (molecular)
+    mt_over_el: float = 1.0      # scattering 2: sigma_mt / sigma_el, in (0, 1]
 
     def with_fraction(self, fraction: float) -> "Component":
-        return Component(self.mass_amu, float(fraction), list(self.channels), self.name)
+        return Component(self.mass_amu, float(fraction), list(self.channels), self.name, self.scattering,
+                         self.mt_over_el)
+
+    def with_scattering(self, scattering: int, mt_over_el: float = 1.0) -> "Component":
+        return Component(self.mass_amu, self.fraction, list(self.channels), self.name, int(scattering),
+                         float(mt_over_el))
 
 
 def grid_node_energies(points_per_octave: int = 64, min_exp2: int = -14, max_exp2: int = 12):
