@@ -88,6 +88,17 @@ typedef struct {
   const double* sigma_m2;
 } swarm_channel;
 
+/* Scattering angle of the electron in a real collision (section "Theoretical framework").
+ * ISOTROPIC: direction uniform on the sphere.  SCREENED_COULOMB (atoms, eq. collision_angle):
+ * cos(theta) = 1 - 2R / (1 + 8 e (1 - R)), e the energy before the collision in Hartree
+ * units.  CONSTANT_XI (molecules, eq. collision_angle_xi): cos(theta) = 1 - 2R(1 - xi) /
+ * (1 + xi (1 - 2R)), xi solving sigma_mt/sigma_el = (1 - xi)/(2 xi^2) ((1 + xi)
+ * ln((1 + xi)/(1 - xi)) - 2 xi) for a ratio given per component (the tables carry only
+ * sigma_mt).  The azimuth about the incoming direction is 2 pi R'; R, R' are the scattering
+ * block's first two uniforms.  A zero incoming velocity scatters isotropically. */
+typedef enum { SWARM_SCATTER_ISOTROPIC = 0, SWARM_SCATTER_SCREENED_COULOMB = 1,
+               SWARM_SCATTER_CONSTANT_XI = 2 } swarm_scattering;
+
 /* One gas component: target mass, number fraction of the density (fractions of all
  * components sum to 1 within 1e-9) and its channels.  Channel order (components in
  * order, then channels in order) fixes the collision-process order used in selection. */
@@ -96,6 +107,8 @@ typedef struct {
   double fraction;         /* >= 0 */
   int32_t n_channels;      /* >= 1 */
   const swarm_channel* channels;
+  int32_t scattering;      /* swarm_scattering of its collisions */
+  double mt_over_el;       /* SWARM_SCATTER_CONSTANT_XI: sigma_mt / sigma_el in (0, 1] */
 } swarm_component;
 
 typedef struct {

@@ -24,6 +24,7 @@ SWARM_ELASTIC, SWARM_EXCITATION, SWARM_IONIZATION, SWARM_ATTACHMENT = 0, 1, 2, 3
 SWARM_FP64, SWARM_FP32_MIXED = 0, 1
 SWARM_DUMMY, SWARM_REAL = 0, 1
 SWARM_TRIAL_CONSTANT, SWARM_TRIAL_VARIABLE = 0, 1
+SWARM_SCATTER_ISOTROPIC, SWARM_SCATTER_SCREENED_COULOMB, SWARM_SCATTER_CONSTANT_XI = 0, 1, 2
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1901_08140_amd/build.py`")
@@ -40,7 +41,7 @@ class swarm_channel(ctypes.Structure):
 
 class swarm_component(ctypes.Structure):
     _fields_ = [("mass_amu", _d), ("fraction", _d), ("n_channels", _i32),
-                ("channels", _P(swarm_channel))]
+                ("channels", _P(swarm_channel)), ("scattering", _i32), ("mt_over_el", _d)]
 
 
 class swarm_params(ctypes.Structure):
@@ -177,6 +178,8 @@ class _Marshalled:
             self.comps[ci].fraction = float(c.fraction)
             self.comps[ci].n_channels = len(c.channels)
             self.comps[ci].channels = chs
+            self.comps[ci].scattering = int(getattr(c, "scattering", 0))
+            self.comps[ci].mt_over_el = float(getattr(c, "mt_over_el", 1.0))
 
 
 def make_params(E_V_per_m, B_T=0.0, B_angle_rad=0.0, N_per_m3=2.5e25, T_K=293.0, init_energy_eV=0.1,

@@ -131,6 +131,10 @@ swarm_status validate(const swarm_component* comps, int32_t n_comps, const swarm
     if (!(c.fraction >= 0.0) || !std::isfinite(c.fraction))
       return fail(SWARM_ERR_INVALID_ARG, "component %d: fraction must be >= 0", k);
     if (c.n_channels <= 0 || !c.channels) return fail(SWARM_ERR_INVALID_ARG, "component %d: no channels", k);
+    if (c.scattering < SWARM_SCATTER_ISOTROPIC || c.scattering > SWARM_SCATTER_CONSTANT_XI)
+      return fail(SWARM_ERR_INVALID_ARG, "component %d: unknown scattering %d", k, c.scattering);
+    if (c.scattering == SWARM_SCATTER_CONSTANT_XI && !(c.mt_over_el > 0.0 && c.mt_over_el <= 1.0))
+      return fail(SWARM_ERR_INVALID_ARG, "component %d: sigma_mt/sigma_el must be in (0, 1]", k);
     fsum += c.fraction;
     for (int j = 0; j < c.n_channels; ++j) {
       const swarm_channel& q = c.channels[j];
@@ -305,11 +309,13 @@ swarm_status swarm_create(const swarm_component* comps, int32_t n_comps, const s
   DeviceInfo& dev = device_info();
   (void)dev;
   // Flatten the raw tables (argument marshalling only).
-  std::vector<double> e_all, s_all, thr, mass, frac;
-  std::vector<int32_t> off, npt, kind, comp;
+  std::vector<double> e_all, s_all, thr, mass, frac, ratio;
+  std::vector<int32_t> off, npt, kind, comp, scat;
   for (int k = 0; k < n_comps; ++k) {
     mass.push_back(comps[k].mass_amu);
     frac.push_back(comps[k].fraction);
+    scat.push_back(comps[k].scattering);
+    ratio.push_back(comps[k].scattering == SWARM_SCATTER_CONSTANT_XI ? comps[k].mt_over_el : 1.0);
     for (int j = 0; j < comps[k].n_channels; ++j) {
       const swarm_channel& q = comps[k].channels[j];
       off.push_back(static_cast<int32_t>(e_all.size()));
@@ -347,7 +353,7 @@ swarm_status swarm_create(const swarm_component* comps, int32_t n_comps, const s
   const size_t b_nu64 = al(static_cast<size_t>(G) * 16), b_nu32 = al(static_cast<size_t>(G) * 8);
   const size_t b_c64 = al(static_cast<size_t>(G) * nc * 16), b_c32 = al(static_cast<size_t>(G) * nc * 8);
   const size_t b_ch = al(nc * sizeof(ChannelDev));
-  const size_t total = b_e + b_s + 4 * b_i + b_cd + 2 * b_k + b_nodes + b_cm + b_nu64 + b_nu32 + b_c64 + b_c32 + b_ch +
+  const size_t total = b_e + b_s + 4 * b_i + b_cd + 4 * b_k + b_nodes + b_cm + b_nu64 + b_nu32 + b_c64 + b_c32 + b_ch +
                        al(sizeof(InstanceDesc)) + al(sizeof(RunCounters));
   hipError_t e = h->arena.ensure(total);
   if (e != hipSuccess) return hip_fail(e, "allocating instance tables");
@@ -363,6 +369,8 @@ swarm_status swarm_create(const swarm_component* comps, int32_t n_comps, const s
   double* d_thr = reinterpret_cast<double*>(take(b_cd));
   double* d_mass = reinterpret_cast<double*>(take(b_k));
   double* d_frac = reinterpret_cast<double*>(take(b_k));
+  int32_t* d_scat = reinterpret_cast<int32_t*>(take(b_k));
+  double* d_ratio = reinterpret_cast<double*>(take(b_k));
   d.nodes = reinterpret_cast<double*>(take(b_nodes));
   d.cum_cm = reinterpret_cast<double*>(take(b_cm));
   d.nu64 = reinterpret_cast<double2*>(take(b_nu64));
@@ -374,10 +382,11 @@ swarm_status swarm_create(const swarm_component* comps, int32_t n_comps, const s
   d.ctr = reinterpret_cast<RunCounters*>(take(al(sizeof(RunCounters))));
   d.raw_e = d_e; d.raw_s = d_s; d.raw_off = d_off; d.raw_n = d_n; d.raw_kind = d_kind;
   d.raw_comp = d_comp; d.raw_thr = d_thr; d.comp_mass_amu = d_mass; d.comp_frac = d_frac;
+  d.comp_scat = d_scat; d.comp_ratio = d_ratio;
   hipStream_t s = h->stream;
 #define CP(dst, v) if ((e = hipMemcpyAsync(dst, v.data(), v.size() * sizeof(v[0]), hipMemcpyHostToDevice, s)) != hipSuccess) return hip_fail(e, "copying tables");
   CP(d_e, e_all) CP(d_s, s_all) CP(d_off, off) CP(d_n, npt) CP(d_kind, kind) CP(d_comp, comp)
-  CP(d_thr, thr) CP(d_mass, mass) CP(d_frac, frac)
+  CP(d_thr, thr) CP(d_mass, mass) CP(d_frac, frac) CP(d_scat, scat) CP(d_ratio, ratio)
 #undef CP
   if ((e = launch_fill_u64(reinterpret_cast<uint64_t*>(d.ctr), 0, sizeof(RunCounters) / 8, s)) != hipSuccess)
     return hip_fail(e, "clearing counters");

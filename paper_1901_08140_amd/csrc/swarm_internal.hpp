@@ -36,6 +36,9 @@ struct ChannelDev {
   double c_M;      // M / (m+M)
   double c_mM;     // (m+M) / M
   float thr_f, c_ela_f, c_M_f, c_mM_f;
+  int32_t scat;    // swarm_scattering of its component
+  float xi_f;
+  double xi;       // SWARM_SCATTER_CONSTANT_XI: the anisotropy parameter
 };
 
 // Saved electron state at a real-collision boundary (serving epochs resume from it).
@@ -92,6 +95,8 @@ struct InstanceDesc {
   const double* raw_thr;
   const double* comp_mass_amu;
   const double* comp_frac;
+  const int32_t* comp_scat;   // swarm_scattering per component
+  const double* comp_ratio;   // sigma_mt / sigma_el per component
   double* nodes;              // G node energies (eV)
   double* cum_cm;             // nc x G running sums, channel major (FP64)
   double2* nu64;              // G pairs (F, F[g+1]-F[g]) of the total rate

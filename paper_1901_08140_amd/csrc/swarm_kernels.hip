@@ -28,6 +28,7 @@ constexpr double kQe = 1.602176634e-19;     // C
 constexpr double kMe = 9.1093837015e-31;    // kg
 constexpr double kAmu = 1.66053906660e-27;  // kg
 constexpr double kPi = 3.14159265358979323846;
+constexpr double kHartreeEV = 27.211386245988;   // Hartree energy in eV (CODATA 2018)
 constexpr double kLn2 = 0.69314718055994530942;
 
 // ---------------------------------------------------------------------------------------
@@ -127,6 +128,63 @@ __device__ __forceinline__ void sincos_rev(float u, float* s, float* c) {
 }
 __device__ __forceinline__ void sincos_rev(double u, double* s, double* c) {
   sincos(2.0 * kPi * u, s, c);
+}
+
+// Anisotropic scattering (section "Theoretical framework", eqs. collision_angle and
+// collision_angle_xi).  For molecules xi solves sigma_mt/sigma_el = (1 - xi)/(2 xi^2)
+// ((1 + xi) ln((1 + xi)/(1 - xi)) - 2 xi); the right side falls from 1 at xi = 0 to 0 at
+// xi = 1, so bisection on (0, 1) in binary64 converges to it.
+__device__ double mt_over_el_of_xi(double xi) {
+  if (xi <= 0.0) return 1.0;
+  return (1.0 - xi) / (2.0 * xi * xi) * ((1.0 + xi) * log((1.0 + xi) / (1.0 - xi)) - 2.0 * xi);
+}
+__device__ double xi_of_ratio(double r) {
+  if (r >= 1.0) return 0.0;
+  double lo = 0.0, hi = 1.0;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid == lo || mid == hi) break;
+    if (mt_over_el_of_xi(mid) > r) lo = mid; else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// cos(theta) from the uniform u: screened Coulomb with the energy before the collision in
+// Hartree units, or the xi form.
+__device__ __forceinline__ double scatter_cos(int scat, double xi, double eps, double u) {
+  if (scat == SWARM_SCATTER_SCREENED_COULOMB) {
+    const double e = eps / kHartreeEV;
+    return 1.0 - 2.0 * u / (1.0 + 8.0 * e * (1.0 - u));
+  }
+  return 1.0 - 2.0 * u * (1.0 - xi) / (1.0 + xi * (1.0 - 2.0 * u));
+}
+__device__ __forceinline__ float scatter_cos(int scat, float xi, float eps, float u) {
+  if (scat == SWARM_SCATTER_SCREENED_COULOMB) {
+    const float e = eps * static_cast<float>(1.0 / kHartreeEV);
+    return 1.0f - 2.0f * u / (1.0f + 8.0f * e * (1.0f - u));
+  }
+  return 1.0f - 2.0f * u * (1.0f - xi) / (1.0f + xi * (1.0f - 2.0f * u));
+}
+
+// The unit vector at polar angle theta (cos given) and azimuth 2 pi u_phi about the unit
+// vector d = (a, b, c): the rotation of direction cosines with s = sqrt(a^2 + b^2),
+//   (a cos + sin (a c cos phi - b sin phi)/s, b cos + sin (b c cos phi + a sin phi)/s,
+//    c cos - s sin cos phi), and (sin cos phi, sin sin phi, c cos) when d is along z.
+template <typename R>
+__device__ __forceinline__ void rotate_dir(R a, R b, R c, R cos_t, R u_phi, R* nx, R* ny, R* nz) {
+  const R sin_t = sqrt_(fmax(R(0), (R(1) - cos_t) * (R(1) + cos_t)));
+  R sp, cp;
+  sincos_rev(u_phi, &sp, &cp);
+  const R s = sqrt_(a * a + b * b);
+  if (s > R(0)) {
+    *nx = a * cos_t + sin_t * (a * c * cp - b * sp) / s;
+    *ny = b * cos_t + sin_t * (b * c * cp + a * sp) / s;
+    *nz = c * cos_t - s * sin_t * cp;
+  } else {
+    *nx = sin_t * cp;
+    *ny = sin_t * sp;
+    *nz = c * cos_t;
+  }
 }
 
 // Isotropic unit vector: cos(Theta) = 1 - 2u, Phi = 2 pi u'.
@@ -294,6 +352,9 @@ __global__ void k_build_constants(InstanceDesc* desc) {
     ch.c_ela_f = static_cast<float>(ch.c_ela);
     ch.c_M_f = static_cast<float>(ch.c_M);
     ch.c_mM_f = static_cast<float>(ch.c_mM);
+    ch.scat = d.comp_scat[comp];
+    ch.xi = ch.scat == SWARM_SCATTER_CONSTANT_XI ? xi_of_ratio(d.comp_ratio[comp]) : 0.0;
+    ch.xi_f = static_cast<float>(ch.xi);
     d.chan[c] = ch;
   }
   if (threadIdx.x == 0) {
@@ -921,11 +982,25 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
   const W4 h = L.sh;        // scattering block k, drawn while the candidate waited
   const W4 l = L.sl;
   R nx, ny, nz;
-  iso_dir<R>(uni(h.x, l.x, R(0)), uni(h.y, l.y, R(0)), &nx, &ny, &nz);
+  const R u_c = uni(h.x, l.x, R(0)), u_p = uni(h.y, l.y, R(0));
   const R v2 = vx * vx + vy * vy + vz * vz;
   R cos_t;
-  if constexpr (sizeof(R) == 8) cos_t = v2 > 0.0 ? (nx * vx + ny * vy + nz * vz) / sqrt(v2) : 0.0;
-  else cos_t = v2 > 0.0f ? (nx * vx + ny * vy + nz * vz) * rsqrt_(v2) : 0.0f;
+  if (ch.scat == SWARM_SCATTER_ISOTROPIC || !(v2 > R(0))) {
+    // isotropic in the lab frame; theta is the angle to the incoming velocity
+    iso_dir<R>(u_c, u_p, &nx, &ny, &nz);
+    if constexpr (sizeof(R) == 8) cos_t = v2 > 0.0 ? (nx * vx + ny * vy + nz * vz) / sqrt(v2) : 0.0;
+    else cos_t = v2 > 0.0f ? (nx * vx + ny * vy + nz * vz) * rsqrt_(v2) : 0.0f;
+  } else {
+    // anisotropic: theta about the incoming direction, azimuth 2 pi u'
+    R xi;
+    if constexpr (sizeof(R) == 8) xi = ch.xi;
+    else xi = ch.xi_f;
+    cos_t = scatter_cos(ch.scat, xi, eps, u_c);
+    R inv;
+    if constexpr (sizeof(R) == 8) inv = 1.0 / sqrt(v2);
+    else inv = rsqrt_(v2);
+    rotate_dir<R>(vx * inv, vy * inv, vz * inv, cos_t, u_p, &nx, &ny, &nz);
+  }
   R c_ela, c_M, c_mM, thr;
   if constexpr (sizeof(R) == 8) { c_ela = ch.c_ela; c_M = ch.c_M; c_mM = ch.c_mM; thr = ch.thr; }
   else { c_ela = ch.c_ela_f; c_M = ch.c_M_f; c_mM = ch.c_mM_f; thr = ch.thr_f; }
