@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variable", action="store_true",
                     help="skip the leg with the variable trial frequency")
+    ap.add_argument("--no-anisotropic", action="store_true",
+                    help="skip the leg with screened-Coulomb scattering")
     ap.add_argument("--serve-rate", type=float, default=5.0)
     ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--autotune", action="store_true",
@@ -208,6 +210,32 @@ def variable_leg(sw, args, cfgs, jobs, opts, tall_const, ms_const, zeta=0.25, gr
             "rel_shift_vs_constant": shift}
 
 
+def anisotropic_leg(sw, args, cfgs, jobs, opts, tall_const, ms_const):
+    """The same batched FP32 step with screened-Coulomb (anisotropic) scattering of the
+    argon-like atom: throughput, and how the drift velocity and mean energy move."""
+    ca = [c.scaled(components=[k.with_scattering(1) for k in c.components]) for c in cfgs]
+    ha = [sw.Swarm.from_config(c, sw.SWARM_FP32_MIXED) for c in ca]
+    b = sw.swarm_batch_create([h.h for h in ha], jobs, opts)
+    try:
+        sw.swarm_batch_launch(b)
+        sw.swarm_batch_wait(b)
+        ms = []
+        for _ in range(max(1, args.steps)):
+            sw.swarm_batch_launch(b)
+            ms.append(sw.swarm_batch_wait(b))
+        ta = [sw.swarm_batch_tallies(b, i) for i in range(len(cfgs))]
+    finally:
+        sw.swarm_batch_destroy(b)
+    avg = sum(ms) / len(ms)
+    real = sum(t["n_real"] for t in ta)
+    trials = sum(t["n_real"] + t["n_null"] + t["n_forbidden"] + t["n_fail"] for t in ta)
+    ratio = {k: [a[k][0] / c[k][0] for a, c in zip(ta, tall_const) if c[k][0] != 0]
+             for k in ("W", "mean_energy")}
+    return {"value": real / (avg * 1e-3), "unit": "real collisions/s", "device_ms_per_step": avg,
+            "efficiency": real / trials, "time_vs_isotropic": avg / ms_const,
+            "ratio_to_isotropic": {k: {"min": min(v), "max": max(v)} for k, v in ratio.items()}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -278,6 +306,9 @@ def main():
     if not args.no_variable:
         out["fp32_batched_variable"] = variable_leg(sw, args, cfgs, jobs, opts, tall32, avg_ms)
         log(args, "variable trial frequency", out["fp32_batched_variable"])
+    if not args.no_anisotropic:
+        out["fp32_batched_screened_coulomb"] = anisotropic_leg(sw, args, cfgs, jobs, opts, tall32, avg_ms)
+        log(args, "screened-Coulomb scattering", out["fp32_batched_screened_coulomb"])
     if not args.no_fp64:
         # the plain FP64 form: one swarm per launch, default launch shape
         h64 = [sw.Swarm.from_config(c, sw.SWARM_FP64) for c in cfgs]
