@@ -45,3 +45,37 @@ def test_struct_sizes_match_the_oracle_layout():
     assert sw.RECORD_DTYPE.itemsize == 104
     assert sw.EVENT_DTYPE.itemsize == 80
     assert ctypes.sizeof(sw.swarm_tallies_t) == 20 * 24 + 4 * 8 + 13 * 8
+
+
+STRUCTS = ["swarm_channel", "swarm_component", "swarm_params", "swarm_stat", "swarm_tallies_t", "swarm_job",
+           "swarm_launch_opts", "swarm_server_params", "swarm_request_info"]
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """The ctypes mirrors have the size and field offsets the C compiler gives the header's
+    structs (compiled with the host C compiler; no GPU)."""
+    import shutil
+    import subprocess
+    import paper_1901_08140_amd as sw
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void) {"]
+    for name in STRUCTS:
+        cls = getattr(sw, name)
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{name}.{fname} %zu\\n", offsetof({name}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-o", str(exe), str(src)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                        text=True).stdout.splitlines())
+    for name in STRUCTS:
+        cls = getattr(sw, name)
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for fname, _ in cls._fields_:
+            assert int(got[f"{name}.{fname}"]) == getattr(cls, fname).offset, (name, fname)
