@@ -250,7 +250,15 @@ typedef struct {
   int32_t service_waves;   /* 0: every wave serves its own candidates; n >= 1: pooled schedule,
                               n waves of each work-group serve the candidates of the others at
                               full width (n < block_size/64; traced runs use the per-wave one) */
+  int32_t table_layout;    /* LDS tables of a work-group: 0 the total-rate pairs and channel
+                              descriptors (running sums read through L2); 1 also the running
+                              sums of every channel, when they fit the work-group's LDS
+                              (otherwise 0) */
 } swarm_launch_opts;
+
+/* Launch shape of the handle's own runs (swarm_run); zero fields take the defaults.  Like
+ * every launch option it changes the schedule only, never the results. */
+swarm_status swarm_set_launch_opts(swarm_t h, const swarm_launch_opts* opts);
 
 typedef struct swarm_batch* swarm_batch_t;
 
@@ -271,7 +279,8 @@ void swarm_batch_destroy(swarm_batch_t b);
 swarm_status swarm_batch_run(swarm_t* handles, const swarm_job* jobs, int32_t n,
                              const swarm_launch_opts* opts);
 
-/* Autotuner: times the result-invariant launch options on a shortened copy of the batch
+/* Autotuner: times the result-invariant launch options (block size, pending trigger, electrons
+ * per work item, LDS table layout) on a shortened copy of the batch
  * (same instances, budgets cut to probe_collisions) and writes the fastest to *best. */
 swarm_status swarm_autotune(swarm_t* handles, const swarm_job* jobs, int32_t n,
                             int64_t probe_collisions, swarm_launch_opts* best);

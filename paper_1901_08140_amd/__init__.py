@@ -75,7 +75,7 @@ class swarm_job(ctypes.Structure):
 
 class swarm_launch_opts(ctypes.Structure):
     _fields_ = [("block_size", _i32), ("chunk", _i32), ("pending_trigger", _i32), ("use_graph", _i32),
-                ("service_waves", _i32)]
+                ("service_waves", _i32), ("table_layout", _i32)]
 
 
 class swarm_server_params(ctypes.Structure):
@@ -106,6 +106,7 @@ EVENT_DTYPE = np.dtype({
 _SIGS = {
     "swarm_create": (_i32, [_P(swarm_component), _i32, _P(swarm_params), _P(_vp)]),
     "swarm_run": (_i32, [_vp, _i64, _i64, _u64]),
+    "swarm_set_launch_opts": (_i32, [_vp, _P(swarm_launch_opts)]),
     "swarm_tallies": (_i32, [_vp, _P(swarm_tallies_t)]),
     "swarm_records": (_i32, [_vp, _vp, _i64, _P(_i64)]),
     "swarm_set_trace": (_i32, [_vp, _P(_u64), _i32, _i32]),
@@ -211,6 +212,10 @@ def swarm_create(components, params):
     h = _vp()
     _check(_lib.swarm_create(m.comps, len(components), ctypes.byref(params), ctypes.byref(h)))
     return h
+
+
+def swarm_set_launch_opts(h, opts):
+    return _check(_lib.swarm_set_launch_opts(h, ctypes.byref(_opts(opts))))
 
 
 def swarm_run(h, n_electrons, n_collisions, seed):
@@ -402,6 +407,9 @@ class Swarm:
 
     def run(self, n_electrons, n_collisions, seed):
         return swarm_run(self.h, n_electrons, n_collisions, seed)
+
+    def set_launch_opts(self, opts):
+        return swarm_set_launch_opts(self.h, opts)
 
     def tallies(self):
         return swarm_tallies(self.h)

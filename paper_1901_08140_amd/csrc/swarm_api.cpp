@@ -56,16 +56,26 @@ DeviceInfo& device_info() {
 }
 
 // Dynamic LDS of the swarm kernels: the total-rate pairs of the G grid nodes plus one
-// padding entry in front, then (16-byte aligned) the nc channel descriptors.
-// With the pooled schedule the candidate pool (64 slots per service wave) follows.
-LdsLayout lds_layout(int precision, int G, int nc, int service_waves) {
+// padding entry in front, then (16-byte aligned) the nc channel descriptors, then with table
+// layout 1 the G x nc running-sum pairs (if everything fits the work-group's LDS), then with
+// the pooled schedule the candidate pool (64 slots per service wave).
+LdsLayout lds_layout(int precision, int G, int nc, int service_waves, int table_layout) {
   auto al = [](size_t n) { return (n + 15) & ~static_cast<size_t>(15); };
+  const size_t pair = precision == SWARM_FP32_MIXED ? sizeof(float2) : sizeof(double2);
+  const size_t pool = service_waves > 0 ? static_cast<size_t>(64 * service_waves) * swarm_pool_slot_bytes(precision) : 0;
   LdsLayout l;
-  const size_t b = static_cast<size_t>(G + 1) * (precision == SWARM_FP32_MIXED ? sizeof(float2) : sizeof(double2));
-  l.ch_off = static_cast<int>(al(b));
-  l.pool_off = static_cast<int>(al(static_cast<size_t>(l.ch_off) + static_cast<size_t>(nc) * sizeof(ChannelDev)));
-  l.bytes = static_cast<size_t>(l.pool_off);
-  if (service_waves > 0) l.bytes += static_cast<size_t>(64 * service_waves) * swarm_pool_slot_bytes(precision);
+  l.ch_off = static_cast<int>(al(static_cast<size_t>(G + 1) * pair));
+  const size_t after_ch = al(static_cast<size_t>(l.ch_off) + static_cast<size_t>(nc) * sizeof(ChannelDev));
+  l.cum_off = -1;
+  l.pool_off = static_cast<int>(after_ch);
+  if (table_layout == 1) {
+    const size_t with_cum = al(after_ch + static_cast<size_t>(G) * static_cast<size_t>(nc) * pair);
+    if (static_cast<int64_t>(with_cum + pool) <= device_info().lds_per_block) {
+      l.cum_off = static_cast<int>(after_ch);
+      l.pool_off = static_cast<int>(with_cum);
+    }
+  }
+  l.bytes = static_cast<size_t>(l.pool_off) + pool;
   return l;
 }
 
@@ -265,6 +275,7 @@ swarm_launch_opts resolve_opts(const swarm_launch_opts* o, int precision) {
   r.chunk = std::max(r.block_size, (r.chunk / r.block_size) * r.block_size);
   r.pending_trigger = std::max(1, std::min(64, r.pending_trigger));
   r.service_waves = o ? std::max(0, std::min(r.block_size / 64 - 1, o->service_waves)) : 0;
+  r.table_layout = (o && o->table_layout == 1) ? 1 : 0;
   return r;
 }
 
@@ -436,6 +447,12 @@ swarm_status swarm_set_trace(swarm_t h, const uint64_t* ids, int32_t n_ids, int3
   return SWARM_OK;
 }
 
+swarm_status swarm_set_launch_opts(swarm_t h, const swarm_launch_opts* opts) {
+  if (!h) return fail(SWARM_ERR_INVALID_ARG, "NULL handle");
+  h->opts = resolve_opts(opts, h->desc.precision);
+  return SWARM_OK;
+}
+
 swarm_status swarm_run(swarm_t h, int64_t n_electrons, int64_t n_collisions, uint64_t seed) {
   if (!h) return fail(SWARM_ERR_INVALID_ARG, "handle is NULL");
   if (n_electrons < 1) return fail(SWARM_ERR_INVALID_ARG, "n_electrons must be >= 1");
@@ -488,7 +505,10 @@ swarm_status swarm_run(swarm_t h, int64_t n_electrons, int64_t n_collisions, uin
   if ((e = sync_desc_to_device(h)) != hipSuccess) return hip_fail(e, "descriptor");
   const swarm_launch_opts& o = h->opts;
   const int svc = trace || real ? 0 : o.service_waves;
-  const LdsLayout ll = lds_layout(d.precision, d.G, d.nc, svc);
+  const LdsLayout ll = lds_layout(d.precision, d.G, d.nc, svc, o.table_layout);
+  if (static_cast<int64_t>(ll.bytes) > device_info().lds_per_block)
+    return fail(SWARM_ERR_INVALID_ARG, "the tables need %zu bytes of LDS per work-group, the device has %lld",
+                ll.bytes, static_cast<long long>(device_info().lds_per_block));
   const size_t lds = ll.bytes;
   const int ch_off = ll.ch_off;
   DeviceInfo& dev = device_info();
@@ -512,12 +532,13 @@ swarm_status swarm_run(swarm_t h, int64_t n_electrons, int64_t n_collisions, uin
     const int grid = std::max(1, std::min<int>(static_cast<int>(items.size()), dev.n_cu * per_cu));
     if ((e = launch_swarm_dummy(h->d_desc, static_cast<const WorkItem*>(h->items.p), static_cast<int32_t>(items.size()),
                                 d_ctr, d.precision, h->has_b, trace, var, svc, o.block_size, grid, o.pending_trigger, lds, ch_off,
-                                ll.pool_off, s)) != hipSuccess)
+                                ll.pool_off, ll.cum_off, s)) != hipSuccess)
       return hip_fail(e, "swarm kernel launch");
   } else {
     const int64_t want = (n_electrons + o.block_size - 1) / o.block_size;
     const int grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want * 4, static_cast<int64_t>(dev.n_cu) * per_cu)));
-    if ((e = launch_swarm_real(h->d_desc, d.precision, h->has_b, trace, var, o.block_size, grid, o.pending_trigger, lds, ch_off, s)) != hipSuccess)
+    if ((e = launch_swarm_real(h->d_desc, d.precision, h->has_b, trace, var, o.block_size, grid, o.pending_trigger, lds, ch_off,
+                               ll.cum_off, s)) != hipSuccess)
       return hip_fail(e, "swarm kernel launch");
   }
   if ((e = hipEventRecord(h->ev[1], s)) != hipSuccess) return hip_fail(e, "event");

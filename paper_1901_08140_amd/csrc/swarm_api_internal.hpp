@@ -46,8 +46,9 @@ swarm_status hip_fail(hipError_t e, const char* what);
 struct LdsLayout {
   size_t bytes;
   int ch_off, pool_off;
+  int cum_off;     // running sums staged at this offset, or -1 (read from global memory)
 };
-LdsLayout lds_layout(int precision, int G, int nc, int service_waves);
+LdsLayout lds_layout(int precision, int G, int nc, int service_waves, int table_layout);
 void make_items(const std::vector<int64_t>& n_e, const std::vector<int64_t>& n_c, int64_t chunk,
                 std::vector<WorkItem>& items, int64_t slots, int64_t block);
 swarm_launch_opts resolve_opts(const swarm_launch_opts* o, int precision);

@@ -26,7 +26,7 @@ struct swarm_batch {
   swarm_launch_opts opts{};
   int grid = 1;
   size_t lds = 0;
-  int ch_off = 0, pool_off = 0;
+  int ch_off = 0, pool_off = 0, cum_off = -1;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -58,7 +58,7 @@ hipError_t enqueue(swarm_batch* b) {
   if ((e = launch_swarm_dummy(static_cast<const InstanceDesc*>(b->descs.p), static_cast<const WorkItem*>(b->items.p),
                               static_cast<int32_t>(b->h_items.size()), item_counter(b), b->precision, b->magnetic,
                               false, b->variable, b->opts.service_waves, b->opts.block_size, b->grid,
-                              b->opts.pending_trigger, b->lds, b->ch_off, b->pool_off, b->stream)) != hipSuccess)
+                              b->opts.pending_trigger, b->lds, b->ch_off, b->pool_off, b->cum_off, b->stream)) != hipSuccess)
     return e;
   return b->tally.launch(static_cast<const InstanceDesc*>(b->descs.p), b->stream);
 }
@@ -123,10 +123,14 @@ swarm_status swarm_batch_create(swarm_t* handles, const swarm_job* jobs, int32_t
     ne.push_back(jobs[i].n_electrons);
     nc.push_back(jobs[i].n_collisions);
   }
-  const LdsLayout ll = lds_layout(b->precision, G, n_ch, b->opts.service_waves);
+  const LdsLayout ll = lds_layout(b->precision, G, n_ch, b->opts.service_waves, b->opts.table_layout);
+  if (static_cast<int64_t>(ll.bytes) > device_info().lds_per_block)
+    return fail(SWARM_ERR_INVALID_ARG, "the tables need %zu bytes of LDS per work-group, the device has %lld",
+                ll.bytes, static_cast<long long>(device_info().lds_per_block));
   b->lds = ll.bytes;
   b->ch_off = ll.ch_off;
   b->pool_off = ll.pool_off;
+  b->cum_off = ll.cum_off;
   const int per_cu = swarm_kernel_max_blocks_per_cu(b->precision, b->magnetic, false, false, b->variable,
                                                     b->opts.service_waves, b->opts.block_size, b->lds);
   const int64_t slots = static_cast<int64_t>(device_info().n_cu) * per_cu;
@@ -263,6 +267,13 @@ swarm_status swarm_autotune(swarm_t* handles, const swarm_job* jobs, int32_t n, 
   for (int mult : {4, 16, 32}) {
     swarm_launch_opts o = base2;
     o.chunk = base2.block_size * mult;
+    if ((st = time_it(o, &t)) != SWARM_OK) return st;
+    if (t < best_t) { best_t = t; cur = o; }
+  }
+  // LDS table layout: running sums in LDS too (taken only where they fit; see lds_layout)
+  {
+    swarm_launch_opts o = cur;
+    o.table_layout = 1;
     if ((st = time_it(o, &t)) != SWARM_OK) return st;
     if (t < best_t) { best_t = t; cur = o; }
   }

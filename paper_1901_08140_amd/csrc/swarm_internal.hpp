@@ -162,11 +162,11 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
 hipError_t launch_swarm_dummy(const InstanceDesc* d_desc, const WorkItem* d_items, int32_t n_items,
                               int32_t* d_item_counter, int precision, bool has_b, bool trace,
                               bool var, int service_waves, int block_size, int grid, int pending_trigger,
-                              size_t lds_bytes, int ch_off, int pool_off, hipStream_t s);
+                              size_t lds_bytes, int ch_off, int pool_off, int cum_off, hipStream_t s);
 size_t swarm_pool_slot_bytes(int precision);
 hipError_t launch_swarm_real(const InstanceDesc* d_desc, int precision, bool has_b, bool trace,
                              bool var, int block_size, int grid, int pending_trigger, size_t lds_bytes,
-                             int ch_off, hipStream_t s);
+                             int ch_off, int cum_off, hipStream_t s);
 hipError_t launch_tallies(const InstanceDesc* d_desc, const TallyTile* d_tiles, int32_t n_tiles,
                           const int32_t* d_tile_base, const int64_t* d_nrec, int32_t n_inst,
                           double* d_part1, double* d_part2, double* d_tot1,

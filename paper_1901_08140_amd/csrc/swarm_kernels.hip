@@ -1061,6 +1061,19 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
   return RC_CONTINUE;
 }
 
+// Table layout 1: the instance's running-sum pairs (G x nc, node major) staged in LDS at
+// cum_off, so the channel search reads LDS instead of L2.
+template <typename R>
+__device__ __forceinline__ void stage_cum(const InstanceDesc& d, unsigned char* smem, int cum_off) {
+  using PT = typename Pair<R>::T;
+  if (cum_off < 0) return;
+  const PT* src = reinterpret_cast<const PT*>(sizeof(R) == 8 ? static_cast<const void*>(d.cum64)
+                                                             : static_cast<const void*>(d.cum32));
+  PT* dst = reinterpret_cast<PT*>(smem + cum_off);
+  const int n = d.G * d.nc;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
 // ---------------------------------------------------------------------------------------
 // Dummy-mode persistent kernel over work items (instance, electron range).  A work-group
 // claims an item, stages the instance's total-rate pairs in LDS (if it changed), and its
@@ -1073,7 +1086,7 @@ template <typename R, bool HB, bool TR, bool VAR>
 __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restrict__ descs,
                                                      const WorkItem* __restrict__ items, int n_items,
                                                      int* __restrict__ item_ctr, int pend_trig,
-                                                     int ch_off) {
+                                                     int ch_off, int cum_off) {
   using PT = typename Pair<R>::T;
   extern __shared__ __align__(16) unsigned char smem[];
   PT* s_nu = reinterpret_cast<PT*>(smem);
@@ -1098,12 +1111,14 @@ __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restr
         s_nu[g] = q;
       }
       for (int c = threadIdx.x; c < d.nc; c += blockDim.x) s_ch[c] = d.chan[c];
+      stage_cum<R>(d, smem, cum_off);
       cur_inst = inst;
     }
     if (threadIdx.x == 0) s_next = 0;
     __syncthreads();
     Consts<R> C = load_consts<R>(d);
     C.chan = s_ch;
+    if (cum_off >= 0) C.cum = reinterpret_cast<const PT*>(smem + cum_off);
     const int64_t count = wi.count;
     Lane<R> L;
     L.state = ST_IDLE;
@@ -1304,7 +1319,7 @@ template <typename R, bool HB, bool VAR>
 __global__ void __launch_bounds__(512) k_swarm_pooled(const InstanceDesc* __restrict__ descs,
                                                       const WorkItem* __restrict__ items, int n_items,
                                                       int* __restrict__ item_ctr, int n_service,
-                                                      int ch_off, int pool_off) {
+                                                      int ch_off, int pool_off, int cum_off) {
   using PT = typename Pair<R>::T;
   extern __shared__ __align__(16) unsigned char smem[];
   PT* s_nu = reinterpret_cast<PT*>(smem);
@@ -1341,6 +1356,7 @@ __global__ void __launch_bounds__(512) k_swarm_pooled(const InstanceDesc* __rest
         s_nu[g] = q;
       }
       for (int c = threadIdx.x; c < d.nc; c += blockDim.x) s_ch[c] = d.chan[c];
+      stage_cum<R>(d, smem, cum_off);
       cur_inst = inst;
     }
     if (threadIdx.x == 0) {
@@ -1351,6 +1367,7 @@ __global__ void __launch_bounds__(512) k_swarm_pooled(const InstanceDesc* __rest
     __syncthreads();
     Consts<R> C = load_consts<R>(d);
     C.chan = s_ch;
+    if (cum_off >= 0) C.cum = reinterpret_cast<const PT*>(smem + cum_off);
     if (server) {
       // ---- service waves: two barriers per round, as the trial waves ----
       for (int round = 0;; ++round) {
@@ -1449,7 +1466,7 @@ __global__ void __launch_bounds__(512) k_swarm_pooled(const InstanceDesc* __rest
 // ---------------------------------------------------------------------------------------
 template <typename R, bool HB, bool TR, bool VAR>
 __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restrict__ desc, int pend_trig,
-                                                    int ch_off) {
+                                                    int ch_off, int cum_off) {
   using PT = typename Pair<R>::T;
   extern __shared__ __align__(16) unsigned char smem[];
   PT* s_nu = reinterpret_cast<PT*>(smem);
@@ -1464,10 +1481,12 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
       s_nu[g] = q;
     }
     for (int c = threadIdx.x; c < d.nc; c += blockDim.x) s_ch[c] = d.chan[c];
+    stage_cum<R>(d, smem, cum_off);
   }
   __syncthreads();
   Consts<R> C = load_consts<R>(d);
   C.chan = s_ch;
+  if (cum_off >= 0) C.cum = reinterpret_cast<const PT*>(smem + cum_off);
   RunCounters* ctr = d.ctr;
   const int64_t N = d.n_electrons;
   const int64_t child_cap = d.capacity - N;
@@ -1895,25 +1914,25 @@ size_t swarm_pool_slot_bytes(int precision) {
 hipError_t launch_swarm_dummy(const InstanceDesc* d_desc, const WorkItem* d_items, int32_t n_items,
                               int32_t* d_item_counter, int precision, bool has_b, bool trace,
                               bool var, int service_waves, int block_size, int grid, int pending_trigger,
-                              size_t lds_bytes, int ch_off, int pool_off, hipStream_t s) {
+                              size_t lds_bytes, int ch_off, int pool_off, int cum_off, hipStream_t s) {
   if (service_waves > 0 && !trace) {
     if (service_waves >= block_size / 64) return hipErrorInvalidValue;
     void* fn = pick_pooled(precision, has_b, var);
     void* args[] = {const_cast<InstanceDesc**>(&d_desc), const_cast<WorkItem**>(&d_items), &n_items,
-                    &d_item_counter, &service_waves, &ch_off, &pool_off};
+                    &d_item_counter, &service_waves, &ch_off, &pool_off, &cum_off};
     return hipLaunchKernel(fn, dim3(grid), dim3(block_size), args, lds_bytes, s);
   }
   void* fn = pick_kernel(precision, has_b, trace, false, var);
   void* args[] = {const_cast<InstanceDesc**>(&d_desc), const_cast<WorkItem**>(&d_items), &n_items,
-                  &d_item_counter, &pending_trigger, &ch_off};
+                  &d_item_counter, &pending_trigger, &ch_off, &cum_off};
   return hipLaunchKernel(fn, dim3(grid), dim3(block_size), args, lds_bytes, s);
 }
 
 hipError_t launch_swarm_real(const InstanceDesc* d_desc, int precision, bool has_b, bool trace,
                              bool var, int block_size, int grid, int pending_trigger, size_t lds_bytes,
-                             int ch_off, hipStream_t s) {
+                             int ch_off, int cum_off, hipStream_t s) {
   void* fn = pick_kernel(precision, has_b, trace, true, var);
-  void* args[] = {const_cast<InstanceDesc**>(&d_desc), &pending_trigger, &ch_off};
+  void* args[] = {const_cast<InstanceDesc**>(&d_desc), &pending_trigger, &ch_off, &cum_off};
   return hipLaunchKernel(fn, dim3(grid), dim3(block_size), args, lds_bytes, s);
 }
 

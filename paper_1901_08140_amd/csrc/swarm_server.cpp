@@ -237,7 +237,7 @@ void scheduler(swarm_server* s) {
       r->epochs += 1;
     }
     const swarm_launch_opts o = resolve_opts(&s->p.opts, s->p.precision);
-    const LdsLayout ll = lds_layout(s->p.precision, G, n_ch, o.service_waves);
+    const LdsLayout ll = lds_layout(s->p.precision, G, n_ch, o.service_waves, o.table_layout);
     const size_t lds = ll.bytes;
     const int per_cu = swarm_kernel_max_blocks_per_cu(s->p.precision, magnetic, false, false, variable,
                                                       o.service_waves, o.block_size, lds);
@@ -255,7 +255,7 @@ void scheduler(swarm_server* s) {
       ok = (e = launch_swarm_dummy(static_cast<const InstanceDesc*>(s->descs.p), static_cast<const WorkItem*>(s->items.p),
                                    static_cast<int32_t>(items.size()), item_ctr, s->p.precision, magnetic, false, variable,
                                    o.service_waves, o.block_size, grid, o.pending_trigger, lds, ll.ch_off,
-                                   ll.pool_off, s->compute)) == hipSuccess &&
+                                   ll.pool_off, ll.cum_off, s->compute)) == hipSuccess &&
            (e = hipEventRecord(ev1, s->compute)) == hipSuccess;
     }
     // while the epoch runs, prepare the requests that arrived meanwhile
