@@ -1186,8 +1186,9 @@ __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restr
 // lanes that found a real-collision candidate copy their state into a pool in LDS (one slot
 // per candidate, at most 64 per service wave; the others retry in the next round).  Between
 // the second and the third the service waves draw the scattering words, serve the pool, one
-// full wave per 64 candidates, and write the outcome back into the slots.  Only the schedule differs from k_swarm_dummy:
-// the streams and the per-electron arithmetic are the same, so the results are identical.
+// full wave per 64 candidates, and write the outcome back into the slots.  Only the schedule
+// differs from k_swarm_dummy: the streams and the per-electron arithmetic are the same, so
+// the results are identical.
 // ---------------------------------------------------------------------------------------
 
 // Pool layout: structure of arrays over `cap` slots (doubles, then working-precision
@@ -1369,7 +1370,7 @@ __global__ void __launch_bounds__(512) k_swarm_pooled(const InstanceDesc* __rest
     C.chan = s_ch;
     if (cum_off >= 0) C.cum = reinterpret_cast<const PT*>(smem + cum_off);
     if (server) {
-      // ---- service waves: two barriers per round, as the trial waves ----
+      // ---- service waves: the same three barriers per round as the trial waves ----
       for (int round = 0;; ++round) {
         __syncthreads();
         __syncthreads();
