@@ -31,9 +31,9 @@ EVENT_DTYPE = np.dtype({
     "offsets": [0, 8, 12, 16, 20, 24, 28, 32, 40, 48, 56],
     "itemsize": 80,
 })
-FLAG_FINISHED, FLAG_ATTACHED, FLAG_STUCK = 1, 2, 4
+FLAG_FINISHED, FLAG_ATTACHED, FLAG_STUCK, FLAG_RETRY_FAILED = 1, 2, 4, 16
 EV_REAL, EV_FORBIDDEN, EV_FAIL = 1, 2, 3
-CONSTANT_TRIAL, VARIABLE_TRIAL = 0, 1
+CONSTANT_TRIAL, VARIABLE_TRIAL, BINNED_TRIAL = 0, 1, 2
 TRIAL_HI, TRIAL_LO, SCAT_HI, SCAT_LO, INIT_HI, INIT_LO, CHILD_ID = range(7)
 
 
@@ -56,7 +56,8 @@ class _Params(ctypes.Structure):
                 ("secondaries", ctypes.c_int32), ("grid_P", ctypes.c_int32),
                 ("grid_emin", ctypes.c_int32), ("grid_emax", ctypes.c_int32),
                 ("user_majorant", ctypes.c_double), ("trial_strategy", ctypes.c_int32),
-                ("trial_zeta", ctypes.c_double), ("trial_grace", ctypes.c_int64)]
+                ("trial_zeta", ctypes.c_double), ("trial_grace", ctypes.c_int64),
+                ("trial_bins", ctypes.c_int32)]
 
 
 _lib = None
@@ -81,6 +82,7 @@ def lib():
             "or_n_channels": (i32, [vp]),
             "or_grid_size": (i32, [vp]),
             "or_majorant": (d, [vp]),
+            "or_bins": (i32, [vp, P(i32), P(d)]),
             "or_tables": (None, [vp, P(d), P(d)]),
             "or_sigma_raw": (d, [vp, i32, d]),
             "or_rate_raw_total": (d, [vp, d]),
@@ -185,7 +187,7 @@ class OracleModel:
     def __init__(self, components, E_V_per_m, B_T=0.0, B_angle_rad=0.0, N_per_m3=2.5e25,
                  T_K=293.0, init_energy_eV=0.1, secondaries=0, grid_P=64, grid_emin=-14,
                  grid_emax=12, user_majorant=0.0, trial_strategy=0, trial_zeta=0.25,
-                 trial_grace=5000):
+                 trial_grace=5000, trial_bins=10):
         L = lib()
         self._keep = []
         comps = (_Component * len(components))()
@@ -211,7 +213,7 @@ class OracleModel:
             comps[ci].mt_over_el = float(getattr(c, "mt_over_el", 1.0))
         p = _Params(E_V_per_m, B_T, B_angle_rad, N_per_m3, T_K, init_energy_eV, secondaries,
                     grid_P, grid_emin, grid_emax, user_majorant, trial_strategy, trial_zeta,
-                    trial_grace)
+                    trial_grace, trial_bins)
         st = ctypes.c_int32(0)
         self.h = L.or_create(comps, len(components), ctypes.byref(p), ctypes.byref(st))
         if not self.h:
@@ -225,6 +227,7 @@ class OracleModel:
         kw.setdefault("trial_strategy", cfg.trial_strategy)
         kw.setdefault("trial_zeta", cfg.trial_zeta)
         kw.setdefault("trial_grace", cfg.trial_grace)
+        kw.setdefault("trial_bins", cfg.trial_bins)
         return cls(cfg.components, cfg.E_V_per_m, cfg.B_T, cfg.B_angle_rad, cfg.N_per_m3, cfg.T_K,
                    cfg.init_energy_eV, cfg.secondaries, **kw)
 
@@ -245,6 +248,16 @@ class OracleModel:
     @property
     def majorant(self):
         return lib().or_majorant(self.h)
+
+    def bins(self):
+        """Binned strategy: (bin of every grid node, nu' of every bin)."""
+        n = lib().or_bins(self.h, None, None)
+        node_bin = np.zeros(self.grid_size if n else 0, dtype=np.int32)
+        nup = np.zeros(n)
+        if n:
+            lib().or_bins(self.h, node_bin.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                          nup.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        return node_bin, nup
 
     def tables(self):
         G, nc = self.grid_size, self.n_channels

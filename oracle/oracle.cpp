@@ -213,9 +213,11 @@ struct Params {
   int secondaries;  // 0 dummy (counted only), 1 real (children created / electrons removed)
   int grid_P, grid_emin, grid_emax;
   double user_majorant;
-  int trial_strategy;   // 0 constant nu' (lazy maximum or fixed), 1 variable (zeta, grace)
+  int trial_strategy;   // 0 constant nu' (lazy maximum or fixed), 1 variable (zeta, grace),
+                        // 2 binned (bins per decade, grace)
   double zeta;          // variable: nu' = (1 + zeta) nu(eps)
-  int64_t grace;        // variable: trials between updates of nu'
+  int64_t grace;        // variable and binned: trials between updates of nu'
+  int bins;             // binned: bins per decade of energy
 };
 
 struct Model {
@@ -225,6 +227,8 @@ struct Model {
   std::vector<double> nodes;   // G node energies (eV)
   std::vector<double> C;       // cumulative rate, channel-major: C[c*G + g]
   double majorant;
+  std::vector<int> node_bin;   // binned strategy: bin of every node (0 = the bin of node 0)
+  std::vector<double> bin_nup; // binned strategy: nu' of every bin
   double node_min, node_max;   // 2^emin, 2^emax
   // field frame
   double omega;                // e B / m
@@ -241,20 +245,26 @@ double node_energy(const Params& p, int g) {
 // "linear interpolation" after resampling on the octave grid).  Split eps = 2^(ex-1) (1+f)
 // exactly with frexp; i = floor(f P), w = f P - i, g = (ex-1-emin) P + i.
 // Below the grid: F[0].  At or above the top node: F[G-1] (counted as over the cap).
-double interp(const Model& m, const double* F, double eps, bool* over) {
-  if (over) *over = false;
-  if (eps < m.node_min) return F[0];
-  if (eps >= m.node_max) {
-    if (over) *over = true;
-    return F[m.G - 1];
-  }
+// locate() gives the lower node g of the cell holding eps and the weight w (energies below
+// the grid: node 0; at or above its top: node G-1; both with w = 0); interp() the value.
+int locate(const Model& m, double eps, double* w) {
+  *w = 0.0;
+  if (eps < m.node_min) return 0;
+  if (eps >= m.node_max) return m.G - 1;
   int ex = 0;
   const double mant = std::frexp(eps, &ex);        // eps = mant * 2^ex, mant in [0.5, 1)
   const double f = 2.0 * mant - 1.0;               // in [0, 1), exact
   const double fP = f * m.p.grid_P;                // exact (P is a power of two)
   const double fi = std::floor(fP);
-  const double w = fP - fi;                        // exact
-  const int g = (ex - 1 - m.p.grid_emin) * m.p.grid_P + static_cast<int>(fi);
+  *w = fP - fi;                                    // exact
+  return (ex - 1 - m.p.grid_emin) * m.p.grid_P + static_cast<int>(fi);
+}
+
+double interp(const Model& m, const double* F, double eps, bool* over) {
+  if (over) *over = eps >= m.node_max;
+  double w;
+  const int g = locate(m, eps, &w);
+  if (eps < m.node_min || eps >= m.node_max) return F[g];
   return F[g] + w * (F[g + 1] - F[g]);
 }
 
@@ -315,7 +325,9 @@ double energy_after_inelastic(double eps, double eps_k, double cos_t, double M) 
 // ---------------------------------------------------------------------------------------
 // Per-electron simulation.
 // ---------------------------------------------------------------------------------------
-constexpr uint32_t FLAG_FINISHED = 1, FLAG_ATTACHED = 2, FLAG_STUCK = 4;
+// FLAG_RETRY_FAILED: a binned-strategy retry failed again before its next real collision or
+// renewal, where the paper throws.  The electron goes on with the constant nu' instead.
+constexpr uint32_t FLAG_FINISHED = 1, FLAG_ATTACHED = 2, FLAG_STUCK = 4, FLAG_RETRY_FAILED = 16;
 constexpr uint64_t kMaxBlocks = 0x7fffffffull;   // per-electron cap on trial blocks
 constexpr int EV_REAL = 1, EV_FORBIDDEN = 2, EV_FAIL = 3;
 
@@ -357,6 +369,29 @@ struct RunCtx {
 // capped at the constant (lazy) maximum, which can never fail, so repeated fails end.
 double variable_nup(const Model& m, double nu) { return std::min((1.0 + m.p.zeta) * nu, m.majorant); }
 
+// The paper's BinnedTrialFrequency: the energy axis is cut into bins, b per decade, bin k
+// holding [10^(k/b), 10^((k+1)/b)) eV.  A grid cell belongs to the bin of its lower node, so
+// each bin is a run of whole cells, and its nu' is the largest total rate on those cells
+// (the rate is linear on a cell: the larger of its two end nodes), raised by 2^-20 as for
+// the constant strategy and capped at the constant value.
+int decade_bin(double eps, int b) { return static_cast<int>(std::floor(b * std::log10(eps))); }
+
+int bin_of(const Model& m, double eps) {
+  double w;
+  return m.node_bin[locate(m, eps, &w)];
+}
+
+double binned_nup(const Model& m, double eps) { return m.bin_nup[bin_of(m, eps)]; }
+
+// After a fail the electron retries from its last real collision with the largest nu' of
+// the bins from the one of that collision's energy to the one where the trial failed.
+double binned_retry_nup(const Model& m, double eps_anchor, double eps_fail) {
+  const int a = bin_of(m, eps_anchor), f = bin_of(m, eps_fail);
+  double v = 0.0;
+  for (int k = std::min(a, f); k <= std::max(a, f); ++k) v = std::max(v, m.bin_nup[k]);
+  return v;
+}
+
 bool traced(const RunCtx& cx, uint64_t id) {
   return std::find(cx.trace_ids.begin(), cx.trace_ids.end(), id) != cx.trace_ids.end();
 }
@@ -368,12 +403,22 @@ Record simulate(const RunCtx& cx, const Electron& e0, std::vector<Electron>& chi
                 std::vector<Event>& events) {
   const Model& m = *cx.m;
   const int nc = static_cast<int>(m.ch.size());
-  // Trial frequency: constant (lazy maximum or the user's fixed value), or the variable
-  // strategy: the first value from the birth energy, then updated after every `grace`
-  // trials (from the energy after the trial that used up the grace) and after every fail.
+  // Trial frequency: constant (lazy maximum or the user's fixed value), or the variable or
+  // binned strategy: the first value from the birth energy, then updated after every
+  // `grace` trials (from the energy after the trial that used up the grace) and after every
+  // fail.
   const bool variable = m.p.trial_strategy == 1;
-  double nup = variable ? variable_nup(m, nu_total(m, e0.eps_birth)) : m.majorant;
+  const bool binned = m.p.trial_strategy == 2;
+  const bool adaptive = variable || binned;
+  double nup = variable ? variable_nup(m, nu_total(m, e0.eps_birth))
+             : binned ? binned_nup(m, e0.eps_birth) : m.majorant;
   int64_t grace = m.p.grace;
+  bool retry = false;        // binned: nu' set by a fail, no real collision or renewal since
+  auto renew = [&](double eps_now, double nu_now) {
+    nup = binned ? binned_nup(m, eps_now) : variable_nup(m, nu_now);
+    grace = m.p.grace;
+    retry = false;
+  };
   Record rec{};
   rec.id = e0.id;
   rec.k_start = e0.k;
@@ -405,11 +450,12 @@ Record simulate(const RunCtx& cx, const Electron& e0, std::vector<Electron>& chi
       const double eps = energy_eV(vT);
       bool over = false;
       const double nu = nu_total(m, eps, &over);
-      if (variable && nu > nup) {
+      if (adaptive && nu > nup) {
         // Fail: nu(eps) <= nu' does not hold just before the candidate.  The electron goes
         // back to the state of its last real collision (the anchor: T = 0), a new nu' comes
-        // from the rate that failed, and the grace count restarts.  The fail uses up its
-        // trial and ends the block.
+        // from the rate that failed (variable) or from the bins between the anchor and the
+        // failing energy (binned), and the grace count restarts.  The fail uses up its trial
+        // and ends the block.
         ++rec.n_fail;
         if (tr && n_ev < cx.max_events) {
           Event ev{};
@@ -420,7 +466,17 @@ Record simulate(const RunCtx& cx, const Electron& e0, std::vector<Electron>& chi
           ++n_ev;
         }
         T = 0.0;
-        nup = variable_nup(m, nu);
+        if (binned) {
+          if (retry) {
+            rec.flags |= FLAG_RETRY_FAILED;
+            nup = m.majorant;
+          } else {
+            nup = binned_retry_nup(m, energy_eV(v), eps);
+          }
+          retry = true;
+        } else {
+          nup = variable_nup(m, nu);
+        }
         grace = m.p.grace;
         break;
       }
@@ -429,7 +485,7 @@ Record simulate(const RunCtx& cx, const Electron& e0, std::vector<Electron>& chi
       const double x = u_r * nup;
       if (!(x < nu)) {
         ++rec.n_null;
-        if (variable && --grace == 0) { nup = variable_nup(m, nu); grace = m.p.grace; }
+        if (adaptive && --grace == 0) renew(eps, nu);
         continue;
       }
       int c = 0;
@@ -440,7 +496,7 @@ Record simulate(const RunCtx& cx, const Electron& e0, std::vector<Electron>& chi
           eps < chn.threshold_eV * ((kMe + M) / M)) {
         // Kinematically forbidden just above threshold (grid smearing): treated as null.
         ++rec.n_forbidden;
-        if (variable && --grace == 0) { nup = variable_nup(m, nu); grace = m.p.grace; }
+        if (adaptive && --grace == 0) renew(eps, nu);
         if (tr && n_ev < cx.max_events) {
           Event ev{};
           ev.id = e0.id; ev.type = EV_FORBIDDEN; ev.channel = c; ev.k = k;
@@ -518,7 +574,8 @@ Record simulate(const RunCtx& cx, const Electron& e0, std::vector<Electron>& chi
       t += T;
       T = 0.0;
       v = scale(n, speed_from_energy(epsp));
-      if (variable && --grace == 0) { nup = variable_nup(m, nu_total(m, epsp)); grace = m.p.grace; }
+      retry = false;
+      if (adaptive && --grace == 0) renew(epsp, nu_total(m, epsp));
       break;
     }
   }
@@ -563,7 +620,8 @@ struct or_component { double mass_amu; double fraction; int32_t n_channels; cons
                       int32_t scattering; double mt_over_el; };
 struct or_params { double E_V_per_m, B_T, B_angle_rad, N_per_m3, T_K, init_energy_eV;
                    int32_t secondaries, grid_P, grid_emin, grid_emax; double user_majorant;
-                   int32_t trial_strategy; double trial_zeta; int64_t trial_grace; };
+                   int32_t trial_strategy; double trial_zeta; int64_t trial_grace;
+                   int32_t trial_bins; };
 
 enum { OR_OK = 0, OR_INVALID = -1, OR_CAPACITY = -3 };
 
@@ -585,14 +643,15 @@ void* or_create(const or_component* comps, int32_t n_comps, const or_params* p, 
   if (!(p->N_per_m3 > 0.0) || !(p->E_V_per_m >= 0.0) || !(p->B_T >= 0.0) || !(p->init_energy_eV >= 0.0))
     return nullptr;
   if (p->grid_P <= 0 || (p->grid_P & (p->grid_P - 1)) != 0 || p->grid_emax <= p->grid_emin) return nullptr;
-  if (p->trial_strategy < 0 || p->trial_strategy > 1) return nullptr;
+  if (p->trial_strategy < 0 || p->trial_strategy > 2) return nullptr;
   if (p->trial_strategy == 1 && (!(p->trial_zeta > 0.0) || !std::isfinite(p->trial_zeta) || p->trial_grace < 1))
     return nullptr;
+  if (p->trial_strategy == 2 && (p->trial_bins < 1 || p->trial_bins > 100 || p->trial_grace < 1)) return nullptr;
   double fsum = 0.0;
   auto* m = new Model();
   m->p = {p->E_V_per_m, p->B_T, p->B_angle_rad, p->N_per_m3, p->T_K, p->init_energy_eV,
           p->secondaries, p->grid_P, p->grid_emin, p->grid_emax, p->user_majorant,
-          p->trial_strategy, p->trial_zeta, p->trial_grace};
+          p->trial_strategy, p->trial_zeta, p->trial_grace, p->trial_bins};
   for (int k = 0; k < n_comps; ++k) {
     const or_component& c = comps[k];
     if (!(c.mass_amu > 0.0) || !(c.fraction >= 0.0) || c.n_channels <= 0) { delete m; return nullptr; }
@@ -650,6 +709,20 @@ void* or_create(const or_component* comps, int32_t n_comps, const or_params* p, 
   }
   m->node_min = std::ldexp(1.0, p->grid_emin);
   m->node_max = std::ldexp(1.0, p->grid_emax);
+  if (p->trial_strategy == 2) {
+    // bins of the nodes, counted from the bin of node 0, and the nu' of every bin
+    const int k0 = decade_bin(m->nodes[0], p->trial_bins);
+    m->node_bin.resize(m->G);
+    for (int g = 0; g < m->G; ++g) m->node_bin[g] = decade_bin(m->nodes[g], p->trial_bins) - k0;
+    std::vector<double> top(m->node_bin[m->G - 1] + 1, 0.0);
+    const double* F = &m->C[static_cast<size_t>(nc - 1) * m->G];
+    for (int g = 0; g < m->G; ++g) {
+      const double cell = g + 1 < m->G ? std::max(F[g], F[g + 1]) : F[g];
+      top[m->node_bin[g]] = std::max(top[m->node_bin[g]], cell);
+    }
+    m->bin_nup.resize(top.size());
+    for (size_t k = 0; k < top.size(); ++k) m->bin_nup[k] = std::min((1.0 + 0x1.0p-20) * top[k], m->majorant);
+  }
   m->omega = kQe * p->B_T / kMe;
   m->a = {0.0, 0.0, -kQe * p->E_V_per_m / kMe};
   m->bhat = {std::sin(p->B_angle_rad), 0.0, std::cos(p->B_angle_rad)};
@@ -669,6 +742,15 @@ void or_destroy(void* h) { delete static_cast<Model*>(h); }
 int32_t or_n_channels(void* h) { return static_cast<int32_t>(static_cast<Model*>(h)->ch.size()); }
 int32_t or_grid_size(void* h) { return static_cast<Model*>(h)->G; }
 double or_majorant(void* h) { return static_cast<Model*>(h)->majorant; }
+
+// Binned strategy: the bin of every node (G entries) and the nu' of every bin; returns the
+// number of bins (0 for the other strategies).  Either pointer may be NULL.
+int32_t or_bins(void* h, int32_t* node_bin, double* bin_nup) {
+  const Model& m = *static_cast<Model*>(h);
+  if (node_bin) std::copy(m.node_bin.begin(), m.node_bin.end(), node_bin);
+  if (bin_nup) std::copy(m.bin_nup.begin(), m.bin_nup.end(), bin_nup);
+  return static_cast<int32_t>(m.bin_nup.size());
+}
 
 void or_tables(void* h, double* nodes, double* C) {
   const Model& m = *static_cast<Model*>(h);

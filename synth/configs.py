@@ -38,9 +38,11 @@ class SwarmConfig:
     n_collisions: int = 1000
     seed: int = 0
     user_majorant: float = 0.0
-    trial_strategy: int = 0      # 0 constant trial frequency, 1 variable (zeta, grace)
+    trial_strategy: int = 0      # 0 constant trial frequency, 1 variable (zeta, grace),
+                                 # 2 binned (bins per decade, grace)
     trial_zeta: float = 0.25
     trial_grace: int = 5000
+    trial_bins: int = 10
     label: str = ""
     extra: dict = field(default_factory=dict)
 
