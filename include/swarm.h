@@ -71,10 +71,19 @@ typedef enum { SWARM_DUMMY = 0, SWARM_REAL = 1 } swarm_secondaries;
  * a trial at which nu(eps) > nu': the electron returns to the state right after its last
  * real collision, takes nu' = (1 + zeta) nu(eps) from the rate that failed, restarts the
  * grace count, and the fail ends its random-number block like a real collision.  The first
- * nu' of an electron comes from the energy it was created with.  This strategy trades
+ * nu' of an electron comes from the energy it was created with.  BINNED: the paper's
+ * BinnedTrialFrequency.  Each decade of energy (1-10 eV, 10-100 eV, ...) is cut into
+ * `trial_bins` bins evenly in log(eps): bin k = [10^(k/b), 10^((k+1)/b)) eV.  A cell of the
+ * rate grid belongs to the bin of its lower node, and a bin's nu' is the largest rate on its
+ * cells raised by 2^-20 (capped at the constant value).  Renewals as for VARIABLE take the
+ * nu' of the current energy's bin.  A fail returns the electron to its last real collision
+ * with the largest nu' of the bins from that collision's energy to the failing energy; a
+ * second fail before the next real collision or renewal, where the paper throws, sets
+ * record flag 16 and continues with the constant nu'.  Both adaptive strategies trade
  * exactness for fewer null trials: returning to the last real collision after a fail
  * favours flights that did not gain energy. */
-typedef enum { SWARM_TRIAL_CONSTANT = 0, SWARM_TRIAL_VARIABLE = 1 } swarm_trial_strategy;
+typedef enum { SWARM_TRIAL_CONSTANT = 0, SWARM_TRIAL_VARIABLE = 1,
+               SWARM_TRIAL_BINNED = 2 } swarm_trial_strategy;
 
 /* One cross-section table: n_points >= 2 strictly increasing energies (> 0, eV) and
  * cross-sections (>= 0, finite, m^2).  Extended outside the points as in section
@@ -131,7 +140,9 @@ typedef struct {
   void* stream;            /* hipStream_t or NULL */
   int32_t trial_strategy;  /* swarm_trial_strategy */
   double trial_zeta;       /* VARIABLE: the overhead zeta > 0; 0 = default 0.25 */
-  int64_t trial_grace;     /* VARIABLE: trials between renewals, 1 .. 2^31 - 1; 0 = 5000 */
+  int64_t trial_grace;     /* VARIABLE, BINNED: trials between renewals, 1 .. 2^31 - 1;
+                              0 = 5000 */
+  int32_t trial_bins;      /* BINNED: bins per decade of energy, 1 .. 100; 0 = 10 */
 } swarm_params;
 
 /* Per-electron result record (one per electron that existed in the run), as stored on
@@ -140,13 +151,15 @@ typedef struct {
   uint64_t id;             /* primaries: index; secondaries: 2^63 | hash of (parent, k) */
   uint32_t flags;          /* 1 finished (made all its real collisions), 2 attached,
                               4 stopped at the per-electron trial-block cap (2^31 - 1),
-                              8 stopped because the run exceeded its capacity */
+                              8 stopped because the run exceeded its capacity,
+                              16 a retry of the binned trial frequency failed again
+                              (the electron went on with the constant nu') */
   uint32_t k_start;        /* real collisions inherited from the lineage at birth */
   uint32_t k_end;          /* real-collision count when the electron stopped */
   uint32_t G, D;           /* ionisations and attachments made by this electron */
   uint32_t n_forbidden;    /* channel picks below the inelastic onset (treated as null) */
   uint32_t n_over;         /* real collisions above the top of the rate grid */
-  uint32_t n_fail;         /* fails of the variable trial frequency (0 otherwise) */
+  uint32_t n_fail;         /* fails of the variable or binned trial frequency */
   uint64_t n_null;         /* null trials */
   uint64_t blocks;         /* random-number blocks used (two candidate trials each) */
   double r[3], t;

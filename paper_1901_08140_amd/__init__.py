@@ -23,7 +23,7 @@ SWARM_ERR_DEVICE, SWARM_ERR_STATE, SWARM_PENDING = -4, -5, 1
 SWARM_ELASTIC, SWARM_EXCITATION, SWARM_IONIZATION, SWARM_ATTACHMENT = 0, 1, 2, 3
 SWARM_FP64, SWARM_FP32_MIXED = 0, 1
 SWARM_DUMMY, SWARM_REAL = 0, 1
-SWARM_TRIAL_CONSTANT, SWARM_TRIAL_VARIABLE = 0, 1
+SWARM_TRIAL_CONSTANT, SWARM_TRIAL_VARIABLE, SWARM_TRIAL_BINNED = 0, 1, 2
 SWARM_SCATTER_ISOTROPIC, SWARM_SCATTER_SCREENED_COULOMB, SWARM_SCATTER_CONSTANT_XI = 0, 1, 2
 
 if not os.path.exists(LIB_PATH):
@@ -49,7 +49,8 @@ class swarm_params(ctypes.Structure):
                 ("init_energy_eV", _d), ("precision", _i32), ("secondaries", _i32),
                 ("grid_points_per_octave", _i32), ("grid_min_exp2", _i32), ("grid_max_exp2", _i32),
                 ("user_majorant", _d), ("capacity", _i64), ("stream", _vp),
-                ("trial_strategy", _i32), ("trial_zeta", _d), ("trial_grace", _i64)]
+                ("trial_strategy", _i32), ("trial_zeta", _d), ("trial_grace", _i64),
+                ("trial_bins", _i32)]
 
 
 class swarm_stat(ctypes.Structure):
@@ -186,7 +187,7 @@ class _Marshalled:
 def make_params(E_V_per_m, B_T=0.0, B_angle_rad=0.0, N_per_m3=2.5e25, T_K=293.0, init_energy_eV=0.1,
                 precision=SWARM_FP64, secondaries=SWARM_DUMMY, grid_points_per_octave=0, grid_min_exp2=0,
                 grid_max_exp2=0, user_majorant=0.0, capacity=0, stream=None,
-                trial_strategy=0, trial_zeta=0.0, trial_grace=0):
+                trial_strategy=0, trial_zeta=0.0, trial_grace=0, trial_bins=0):
     p = swarm_params()
     p.E_V_per_m, p.B_T, p.B_angle_rad, p.N_per_m3, p.T_K = E_V_per_m, B_T, B_angle_rad, N_per_m3, T_K
     p.init_energy_eV, p.precision, p.secondaries = init_energy_eV, int(precision), int(secondaries)
@@ -194,6 +195,7 @@ def make_params(E_V_per_m, B_T=0.0, B_angle_rad=0.0, N_per_m3=2.5e25, T_K=293.0,
     p.user_majorant, p.capacity = user_majorant, int(capacity)
     p.stream = _stream_handle(stream)
     p.trial_strategy, p.trial_zeta, p.trial_grace = int(trial_strategy), float(trial_zeta), int(trial_grace)
+    p.trial_bins = int(trial_bins)
     return p
 
 
@@ -203,6 +205,7 @@ def params_from_config(cfg, precision=SWARM_FP64, **kw):
     kw.setdefault("trial_strategy", getattr(cfg, "trial_strategy", 0))
     kw.setdefault("trial_zeta", getattr(cfg, "trial_zeta", 0.0))
     kw.setdefault("trial_grace", getattr(cfg, "trial_grace", 0))
+    kw.setdefault("trial_bins", getattr(cfg, "trial_bins", 0))
     return make_params(cfg.E_V_per_m, cfg.B_T, cfg.B_angle_rad, cfg.N_per_m3, cfg.T_K, cfg.init_energy_eV,
                        precision, cfg.secondaries, **kw)
 

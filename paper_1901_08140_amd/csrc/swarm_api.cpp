@@ -102,6 +102,30 @@ hipError_t DevBuf::ensure(size_t n) {
 
 namespace {
 
+// Bins of the binned trial frequency (BinnedTrialFrequency, section "Trial frequency
+// strategies"): b per decade of energy, bin k = [10^(k/b), 10^((k+1)/b)) eV, counted from the
+// bin of the lowest grid node.  A grid cell belongs to the bin of its lower node.  The table
+// is indexed like the padded rate table of the kernels: entry 0 (below the grid) belongs to
+// node 0, entry g + 1 to node g (its cell, or for the top node the energies above it).
+// Bins are numbered from 0 to the top node's bin; on a coarse grid some hold no node (their
+// nu' is 0 and only the range maximum after a fail visits them).  Entries first[k] ..
+// first[k+1] - 1 are those of bin k (an empty range for an empty bin); first[n_bins] = G + 1.
+// Node energies are exact (a power of two times 1 + i/P); 1, 10, 100 and 1000 eV are nodes,
+// and log10 returns their exact logarithms, so those nodes open their bins.
+void decade_bins(int P, int emin, int G, int b, std::vector<int32_t>& entry_bin, std::vector<int32_t>& first) {
+  auto bin = [&](int g) {
+    const double e = std::ldexp(1.0 + static_cast<double>(g % P) / P, emin + g / P);
+    return static_cast<int32_t>(std::floor(std::log10(e) * b));
+  };
+  const int32_t k0 = bin(0);
+  entry_bin.assign(G + 1, 0);
+  for (int i = 1; i <= G; ++i) entry_bin[i] = bin(i - 1) - k0;
+  const int nb = entry_bin[G] + 1;
+  first.assign(nb + 1, G + 1);
+  for (int i = G; i >= 0; --i) first[entry_bin[i]] = i;
+  for (int k = nb - 1; k >= 0; --k) first[k] = std::min(first[k], first[k + 1]);
+}
+
 swarm_status validate(const swarm_component* comps, int32_t n_comps, const swarm_params* p) {
   if (!comps || n_comps <= 0) return fail(SWARM_ERR_INVALID_ARG, "need at least one component");
   if (!p) return fail(SWARM_ERR_INVALID_ARG, "params is NULL");
@@ -118,14 +142,17 @@ swarm_status validate(const swarm_component* comps, int32_t n_comps, const swarm
   if (!(p->user_majorant >= 0.0) || !std::isfinite(p->user_majorant))
     return fail(SWARM_ERR_INVALID_ARG, "user majorant must be >= 0");
   if (p->capacity < 0) return fail(SWARM_ERR_INVALID_ARG, "capacity must be >= 0");
-  if (p->trial_strategy != SWARM_TRIAL_CONSTANT && p->trial_strategy != SWARM_TRIAL_VARIABLE)
+  if (p->trial_strategy != SWARM_TRIAL_CONSTANT && p->trial_strategy != SWARM_TRIAL_VARIABLE &&
+      p->trial_strategy != SWARM_TRIAL_BINNED)
     return fail(SWARM_ERR_INVALID_ARG, "unknown trial strategy %d", p->trial_strategy);
   if (p->trial_strategy == SWARM_TRIAL_VARIABLE) {
     if (!(p->trial_zeta >= 0.0) || !std::isfinite(p->trial_zeta))
       return fail(SWARM_ERR_INVALID_ARG, "trial zeta must be finite and > 0 (0 = default)");
-    if (p->trial_grace < 0 || p->trial_grace > 0x7fffffffLL)
-      return fail(SWARM_ERR_INVALID_ARG, "trial grace must be in [1, 2^31 - 1] (0 = default)");
   }
+  if (p->trial_strategy != SWARM_TRIAL_CONSTANT && (p->trial_grace < 0 || p->trial_grace > 0x7fffffffLL))
+    return fail(SWARM_ERR_INVALID_ARG, "trial grace must be in [1, 2^31 - 1] (0 = default)");
+  if (p->trial_strategy == SWARM_TRIAL_BINNED && (p->trial_bins < 0 || p->trial_bins > 100))
+    return fail(SWARM_ERR_INVALID_ARG, "trial bins per decade must be in [1, 100] (0 = default)");
   const int P = p->grid_points_per_octave ? p->grid_points_per_octave : 64;
   if (P <= 0 || P > 1024 || (P & (P - 1)) != 0)
     return fail(SWARM_ERR_INVALID_ARG, "grid points per octave must be a power of two <= 1024");
@@ -355,6 +382,10 @@ swarm_status swarm_create(const swarm_component* comps, int32_t n_comps, const s
   d.trial_strategy = params->trial_strategy;
   d.trial_zeta = params->trial_zeta > 0.0 ? params->trial_zeta : 0.25;
   d.trial_grace = static_cast<uint32_t>(params->trial_grace > 0 ? params->trial_grace : 5000);
+  d.trial_bins = params->trial_bins > 0 ? params->trial_bins : 10;
+  std::vector<int32_t> entry_bin, bin_first;
+  if (params->trial_strategy == SWARM_TRIAL_BINNED) decade_bins(P, emin, G, d.trial_bins, entry_bin, bin_first);
+  d.n_bins = entry_bin.empty() ? 0 : static_cast<int32_t>(bin_first.size()) - 1;
   h->has_b = params->B_T > 0.0;
   // one arena for the raw inputs and the tables
   auto al = [](size_t n) { return (n + 255) & ~size_t(255); };
@@ -364,8 +395,10 @@ swarm_status swarm_create(const swarm_component* comps, int32_t n_comps, const s
   const size_t b_nu64 = al(static_cast<size_t>(G) * 16), b_nu32 = al(static_cast<size_t>(G) * 8);
   const size_t b_c64 = al(static_cast<size_t>(G) * nc * 16), b_c32 = al(static_cast<size_t>(G) * nc * 8);
   const size_t b_ch = al(nc * sizeof(ChannelDev));
+  const size_t b_eb = al(entry_bin.size() * 4), b_bf = al(bin_first.size() * 4);
+  const size_t b_bn = al(static_cast<size_t>(d.n_bins) * 8), b_bn32 = al(static_cast<size_t>(d.n_bins) * 4);
   const size_t total = b_e + b_s + 4 * b_i + b_cd + 4 * b_k + b_nodes + b_cm + b_nu64 + b_nu32 + b_c64 + b_c32 + b_ch +
-                       al(sizeof(InstanceDesc)) + al(sizeof(RunCounters));
+                       b_eb + b_bf + b_bn + b_bn32 + al(sizeof(InstanceDesc)) + al(sizeof(RunCounters));
   hipError_t e = h->arena.ensure(total);
   if (e != hipSuccess) return hip_fail(e, "allocating instance tables");
   char* base = static_cast<char*>(h->arena.p);
@@ -389,6 +422,12 @@ swarm_status swarm_create(const swarm_component* comps, int32_t n_comps, const s
   d.cum64 = reinterpret_cast<double2*>(take(b_c64));
   d.cum32 = reinterpret_cast<float2*>(take(b_c32));
   d.chan = reinterpret_cast<ChannelDev*>(take(b_ch));
+  int32_t* d_entry_bin = reinterpret_cast<int32_t*>(take(b_eb));
+  int32_t* d_bin_first = reinterpret_cast<int32_t*>(take(b_bf));
+  d.bin_of = d_entry_bin;
+  d.bin_first = d_bin_first;
+  d.bin_nup64 = reinterpret_cast<double*>(take(b_bn));
+  d.bin_nup32 = reinterpret_cast<float*>(take(b_bn32));
   h->d_desc = reinterpret_cast<InstanceDesc*>(take(al(sizeof(InstanceDesc))));
   d.ctr = reinterpret_cast<RunCounters*>(take(al(sizeof(RunCounters))));
   d.raw_e = d_e; d.raw_s = d_s; d.raw_off = d_off; d.raw_n = d_n; d.raw_kind = d_kind;
@@ -398,6 +437,7 @@ swarm_status swarm_create(const swarm_component* comps, int32_t n_comps, const s
 #define CP(dst, v) if ((e = hipMemcpyAsync(dst, v.data(), v.size() * sizeof(v[0]), hipMemcpyHostToDevice, s)) != hipSuccess) return hip_fail(e, "copying tables");
   CP(d_e, e_all) CP(d_s, s_all) CP(d_off, off) CP(d_n, npt) CP(d_kind, kind) CP(d_comp, comp)
   CP(d_thr, thr) CP(d_mass, mass) CP(d_frac, frac) CP(d_scat, scat) CP(d_ratio, ratio)
+  if (!entry_bin.empty()) { CP(d_entry_bin, entry_bin) CP(d_bin_first, bin_first) }
 #undef CP
   if ((e = launch_fill_u64(reinterpret_cast<uint64_t*>(d.ctr), 0, sizeof(RunCounters) / 8, s)) != hipSuccess)
     return hip_fail(e, "clearing counters");
@@ -512,7 +552,7 @@ swarm_status swarm_run(swarm_t h, int64_t n_electrons, int64_t n_collisions, uin
   const size_t lds = ll.bytes;
   const int ch_off = ll.ch_off;
   DeviceInfo& dev = device_info();
-  const bool var = d.trial_strategy == SWARM_TRIAL_VARIABLE;
+  const bool var = d.trial_strategy != SWARM_TRIAL_CONSTANT;
   const int per_cu = swarm_kernel_max_blocks_per_cu(d.precision, h->has_b, trace, real, var, svc, o.block_size, lds);
   if ((e = hipEventRecord(h->ev[0], s)) != hipSuccess) return hip_fail(e, "event");
   if (!real) {

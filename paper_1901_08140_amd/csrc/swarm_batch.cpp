@@ -87,7 +87,7 @@ swarm_status swarm_batch_create(swarm_t* handles, const swarm_job* jobs, int32_t
     for (int j = 0; j < i; ++j)
       if (handles[j] == h) return fail(SWARM_ERR_INVALID_ARG, "handle %d appears twice", i);
     b->magnetic |= h->has_b;
-    b->variable |= h->desc.trial_strategy == SWARM_TRIAL_VARIABLE;
+    b->variable |= h->desc.trial_strategy != SWARM_TRIAL_CONSTANT;
     G = std::max(G, h->desc.G);
     n_ch = std::max(n_ch, h->desc.nc);
     b->hs.push_back(h);

@@ -83,9 +83,13 @@ struct InstanceDesc {
   int32_t n_raw_channels;
   int32_t precision, secondaries;
   double E, B, B_angle, N, eps0, user_majorant;
-  int32_t trial_strategy;     // SWARM_TRIAL_CONSTANT or SWARM_TRIAL_VARIABLE
-  uint32_t trial_grace;       // variable: trials between updates of nu'
+  int32_t trial_strategy;     // swarm_trial_strategy
+  uint32_t trial_grace;       // variable and binned: trials between updates of nu'
   double trial_zeta;          // variable: nu' = (1 + zeta) nu(eps)
+  int32_t trial_bins;         // binned: bins per decade
+  int32_t n_bins;             // binned: number of bins (0 for the other strategies)
+  const int32_t* bin_of;      // binned: bin of every entry of the padded rate table (G + 1)
+  const int32_t* bin_first;   // binned: first table entry of every bin (n_bins + 1)
   const double* raw_e;        // concatenated raw energies
   const double* raw_s;        // concatenated raw cross-sections
   const int32_t* raw_off;     // per channel: first point
@@ -104,6 +108,8 @@ struct InstanceDesc {
   double2* cum64;             // G x nc pairs, node major
   float2* cum32;
   ChannelDev* chan;
+  double* bin_nup64;          // binned: nu' of every bin (built on the device)
+  float* bin_nup32;
   // run parameters
   int64_t n_electrons;
   uint32_t n_collisions;

@@ -401,6 +401,26 @@ __global__ void k_build_constants(InstanceDesc* desc) {
   }
 }
 
+// Binned trial frequency: the nu' of every bin, the largest total rate on its cells (a
+// cell's largest rate is at one of its end nodes; table entry 0 holds node 0 alone and entry
+// G the top node alone) raised by 2^-20 and capped at the constant value.  One thread per
+// bin, after k_build_constants.
+__global__ void k_build_bins(InstanceDesc* desc) {
+  const InstanceDesc& d = *desc;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= d.n_bins) return;
+  const double* F = d.cum_cm + static_cast<size_t>(d.nc - 1) * d.G;
+  double m = 0.0;
+  for (int i = d.bin_first[k]; i < d.bin_first[k + 1]; ++i) {
+    const int g = i == 0 ? 0 : i - 1;
+    m = fmax(m, F[g]);
+    if (i >= 1 && g + 1 < d.G) m = fmax(m, F[g + 1]);
+  }
+  const double v = fmin((1.0 + 0x1.0p-20) * m, d.majorant);
+  d.bin_nup64[k] = v;
+  d.bin_nup32[k] = static_cast<float>(v);
+}
+
 // Mark record slots as empty (id = all ones): real-secondaries runs that stop early leave
 // slots of queued secondaries unwritten, and the reductions skip empty slots.
 __global__ void k_mark_empty(swarm_record* r, int64_t n) {
@@ -438,7 +458,8 @@ struct Consts {
   R zeta1;       // variable trial frequency: 1 + zeta
   R eps0;        // initial energy of the primaries (eV)
   bool magnetic; // B > 0 (kernels built for B may also serve B = 0 instances)
-  bool variable; // variable trial frequency (otherwise the constant nu' above)
+  bool variable; // a per-lane trial frequency: the variable or the binned strategy
+  bool binned;   // the binned strategy
   uint32_t grace0;
   int G, nc, off, p;
   int off1;      // off - 1: raw index of entry 0 of the padded LDS table
@@ -447,6 +468,8 @@ struct Consts {
   Key key;
   const typename Pair<R>::T* cum;
   const ChannelDev* chan;
+  const int32_t* bin_of;   // binned: bin of every padded table entry
+  const R* bin_nup;        // binned: nu' of every bin
 };
 
 template <typename R>
@@ -473,7 +496,11 @@ __device__ __forceinline__ Consts<R> load_consts(const InstanceDesc& d) {
     c.Pf = d.Pf_f; c.twoPf = d.twoPf_f;
   }
   c.magnetic = d.B > 0.0;
-  c.variable = d.trial_strategy == SWARM_TRIAL_VARIABLE;
+  c.variable = d.trial_strategy != SWARM_TRIAL_CONSTANT;
+  c.binned = d.trial_strategy == SWARM_TRIAL_BINNED;
+  c.bin_of = d.bin_of;
+  if constexpr (sizeof(R) == 8) c.bin_nup = d.bin_nup64;
+  else c.bin_nup = d.bin_nup32;
   c.grace0 = d.trial_grace;
   c.zeta1 = static_cast<R>(1.0 + d.trial_zeta);
   c.eps0 = static_cast<R>(d.eps0);
@@ -592,9 +619,16 @@ __device__ __forceinline__ R energy_at(const Lane<R>& L, const Consts<R>& C, R T
 // exponent and leading mantissa bits, and w = frac(2 P mant) = frac((2 mant - 1) P) (the
 // product by the power of two 2P is exact).  The raw index (exponent and leading mantissa
 // bits, clamped to [off1, off1 + G]) is returned; the padded index is raw - off1.
+__device__ __forceinline__ int raw_index(float eps, const Consts<float>& C) {
+  return min(max(static_cast<int>(__float_as_uint(eps) >> (23 - C.p)), C.off1), C.off1G);
+}
+__device__ __forceinline__ int raw_index(double eps, const Consts<double>& C) {
+  const uint32_t hi = static_cast<uint32_t>(static_cast<uint64_t>(__double_as_longlong(eps)) >> 32);
+  return min(max(static_cast<int>(hi >> (20 - C.p)), C.off1), C.off1G);
+}
 __device__ __forceinline__ float lds_rate(const float2* __restrict__ s_nu, float eps, const Consts<float>& C,
                                          int* raw_out, float* w_out) {
-  const int raw = min(max(static_cast<int>(__float_as_uint(eps) >> (23 - C.p)), C.off1), C.off1G);
+  const int raw = raw_index(eps, C);
   const float w = __builtin_amdgcn_fractf(__builtin_amdgcn_frexp_mantf(eps) * C.twoPf);
   const float2 q = s_nu[raw - C.off1];
   *raw_out = raw;
@@ -603,8 +637,7 @@ __device__ __forceinline__ float lds_rate(const float2* __restrict__ s_nu, float
 }
 __device__ __forceinline__ double lds_rate(const double2* __restrict__ s_nu, double eps, const Consts<double>& C,
                                           int* raw_out, double* w_out) {
-  const uint32_t hi = static_cast<uint32_t>(static_cast<uint64_t>(__double_as_longlong(eps)) >> 32);
-  const int raw = min(max(static_cast<int>(hi >> (20 - C.p)), C.off1), C.off1G);
+  const int raw = raw_index(eps, C);
   const double w = __builtin_amdgcn_fract(__builtin_amdgcn_frexp_mant(eps) * C.twoPf);
   const double2 q = s_nu[raw - C.off1];
   *raw_out = raw;
@@ -612,19 +645,12 @@ __device__ __forceinline__ double lds_rate(const double2* __restrict__ s_nu, dou
   return q.x + w * q.y;
 }
 
-// Total rate at eps (no table position needed).
-template <typename R>
-__device__ __forceinline__ R rate_at(const typename Pair<R>::T* __restrict__ s_nu, R eps, const Consts<R>& C) {
-  int raw;
-  R w;
-  return lds_rate(s_nu, eps, C, &raw, &w);
-}
-
 // Trial frequency of a lane.  The constant strategy (the paper's LazyTrialFrequency or a
-// fixed value) uses the instance's nu'.  The variable strategy (section "Trial frequency
-// strategies", VariableTrialFrequency) sets nu' = (1 + zeta) nu(eps) from the total rate at
-// the current energy, capped at the constant value, which can never fail; it is renewed
-// after every `grace` trials and after every fail.
+// fixed value) uses the instance's nu'.  The adaptive strategies of section "Trial
+// frequency strategies" keep a per-lane nu', capped at the constant value (which can never
+// fail), renewed after every `grace` trials and set anew after every fail: the variable
+// strategy (VariableTrialFrequency) takes nu' = (1 + zeta) nu(eps) from the total rate at
+// the current energy, the binned one (BinnedTrialFrequency) the nu' of the energy's bin.
 template <typename R>
 __device__ __forceinline__ void constant_trial_frequency(Lane<R>& L, const Consts<R>& C) {
   L.nup = C.nup;
@@ -643,10 +669,42 @@ __device__ __forceinline__ void apply_trial_frequency(Lane<R>& L, const Consts<R
   }
 }
 template <typename R>
-__device__ __forceinline__ void variable_trial_frequency(Lane<R>& L, const Consts<R>& C, R nu) {
-  const R v = C.zeta1 * nu;
+__device__ __forceinline__ void set_trial_frequency(Lane<R>& L, const Consts<R>& C, R v) {
   if (v < C.nup) apply_trial_frequency(L, C, v);
   else constant_trial_frequency(L, C);     // at the cap: exactly the constant strategy
+}
+
+// Lane flag (never stored in a record): a binned retry is running, from a fail until the
+// next real collision or renewal.
+constexpr uint32_t kRetryFlag = 0x80000000u;
+
+// Renewal (and first value) at energy eps with total rate nu and padded table entry `entry`.
+template <typename R>
+__device__ __forceinline__ void renew_trial_frequency(Lane<R>& L, const Consts<R>& C, R nu, int entry) {
+  set_trial_frequency(L, C, C.binned ? C.bin_nup[C.bin_of[entry]] : C.zeta1 * nu);
+  L.grace = C.grace0;
+  L.flags &= ~kRetryFlag;
+}
+
+// After a fail at the candidate's energy (rate nu), with the lane back at its anchor.
+// Variable: (1 + zeta) nu from the rate that failed.  Binned: the largest nu' of the bins
+// from the anchor energy's bin to the failing energy's bin; a fail during that retry, where
+// the paper throws, sets record flag 16 and takes the constant nu'.
+template <typename R, bool HB>
+__device__ __forceinline__ void fail_trial_frequency(Lane<R>& L, const Consts<R>& C, R nu) {
+  if (!C.binned) {
+    set_trial_frequency(L, C, C.zeta1 * nu);
+  } else if (L.flags & kRetryFlag) {
+    L.flags |= 16u;
+    constant_trial_frequency(L, C);
+  } else {
+    const int a = C.bin_of[raw_index(energy_at<R, HB>(L, C, R(0)), C) - C.off1];
+    const int f = C.bin_of[L.p_gi - C.off1];
+    R v = R(0);
+    for (int k = min(a, f); k <= max(a, f); ++k) v = C.bin_nup[k] > v ? C.bin_nup[k] : v;
+    set_trial_frequency(L, C, v);
+    L.flags |= kRetryFlag;
+  }
   L.grace = C.grace0;
 }
 // VAR: the kernel is built for instances that may use the variable strategy.  Kernels
@@ -656,8 +714,14 @@ __device__ __forceinline__ void start_trial_frequency(Lane<R>& L, const Consts<R
                                                       const typename Pair<R>::T* __restrict__ s_nu, R eps) {
   L.nfail = 0;
   if constexpr (VAR) {
-    if (C.variable) variable_trial_frequency(L, C, rate_at<R>(s_nu, eps, C));
-    else constant_trial_frequency(L, C);
+    if (C.variable) {
+      int raw;
+      R w;
+      const R nu = lds_rate(s_nu, eps, C, &raw, &w);
+      renew_trial_frequency(L, C, nu, raw - C.off1);
+    } else {
+      constant_trial_frequency(L, C);
+    }
   }
 }
 
@@ -736,7 +800,7 @@ template <typename R>
 __device__ __forceinline__ void write_record(const InstanceDesc& d, const Lane<R>& L) {
   swarm_record r;
   r.id = L.id;
-  r.flags = L.flags;
+  r.flags = L.flags & ~kRetryFlag;
   r.k_start = L.k_start;
   r.k_end = L.k;
   r.G = L.G;
@@ -842,12 +906,12 @@ __device__ __forceinline__ bool one_trial(Lane<R>& L, const Consts<R>& C,
   }
   L.p_eps = energy_at<R, HB>(L, C, L.T);
   const R nu = lds_rate(s_nu, L.p_eps, C, &L.p_gi, &L.p_w);
-  // Not null when x < nu.  That includes nu > nu' (then x < nu' < nu), a fail of the
-  // variable strategy, which the collision phase tells apart.
+  // Not null when x < nu.  That includes nu > nu' (then x < nu' < nu), a fail of an
+  // adaptive strategy, which the collision phase tells apart.
   const bool hit = L.p_x < nu;
   if (VAR && C.variable) {
     L.grace -= 1u;
-    if (!hit && L.grace == 0u) variable_trial_frequency(L, C, nu);   // renewed after a null
+    if (!hit && L.grace == 0u) renew_trial_frequency(L, C, nu, L.p_gi - C.off1);   // after a null
   }
   return hit;
 }
@@ -920,11 +984,11 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
     nu_eps = lerp_pair(s_nu[L.p_gi - C.off1], L.p_w);
     if (nu_eps > L.nup) {
       // Fail: nu(eps) <= nu' does not hold.  Back to the state of the last real collision
-      // (the anchor: T = 0), a new nu' from the rate that failed, the grace count restarts.
+      // (the anchor: T = 0) with a new nu'; the grace count restarts.
       L.nfail += 1u;
       trace_event<R, TR>(d, L, 3, -1, eps, eps, L.t + static_cast<double>(L.T), L.rx, L.ry, L.rz);
       L.T = R(0);
-      variable_trial_frequency(L, C, nu_eps);
+      fail_trial_frequency<R, HB>(L, C, nu_eps);
       L.state = ST_ACTIVE;
       return RC_CONTINUE;
     }
@@ -973,7 +1037,7 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
     if (e64 < ch.onset) {
       L.nforb += 1;
       trace_event<R, TR>(d, L, 2, lo, eps, eps, L.t + static_cast<double>(L.T), L.rx, L.ry, L.rz);
-      if (VAR && C.variable && L.grace == 0u) variable_trial_frequency(L, C, nu_eps);   // as after a null
+      if (VAR && C.variable && L.grace == 0u) renew_trial_frequency(L, C, nu_eps, L.p_gi - C.off1);   // as after a null
       L.state = ST_ACTIVE;
       return RC_CONTINUE;
     }
@@ -1049,8 +1113,15 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
   L.T = R(0);
   const R sp = C.c_speed * sqrt_(epsp);
   L.vx = sp * nx; L.vy = sp * ny; L.vz = sp * nz;
-  // renewed after a real collision: from the energy after it
-  if (VAR && C.variable && L.grace == 0u) variable_trial_frequency(L, C, rate_at<R>(s_nu, epsp, C));
+  if (VAR && C.variable) {
+    L.flags &= ~kRetryFlag;     // a binned retry ends at the next real collision
+    if (L.grace == 0u) {        // renewed after a real collision: from the energy after it
+      int raw;
+      R w;
+      const R nu_n = lds_rate(s_nu, epsp, C, &raw, &w);
+      renew_trial_frequency(L, C, nu_n, raw - C.off1);
+    }
+  }
   if (removed) {
     L.flags |= 2u;
     return RC_STOP;
@@ -1883,6 +1954,7 @@ hipError_t launch_build(InstanceDesc* d_desc, const InstanceDesc& h, hipStream_t
   const int64_t n = static_cast<int64_t>(h.G) * h.nc;
   hipLaunchKernelGGL(k_build_pairs, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, d_desc);
   hipLaunchKernelGGL(k_build_constants, dim3(1), dim3(256), 0, s, d_desc);
+  if (h.n_bins > 0) hipLaunchKernelGGL(k_build_bins, dim3((h.n_bins + 63) / 64), dim3(64), 0, s, d_desc);
   return hipGetLastError();
 }
 

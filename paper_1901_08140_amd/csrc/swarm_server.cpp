@@ -38,6 +38,8 @@ struct ChannelCopy {
 struct ComponentCopy {
   double mass, frac;
   std::vector<ChannelCopy> ch;
+  int32_t scattering = SWARM_SCATTER_ISOTROPIC;
+  double mt_over_el = 1.0;
 };
 
 struct Request {
@@ -99,7 +101,9 @@ int64_t request_bytes(const Request& r) {
   int emin = r.params.grid_min_exp2, emax = r.params.grid_max_exp2;
   if (emin == 0 && emax == 0) { emin = -14; emax = 12; }
   const int64_t G = static_cast<int64_t>(emax - emin) * P + 1;
-  const int64_t tables = 16 * pts + G * (8 + 16 + 8) + G * nc * (8 + 16 + 8) + nc * 64 + 4096;
+  // (the binned strategy adds a bin of every table entry and at most 785 bins of 16 bytes)
+  const int64_t bins = r.params.trial_strategy == SWARM_TRIAL_BINNED ? 4 * (G + 1) + 16 * 1024 : 0;
+  const int64_t tables = 16 * pts + G * (8 + 16 + 8) + G * nc * (8 + 16 + 8) + nc * 128 + 8192 + bins;
   return tables + r.n_e * static_cast<int64_t>(sizeof(swarm_record) + sizeof(SavedState));
 }
 
@@ -109,7 +113,8 @@ swarm_status admit(swarm_server* s, const std::shared_ptr<Request>& r) {
   for (size_t k = 0; k < r->comps.size(); ++k) {
     for (auto& c : r->comps[k].ch)
       chs[k].push_back({c.kind, c.thr, static_cast<int32_t>(c.e.size()), c.e.data(), c.s.data()});
-    comps[k] = {r->comps[k].mass, r->comps[k].frac, static_cast<int32_t>(chs[k].size()), chs[k].data()};
+    comps[k] = {r->comps[k].mass, r->comps[k].frac, static_cast<int32_t>(chs[k].size()), chs[k].data(),
+                r->comps[k].scattering, r->comps[k].mt_over_el};
   }
   swarm_params p = r->params;
   p.precision = s->p.precision;
@@ -233,7 +238,7 @@ void scheduler(swarm_server* s) {
       G = std::max(G, d.G);
       n_ch = std::max(n_ch, d.nc);
       magnetic |= r->h->has_b;
-      variable |= d.trial_strategy == SWARM_TRIAL_VARIABLE;
+      variable |= d.trial_strategy != SWARM_TRIAL_CONSTANT;
       r->epochs += 1;
     }
     const swarm_launch_opts o = resolve_opts(&s->p.opts, s->p.precision);
@@ -352,6 +357,8 @@ swarm_status swarm_server_submit(swarm_server_t s, const swarm_component* comps,
     ComponentCopy c;
     c.mass = comps[k].mass_amu;
     c.frac = comps[k].fraction;
+    c.scattering = comps[k].scattering;
+    c.mt_over_el = comps[k].mt_over_el;
     for (int j = 0; j < comps[k].n_channels && comps[k].channels; ++j) {
       const swarm_channel& q = comps[k].channels[j];
       ChannelCopy ch;

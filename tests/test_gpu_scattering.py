@@ -3,6 +3,7 @@ xi form for molecules) on the GPU, through the C ABI, against the FP64 oracle: r
 event sequences element by element in FP64, FP32 tallies within the statistical tolerance,
 the Maxwell-gas drift eE/(m nu (1 - <cos>)) and batches that mix the models."""
 import math
+import time
 
 import numpy as np
 import pytest
@@ -114,3 +115,34 @@ def test_invalid_scattering_refused(gpu):
     cfg = _with(synth.cfg1_maxwell(), [(3,)])
     with pytest.raises(sw.SwarmError):
         sw.Swarm.from_config(cfg, sw.SWARM_FP64)
+
+
+def test_server_keeps_scattering_model(gpu):
+    """Served requests keep their components' scattering models: each equals its own run."""
+    sw = gpu
+    models = [[(1,)], [(2, 0.4)], [(0,)], [(1,)]]
+    reqs = []
+    for i, mdl in enumerate(models):
+        c = synth.cfg5_request(i).scaled(n_electrons=3000, n_collisions=600)
+        comps = [comp.with_scattering(*mdl[0]) for comp in c.components]
+        reqs.append(c.scaled(components=comps))
+    srv = sw.swarm_server_create(32 << 30, sw.SWARM_FP32_MIXED, quantum_collisions=200)
+    try:
+        tickets = [sw.swarm_server_submit(srv, c.components, sw.params_from_config(c, 1), c.n_electrons,
+                                          c.n_collisions, c.seed) for c in reqs]
+        t0 = time.time()
+        got = {}
+        while len(got) < len(tickets):
+            for t in tickets:
+                if t not in got:
+                    done, tal, _ = sw.swarm_server_poll(srv, t)
+                    if done:
+                        got[t] = tal
+            assert time.time() - t0 < 120
+            time.sleep(0.01)
+    finally:
+        sw.swarm_server_destroy(srv)
+    for t, c in zip(tickets, reqs):
+        s = sw.Swarm.from_config(c, sw.SWARM_FP32_MIXED)
+        s.run(c.n_electrons, c.n_collisions, c.seed)
+        assert got[t] == s.tallies(), c.label
