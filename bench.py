@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variable", action="store_true",
                     help="skip the leg with the variable trial frequency")
+    ap.add_argument("--no-binned", action="store_true",
+                    help="skip the leg with the binned trial frequency")
     ap.add_argument("--no-anisotropic", action="store_true",
                     help="skip the leg with screened-Coulomb scattering")
     ap.add_argument("--serve-rate", type=float, default=5.0)
@@ -175,12 +177,12 @@ def serve(sw, args):
         sw.swarm_server_destroy(srv)
 
 
-def variable_leg(sw, args, cfgs, jobs, opts, tall_const, ms_const, zeta=0.25, grace=5000):
-    """The same batched FP32 step with the paper's variable trial frequency (per-electron
-    nu' = (1 + zeta) nu(eps), renewed every `grace` trials and after fails): throughput,
-    efficiency, fails, and how far its tallies move from the exact constant-frequency run."""
-    hv = [sw.Swarm.from_config(c.scaled(trial_strategy=1, trial_zeta=zeta, trial_grace=grace),
-                               sw.SWARM_FP32_MIXED) for c in cfgs]
+def adaptive_leg(sw, args, cfgs, jobs, opts, tall_const, ms_const, strategy):
+    """The same batched FP32 step with one of the paper's adaptive trial frequencies
+    (variable: per-electron nu' = (1 + zeta) nu(eps); binned: the nu' of the energy's bin;
+    both renewed every `grace` trials and after fails): throughput, efficiency, fails, and
+    how far its tallies move from the exact constant-frequency run."""
+    hv = [sw.Swarm.from_config(c.scaled(**strategy), sw.SWARM_FP32_MIXED) for c in cfgs]
     b = sw.swarm_batch_create([h.h for h in hv], jobs, opts)
     try:
         sw.swarm_batch_launch(b)
@@ -202,12 +204,17 @@ def variable_leg(sw, args, cfgs, jobs, opts, tall_const, ms_const, zeta=0.25, gr
         rel = [(a[k][0] - c[k][0]) / abs(c[k][0]) for a, c in zip(tv, tall_const)
                if c[k][0] != 0 and math.isfinite(a[k][0]) and math.isfinite(c[k][0])]
         shift[k] = {"min": min(rel), "max": max(rel)} if rel else None
-    return {"value": real / (avg * 1e-3), "unit": "real collisions/s", "device_ms_per_step": avg,
-            "zeta": zeta, "grace": grace, "efficiency": real / trials,
-            "fails_per_real": sum(t["n_fail"] for t in tv) / real,
-            "speedup_vs_constant": ms_const / avg,
-            "within_tolerance_of_constant": f"{agree}/{len(keys) * len(cfgs)}",
-            "rel_shift_vs_constant": shift}
+    out = {"value": real / (avg * 1e-3), "unit": "real collisions/s", "device_ms_per_step": avg}
+    out.update({k: v for k, v in strategy.items() if k != "trial_strategy"})
+    out.update({"efficiency": real / trials, "fails_per_real": sum(t["n_fail"] for t in tv) / real,
+                "speedup_vs_constant": ms_const / avg,
+                "within_tolerance_of_constant": f"{agree}/{len(keys) * len(cfgs)}",
+                "rel_shift_vs_constant": shift})
+    if strategy["trial_strategy"] == 2:
+        # electrons whose retry failed again (flag 16: where the paper throws)
+        n16 = sum(int(((h.records()["flags"] & 16) != 0).sum()) for h in hv)
+        out["retry_failed_electron_fraction"] = n16 / sum(j[0] for j in jobs)
+    return out
 
 
 def anisotropic_leg(sw, args, cfgs, jobs, opts, tall_const, ms_const):
@@ -304,7 +311,11 @@ def main():
                      "ops_per_trial": OPS_PER_TRIAL, "ops_per_real": OPS_PER_REAL},
     }
     if not args.no_variable:
-        out["fp32_batched_variable"] = variable_leg(sw, args, cfgs, jobs, opts, tall32, avg_ms)
+        out["fp32_batched_variable"] = adaptive_leg(sw, args, cfgs, jobs, opts, tall32, avg_ms,
+                                                    dict(trial_strategy=1, trial_zeta=0.25, trial_grace=5000))
+    if not args.no_binned:
+        out["fp32_batched_binned"] = adaptive_leg(sw, args, cfgs, jobs, opts, tall32, avg_ms,
+                                                  dict(trial_strategy=2, trial_bins=10, trial_grace=5000))
         log(args, "variable trial frequency", out["fp32_batched_variable"])
     if not args.no_anisotropic:
         out["fp32_batched_screened_coulomb"] = anisotropic_leg(sw, args, cfgs, jobs, opts, tall32, avg_ms)
