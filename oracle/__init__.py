@@ -34,7 +34,7 @@ EVENT_DTYPE = np.dtype({
 FLAG_FINISHED, FLAG_ATTACHED, FLAG_STUCK, FLAG_RETRY_FAILED = 1, 2, 4, 16
 EV_REAL, EV_FORBIDDEN, EV_FAIL = 1, 2, 3
 CONSTANT_TRIAL, VARIABLE_TRIAL, BINNED_TRIAL = 0, 1, 2
-TRIAL_HI, TRIAL_LO, SCAT_HI, SCAT_LO, INIT_HI, INIT_LO, CHILD_ID = range(7)
+TRIAL_HI, TRIAL_LO, SCAT_HI, SCAT_LO, INIT_HI, INIT_LO, CHILD_ID, THERMAL_HI, THERMAL_LO = range(9)
 
 
 class _Channel(ctypes.Structure):
@@ -57,7 +57,7 @@ class _Params(ctypes.Structure):
                 ("grid_emin", ctypes.c_int32), ("grid_emax", ctypes.c_int32),
                 ("user_majorant", ctypes.c_double), ("trial_strategy", ctypes.c_int32),
                 ("trial_zeta", ctypes.c_double), ("trial_grace", ctypes.c_int64),
-                ("trial_bins", ctypes.c_int32)]
+                ("trial_bins", ctypes.c_int32), ("thermal_targets", ctypes.c_int32)]
 
 
 _lib = None
@@ -93,6 +93,8 @@ def lib():
             "or_energy_after": (d, [i32, d, d, d, d]),
             "or_const": (d, [i32]),
             "or_xi_from_ratio": (d, [d]),
+            "or_target_velocity": (None, [d, P(d), P(d)]),
+            "or_moving_target": (i32, [P(d), P(d), d, d, P(d), P(d)]),
             "or_mt_over_el_of_xi": (d, [d]),
             "or_scatter_cos": (d, [i32, d, d, d]),
             "or_rotate": (None, [P(d), d, d, P(d)]),
@@ -147,6 +149,29 @@ def energy_after(kind, eps, eps_k, cos_t, mass_amu):
 ISOTROPIC, SCREENED_COULOMB, CONSTANT_XI = 0, 1, 2
 
 
+def boltzmann():
+    return lib().or_const(4)
+
+
+def target_velocity(sigma, u):
+    """Velocity of a moving target: three normals of spread sigma from four uniforms."""
+    P = ctypes.POINTER(ctypes.c_double)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.zeros(3)
+    lib().or_target_velocity(sigma, u.ctypes.data_as(P), out.ctypes.data_as(P))
+    return out
+
+
+def moving_target(V1, V2, mass_amu, eps_k_eV, u_hat):
+    """Electron velocity after a collision with a target moving at V2 (None if forbidden)."""
+    P = ctypes.POINTER(ctypes.c_double)
+    a, b, h = (np.ascontiguousarray(x, dtype=np.float64) for x in (V1, V2, u_hat))
+    out = np.zeros(3)
+    ok = lib().or_moving_target(a.ctypes.data_as(P), b.ctypes.data_as(P), mass_amu, eps_k_eV,
+                                h.ctypes.data_as(P), out.ctypes.data_as(P))
+    return out if ok else None
+
+
 def hartree_eV():
     return lib().or_const(3)
 
@@ -187,7 +212,7 @@ class OracleModel:
     def __init__(self, components, E_V_per_m, B_T=0.0, B_angle_rad=0.0, N_per_m3=2.5e25,
                  T_K=293.0, init_energy_eV=0.1, secondaries=0, grid_P=64, grid_emin=-14,
                  grid_emax=12, user_majorant=0.0, trial_strategy=0, trial_zeta=0.25,
-                 trial_grace=5000, trial_bins=10):
+                 trial_grace=5000, trial_bins=10, thermal_targets=0):
         L = lib()
         self._keep = []
         comps = (_Component * len(components))()
@@ -213,7 +238,7 @@ class OracleModel:
             comps[ci].mt_over_el = float(getattr(c, "mt_over_el", 1.0))
         p = _Params(E_V_per_m, B_T, B_angle_rad, N_per_m3, T_K, init_energy_eV, secondaries,
                     grid_P, grid_emin, grid_emax, user_majorant, trial_strategy, trial_zeta,
-                    trial_grace, trial_bins)
+                    trial_grace, trial_bins, thermal_targets)
         st = ctypes.c_int32(0)
         self.h = L.or_create(comps, len(components), ctypes.byref(p), ctypes.byref(st))
         if not self.h:
@@ -228,6 +253,7 @@ class OracleModel:
         kw.setdefault("trial_zeta", cfg.trial_zeta)
         kw.setdefault("trial_grace", cfg.trial_grace)
         kw.setdefault("trial_bins", cfg.trial_bins)
+        kw.setdefault("thermal_targets", cfg.thermal_targets)
         return cls(cfg.components, cfg.E_V_per_m, cfg.B_T, cfg.B_angle_rad, cfg.N_per_m3, cfg.T_K,
                    cfg.init_energy_eV, cfg.secondaries, **kw)
 

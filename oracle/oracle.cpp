@@ -41,6 +41,7 @@ constexpr double kMe = 9.1093837015e-31;    // kg
 constexpr double kAmu = 1.66053906660e-27;  // kg
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kHartreeEV = 27.211386245988;   // Hartree energy in eV (CODATA 2018)
+constexpr double kKb = 1.380649e-23;         // J/K
 
 enum Kind { ELASTIC = 0, EXCITATION = 1, IONIZATION = 2, ATTACHMENT = 3 };
 
@@ -76,7 +77,7 @@ Words philox4x32_10(const uint32_t ctr[4], const uint32_t key[2]) {
 
 // Stream layout: key = (lo32(seed), hi32(seed)); counter = (block, tag, lo32(id), hi32(id)).
 enum Tag : uint32_t { TRIAL_HI = 0, TRIAL_LO = 1, SCAT_HI = 2, SCAT_LO = 3, INIT_HI = 4,
-                      INIT_LO = 5, CHILD_ID = 6 };
+                      INIT_LO = 5, CHILD_ID = 6, THERMAL_HI = 7, THERMAL_LO = 8 };
 
 Words stream_block(uint64_t seed, uint64_t id, uint32_t tag, uint32_t block) {
   const uint32_t ctr[4] = {block, tag, static_cast<uint32_t>(id), static_cast<uint32_t>(id >> 32)};
@@ -134,6 +135,7 @@ struct Channel {
   double density;             // n_k = fraction_k * N
   int scattering;             // of its component: 0 isotropic, 1 screened Coulomb, 2 constant xi
   double xi;                  // scattering 2: the anisotropy parameter
+  double thermal_sigma;       // moving targets: sqrt(k T / M), each velocity component's spread
 };
 
 // Okhrimovskyy anisotropic scattering (section "Theoretical framework", eqs. collision_angle
@@ -218,6 +220,7 @@ struct Params {
   double zeta;          // variable: nu' = (1 + zeta) nu(eps)
   int64_t grace;        // variable and binned: trials between updates of nu'
   int bins;             // binned: bins per decade of energy
+  int thermal;          // 1: targets move (Maxwell-Boltzmann at temperature T), 0: at rest
 };
 
 struct Model {
@@ -320,6 +323,30 @@ double energy_after_inelastic(double eps, double eps_k, double cos_t, double M) 
   const double ratio = eps_k / eps;
   const double root = std::sqrt(std::max(0.0, 1.0 - (m + M) / M * ratio));
   return eps * (1.0 - M / (m + M) * ratio + 2.0 * m * M / ((m + M) * (m + M)) * (root * cos_t - 1.0));
+}
+
+// Velocity of the target in a collision with moving targets (section "Effect of gas
+// temperature"): the gas molecules have the Maxwell-Boltzmann distribution of temperature T,
+// so each Cartesian component is normal with standard deviation sigma = sqrt(k T / M).  The
+// three normals come from four uniforms by the Box-Muller transform.
+Vec3 target_velocity(double sigma, double u0, double u1, double u2, double u3) {
+  const double r01 = std::sqrt(-2.0 * std::log(1.0 - u0));
+  const double r23 = std::sqrt(-2.0 * std::log(1.0 - u2));
+  return {sigma * r01 * std::cos(2.0 * kPi * u1), sigma * r01 * std::sin(2.0 * kPi * u1),
+          sigma * r23 * std::cos(2.0 * kPi * u3)};
+}
+
+// The paper's equation for the electron (V1') in a collision with a target moving at V2:
+// with Vcm = (m V1 + M V2)/(m + M), the electron's speed in the centre-of-momentum frame
+// |V1 - Vcm| becomes sqrt(|V1 - Vcm|^2 - 2 eps_k M / ((m + M) m)), in the direction u_hat
+// there.  cm_speed2() is the argument of that root: negative when the energy in that frame is
+// below the threshold eps_k (joule), and the process cannot happen.
+double cm_speed2(Vec3 V1, Vec3 Vcm, double M, double eps_k_J) {
+  const Vec3 u1 = sub(V1, Vcm);
+  return dot(u1, u1) - 2.0 * eps_k_J / (kMe + M) * (M / kMe);
+}
+Vec3 centre_of_momentum(Vec3 V1, Vec3 V2, double M) {
+  return scale(add(scale(V1, kMe), scale(V2, M)), 1.0 / (kMe + M));
 }
 
 // ---------------------------------------------------------------------------------------
@@ -492,9 +519,26 @@ Record simulate(const RunCtx& cx, const Electron& e0, std::vector<Electron>& chi
       while (c < nc - 1 && !(x < interp(m, &m.C[static_cast<size_t>(c) * m.G], eps, nullptr))) ++c;
       const Channel& chn = m.ch[c];
       const double M = chn.mass_kg;
-      if ((chn.kind == EXCITATION || chn.kind == IONIZATION) &&
-          eps < chn.threshold_eV * ((kMe + M) / M)) {
-        // Kinematically forbidden just above threshold (grid smearing): treated as null.
+      const double eps_k_J = (chn.kind == EXCITATION || chn.kind == IONIZATION) ? chn.threshold_eV * kQe : 0.0;
+      // Moving targets: the target velocity of this collision (THERMAL block k) and the
+      // electron's squared speed in the centre-of-momentum frame after the threshold loss.
+      Vec3 Vcm{0.0, 0.0, 0.0};
+      double g2 = 0.0;
+      if (m.p.thermal) {
+        const Words th = stream_block(cx.seed, e0.id, THERMAL_HI, k);
+        const Words tl = stream_block(cx.seed, e0.id, THERMAL_LO, k);
+        const Vec3 V2 = target_velocity(chn.thermal_sigma, uniform53(th.w[0], tl.w[0]), uniform53(th.w[1], tl.w[1]),
+                                        uniform53(th.w[2], tl.w[2]), uniform53(th.w[3], tl.w[3]));
+        Vcm = centre_of_momentum(vT, V2, M);
+        g2 = cm_speed2(vT, Vcm, M, eps_k_J);
+      }
+      const bool forbidden =
+          m.p.thermal ? (chn.kind != ATTACHMENT && g2 < 0.0)
+                      : ((chn.kind == EXCITATION || chn.kind == IONIZATION) &&
+                         eps < chn.threshold_eV * ((kMe + M) / M));
+      if (forbidden) {
+        // Kinematically forbidden: just above threshold (grid smearing), or with moving
+        // targets below the threshold in the centre-of-momentum frame.  Treated as null.
         ++rec.n_forbidden;
         if (adaptive && --grace == 0) renew(eps, nu);
         if (tr && n_ev < cx.max_events) {
@@ -515,8 +559,25 @@ Record simulate(const RunCtx& cx, const Electron& e0, std::vector<Electron>& chi
       const Words sl = stream_block(cx.seed, e0.id, SCAT_LO, k);
       const double v2 = dot(vT, vT);
       Vec3 n;
-      double cos_t;
-      if (chn.scattering == 0 || !(v2 > 0.0)) {
+      double cos_t = 0.0;
+      double epsp;
+      if (m.p.thermal) {
+        // Moving target: the new direction in the centre-of-momentum frame (isotropic, or
+        // theta about the incoming relative direction), then back to the laboratory.
+        const Vec3 u1 = ::sub(vT, Vcm);   // (the block loop's `sub` hides the function)
+        const double g = std::sqrt(dot(u1, u1));
+        Vec3 uh;
+        if (chn.scattering == 0 || !(g > 0.0)) {
+          uh = iso_direction(uniform53(sh.w[0], sl.w[0]), uniform53(sh.w[1], sl.w[1]));
+        } else {
+          cos_t = scatter_cos(chn.scattering, chn.xi, eps, uniform53(sh.w[0], sl.w[0]));
+          uh = rotate_direction(scale(u1, 1.0 / g), cos_t, 2.0 * kPi * uniform53(sh.w[1], sl.w[1]));
+        }
+        const Vec3 V1p = add(Vcm, scale(uh, std::sqrt(std::max(g2, 0.0))));
+        const double s1 = std::sqrt(dot(V1p, V1p));
+        n = s1 > 0.0 ? scale(V1p, 1.0 / s1) : uh;
+        epsp = chn.kind == ATTACHMENT ? 0.0 : energy_eV(V1p);
+      } else if (chn.scattering == 0 || !(v2 > 0.0)) {
         // isotropic in the lab frame; theta is the angle to the incoming velocity
         n = iso_direction(uniform53(sh.w[0], sl.w[0]), uniform53(sh.w[1], sl.w[1]));
         cos_t = v2 > 0.0 ? dot(n, vT) / std::sqrt(v2) : 0.0;
@@ -525,8 +586,9 @@ Record simulate(const RunCtx& cx, const Electron& e0, std::vector<Electron>& chi
         cos_t = scatter_cos(chn.scattering, chn.xi, eps, uniform53(sh.w[0], sl.w[0]));
         n = rotate_direction(scale(vT, 1.0 / std::sqrt(v2)), cos_t, 2.0 * kPi * uniform53(sh.w[1], sl.w[1]));
       }
-      double epsp;
-      if (chn.kind == ELASTIC) {
+      if (m.p.thermal) {
+        // (epsp set above)
+      } else if (chn.kind == ELASTIC) {
         epsp = energy_after_elastic(eps, cos_t, M);
       } else if (chn.kind == ATTACHMENT) {
         epsp = 0.0;   // plastic collision: all the energy is transferred
@@ -621,7 +683,7 @@ struct or_component { double mass_amu; double fraction; int32_t n_channels; cons
 struct or_params { double E_V_per_m, B_T, B_angle_rad, N_per_m3, T_K, init_energy_eV;
                    int32_t secondaries, grid_P, grid_emin, grid_emax; double user_majorant;
                    int32_t trial_strategy; double trial_zeta; int64_t trial_grace;
-                   int32_t trial_bins; };
+                   int32_t trial_bins; int32_t thermal_targets; };
 
 enum { OR_OK = 0, OR_INVALID = -1, OR_CAPACITY = -3 };
 
@@ -647,11 +709,12 @@ void* or_create(const or_component* comps, int32_t n_comps, const or_params* p, 
   if (p->trial_strategy == 1 && (!(p->trial_zeta > 0.0) || !std::isfinite(p->trial_zeta) || p->trial_grace < 1))
     return nullptr;
   if (p->trial_strategy == 2 && (p->trial_bins < 1 || p->trial_bins > 100 || p->trial_grace < 1)) return nullptr;
+  if (p->thermal_targets < 0 || p->thermal_targets > 1 || !(p->T_K >= 0.0) || !std::isfinite(p->T_K)) return nullptr;
   double fsum = 0.0;
   auto* m = new Model();
   m->p = {p->E_V_per_m, p->B_T, p->B_angle_rad, p->N_per_m3, p->T_K, p->init_energy_eV,
           p->secondaries, p->grid_P, p->grid_emin, p->grid_emax, p->user_majorant,
-          p->trial_strategy, p->trial_zeta, p->trial_grace, p->trial_bins};
+          p->trial_strategy, p->trial_zeta, p->trial_grace, p->trial_bins, p->thermal_targets};
   for (int k = 0; k < n_comps; ++k) {
     const or_component& c = comps[k];
     if (!(c.mass_amu > 0.0) || !(c.fraction >= 0.0) || c.n_channels <= 0) { delete m; return nullptr; }
@@ -678,6 +741,7 @@ void* or_create(const or_component* comps, int32_t n_comps, const or_params* p, 
       ch.xi = xi;
       ch.mass_kg = c.mass_amu * kAmu;
       ch.density = c.fraction * p->N_per_m3;
+      ch.thermal_sigma = std::sqrt(kKb * p->T_K / ch.mass_kg);
       m->ch.push_back(std::move(ch));
     }
   }
@@ -801,6 +865,25 @@ double or_energy_after(int32_t kind, double eps, double eps_k, double cos_t, dou
 }
 
 double or_xi_from_ratio(double r) { return xi_from_ratio(r); }
+
+// Moving-target kinematics: the target velocity from four uniforms, and the electron's
+// velocity after a collision with a target of mass_amu moving at V2 (direction u_hat in the
+// centre-of-momentum frame, threshold eps_k_eV); returns 0 when the process cannot happen.
+void or_target_velocity(double sigma, const double* u, double* out) {
+  const Vec3 v = target_velocity(sigma, u[0], u[1], u[2], u[3]);
+  out[0] = v.x; out[1] = v.y; out[2] = v.z;
+}
+int32_t or_moving_target(const double* V1, const double* V2, double mass_amu, double eps_k_eV,
+                         const double* u_hat, double* V1p) {
+  const double M = mass_amu * kAmu;
+  const Vec3 a{V1[0], V1[1], V1[2]}, b{V2[0], V2[1], V2[2]}, uh{u_hat[0], u_hat[1], u_hat[2]};
+  const Vec3 Vcm = centre_of_momentum(a, b, M);
+  const double g2 = cm_speed2(a, Vcm, M, eps_k_eV * kQe);
+  if (g2 < 0.0) return 0;
+  const Vec3 r = add(Vcm, scale(uh, std::sqrt(g2)));
+  V1p[0] = r.x; V1p[1] = r.y; V1p[2] = r.z;
+  return 1;
+}
 double or_mt_over_el_of_xi(double xi) { return mt_over_el_of_xi(xi); }
 double or_scatter_cos(int32_t scattering, double xi, double eps_eV, double u) {
   return scatter_cos(scattering, xi, eps_eV, u);
@@ -816,6 +899,7 @@ double or_const(int32_t which) {
     case 1: return kMe;
     case 2: return kAmu;
     case 3: return kHartreeEV;
+    case 4: return kKb;
     default: return 0.0;
   }
 }

@@ -43,6 +43,7 @@ class SwarmConfig:
     trial_zeta: float = 0.25
     trial_grace: int = 5000
     trial_bins: int = 10
+    thermal_targets: int = 0     # 1: targets with Maxwell-Boltzmann velocities at T_K
     label: str = ""
     extra: dict = field(default_factory=dict)
 
