@@ -125,7 +125,8 @@ typedef struct {
   double B_T;              /* >= 0 */
   double B_angle_rad;      /* angle of B from E, B in the xz plane */
   double N_per_m3;         /* gas number density, > 0 */
-  double T_K;              /* gas temperature (targets are at rest; bookkeeping only) */
+  double T_K;              /* gas temperature (K, >= 0): the targets' Maxwell-Boltzmann
+                              temperature with thermal_targets, else bookkeeping only */
   double init_energy_eV;   /* energy of the primaries, isotropic directions; >= 0 */
   int32_t precision;       /* swarm_precision */
   int32_t secondaries;     /* swarm_secondaries */
@@ -143,6 +144,17 @@ typedef struct {
   int64_t trial_grace;     /* VARIABLE, BINNED: trials between renewals, 1 .. 2^31 - 1;
                               0 = 5000 */
   int32_t trial_bins;      /* BINNED: bins per decade of energy, 1 .. 100; 0 = 10 */
+  int32_t thermal_targets; /* 0: targets at rest (eqs. delta_energy_ela / delta_energy_ine);
+                              1: moving targets (section "Effect of gas temperature").  At a
+                              real collision the target velocity is drawn from the
+                              Maxwell-Boltzmann distribution at T_K (three normals of spread
+                              sqrt(kT/M), Box-Muller on its own random stream) and the
+                              electron's velocity becomes Vcm + sqrt(|V1 - Vcm|^2 - 2 eps_k M /
+                              ((m + M) m)) u, u its new direction in the centre-of-momentum
+                              frame (isotropic, or theta about V1 - Vcm for the anisotropic
+                              models).  A process below its threshold in that frame is
+                              forbidden (counted in n_forbidden).  Rates and the null test keep
+                              the laboratory energy. */
 } swarm_params;
 
 /* Per-electron result record (one per electron that existed in the run), as stored on

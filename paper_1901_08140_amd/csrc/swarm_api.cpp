@@ -153,6 +153,10 @@ swarm_status validate(const swarm_component* comps, int32_t n_comps, const swarm
     return fail(SWARM_ERR_INVALID_ARG, "trial grace must be in [1, 2^31 - 1] (0 = default)");
   if (p->trial_strategy == SWARM_TRIAL_BINNED && (p->trial_bins < 0 || p->trial_bins > 100))
     return fail(SWARM_ERR_INVALID_ARG, "trial bins per decade must be in [1, 100] (0 = default)");
+  if (p->thermal_targets != 0 && p->thermal_targets != 1)
+    return fail(SWARM_ERR_INVALID_ARG, "thermal_targets must be 0 or 1");
+  if (p->thermal_targets && (!(p->T_K >= 0.0) || !std::isfinite(p->T_K)))
+    return fail(SWARM_ERR_INVALID_ARG, "moving targets need a gas temperature T_K >= 0");
   const int P = p->grid_points_per_octave ? p->grid_points_per_octave : 64;
   if (P <= 0 || P > 1024 || (P & (P - 1)) != 0)
     return fail(SWARM_ERR_INVALID_ARG, "grid points per octave must be a power of two <= 1024");
@@ -379,6 +383,7 @@ swarm_status swarm_create(const swarm_component* comps, int32_t n_comps, const s
   d.precision = params->precision; d.secondaries = params->secondaries;
   d.E = params->E_V_per_m; d.B = params->B_T; d.B_angle = params->B_angle_rad; d.N = params->N_per_m3;
   d.eps0 = params->init_energy_eV; d.user_majorant = params->user_majorant;
+  d.T_K = params->T_K; d.thermal_targets = params->thermal_targets;
   d.trial_strategy = params->trial_strategy;
   d.trial_zeta = params->trial_zeta > 0.0 ? params->trial_zeta : 0.25;
   d.trial_grace = static_cast<uint32_t>(params->trial_grace > 0 ? params->trial_grace : 5000);
@@ -394,11 +399,11 @@ swarm_status swarm_create(const swarm_component* comps, int32_t n_comps, const s
   const size_t b_cm = al(static_cast<size_t>(G) * nc * 8);
   const size_t b_nu64 = al(static_cast<size_t>(G) * 16), b_nu32 = al(static_cast<size_t>(G) * 8);
   const size_t b_c64 = al(static_cast<size_t>(G) * nc * 16), b_c32 = al(static_cast<size_t>(G) * nc * 8);
-  const size_t b_ch = al(nc * sizeof(ChannelDev));
+  const size_t b_ch = al(nc * sizeof(ChannelDev)), b_th = al(nc * sizeof(ThermalChannel));
   const size_t b_eb = al(entry_bin.size() * 4), b_bf = al(bin_first.size() * 4);
   const size_t b_bn = al(static_cast<size_t>(d.n_bins) * 8), b_bn32 = al(static_cast<size_t>(d.n_bins) * 4);
   const size_t total = b_e + b_s + 4 * b_i + b_cd + 4 * b_k + b_nodes + b_cm + b_nu64 + b_nu32 + b_c64 + b_c32 + b_ch +
-                       b_eb + b_bf + b_bn + b_bn32 + al(sizeof(InstanceDesc)) + al(sizeof(RunCounters));
+                       b_th + b_eb + b_bf + b_bn + b_bn32 + al(sizeof(InstanceDesc)) + al(sizeof(RunCounters));
   hipError_t e = h->arena.ensure(total);
   if (e != hipSuccess) return hip_fail(e, "allocating instance tables");
   char* base = static_cast<char*>(h->arena.p);
@@ -422,6 +427,7 @@ swarm_status swarm_create(const swarm_component* comps, int32_t n_comps, const s
   d.cum64 = reinterpret_cast<double2*>(take(b_c64));
   d.cum32 = reinterpret_cast<float2*>(take(b_c32));
   d.chan = reinterpret_cast<ChannelDev*>(take(b_ch));
+  d.chan_th = reinterpret_cast<ThermalChannel*>(take(b_th));
   int32_t* d_entry_bin = reinterpret_cast<int32_t*>(take(b_eb));
   int32_t* d_bin_first = reinterpret_cast<int32_t*>(take(b_bf));
   d.bin_of = d_entry_bin;
@@ -552,8 +558,8 @@ swarm_status swarm_run(swarm_t h, int64_t n_electrons, int64_t n_collisions, uin
   const size_t lds = ll.bytes;
   const int ch_off = ll.ch_off;
   DeviceInfo& dev = device_info();
-  const bool var = d.trial_strategy != SWARM_TRIAL_CONSTANT;
-  const int per_cu = swarm_kernel_max_blocks_per_cu(d.precision, h->has_b, trace, real, var, svc, o.block_size, lds);
+  const int ext = d.thermal_targets ? 2 : d.trial_strategy != SWARM_TRIAL_CONSTANT ? 1 : 0;
+  const int per_cu = swarm_kernel_max_blocks_per_cu(d.precision, h->has_b, trace, real, ext, svc, o.block_size, lds);
   if ((e = hipEventRecord(h->ev[0], s)) != hipSuccess) return hip_fail(e, "event");
   if (!real) {
     // enough work items to give every resident work-group several of them
@@ -571,13 +577,13 @@ swarm_status swarm_run(swarm_t h, int64_t n_electrons, int64_t n_collisions, uin
     if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(d_ctr), 0u, 1, s)) != hipSuccess) return hip_fail(e, "item counter");
     const int grid = std::max(1, std::min<int>(static_cast<int>(items.size()), dev.n_cu * per_cu));
     if ((e = launch_swarm_dummy(h->d_desc, static_cast<const WorkItem*>(h->items.p), static_cast<int32_t>(items.size()),
-                                d_ctr, d.precision, h->has_b, trace, var, svc, o.block_size, grid, o.pending_trigger, lds, ch_off,
+                                d_ctr, d.precision, h->has_b, trace, ext, svc, o.block_size, grid, o.pending_trigger, lds, ch_off,
                                 ll.pool_off, ll.cum_off, s)) != hipSuccess)
       return hip_fail(e, "swarm kernel launch");
   } else {
     const int64_t want = (n_electrons + o.block_size - 1) / o.block_size;
     const int grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want * 4, static_cast<int64_t>(dev.n_cu) * per_cu)));
-    if ((e = launch_swarm_real(h->d_desc, d.precision, h->has_b, trace, var, o.block_size, grid, o.pending_trigger, lds, ch_off,
+    if ((e = launch_swarm_real(h->d_desc, d.precision, h->has_b, trace, ext, o.block_size, grid, o.pending_trigger, lds, ch_off,
                                ll.cum_off, s)) != hipSuccess)
       return hip_fail(e, "swarm kernel launch");
   }

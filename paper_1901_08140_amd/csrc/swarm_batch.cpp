@@ -17,7 +17,8 @@ struct swarm_batch {
   std::vector<swarm_job> jobs;
   int precision = 0;
   bool magnetic = false;
-  bool variable = false;   // some instance uses the variable trial frequency
+  int extended = 0;   // kernel level: 1 some instance uses an adaptive trial frequency,
+                      // 2 some instance has moving targets
   hipStream_t stream = nullptr;
   DevBuf descs, items;
   std::vector<InstanceDesc> h_descs;
@@ -57,7 +58,7 @@ hipError_t enqueue(swarm_batch* b) {
   if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(item_counter(b)), 0u, 1, b->stream)) != hipSuccess) return e;
   if ((e = launch_swarm_dummy(static_cast<const InstanceDesc*>(b->descs.p), static_cast<const WorkItem*>(b->items.p),
                               static_cast<int32_t>(b->h_items.size()), item_counter(b), b->precision, b->magnetic,
-                              false, b->variable, b->opts.service_waves, b->opts.block_size, b->grid,
+                              false, b->extended, b->opts.service_waves, b->opts.block_size, b->grid,
                               b->opts.pending_trigger, b->lds, b->ch_off, b->pool_off, b->cum_off, b->stream)) != hipSuccess)
     return e;
   return b->tally.launch(static_cast<const InstanceDesc*>(b->descs.p), b->stream);
@@ -87,7 +88,7 @@ swarm_status swarm_batch_create(swarm_t* handles, const swarm_job* jobs, int32_t
     for (int j = 0; j < i; ++j)
       if (handles[j] == h) return fail(SWARM_ERR_INVALID_ARG, "handle %d appears twice", i);
     b->magnetic |= h->has_b;
-    b->variable |= h->desc.trial_strategy != SWARM_TRIAL_CONSTANT;
+    b->extended = std::max(b->extended, h->desc.thermal_targets ? 2 : h->desc.trial_strategy != SWARM_TRIAL_CONSTANT ? 1 : 0);
     G = std::max(G, h->desc.G);
     n_ch = std::max(n_ch, h->desc.nc);
     b->hs.push_back(h);
@@ -131,7 +132,7 @@ swarm_status swarm_batch_create(swarm_t* handles, const swarm_job* jobs, int32_t
   b->ch_off = ll.ch_off;
   b->pool_off = ll.pool_off;
   b->cum_off = ll.cum_off;
-  const int per_cu = swarm_kernel_max_blocks_per_cu(b->precision, b->magnetic, false, false, b->variable,
+  const int per_cu = swarm_kernel_max_blocks_per_cu(b->precision, b->magnetic, false, false, b->extended,
                                                     b->opts.service_waves, b->opts.block_size, b->lds);
   const int64_t slots = static_cast<int64_t>(device_info().n_cu) * per_cu;
   make_items(ne, nc, b->opts.chunk, b->h_items, slots, b->opts.block_size);

@@ -41,6 +41,15 @@ struct ChannelDev {
   double xi;       // SWARM_SCATTER_CONSTANT_XI: the anisotropy parameter
 };
 
+// Per-channel constants of moving targets, kept out of ChannelDev (which the kernels copy
+// from LDS into registers) and read from global memory only at such collisions.
+struct ThermalChannel {
+  double mass;     // target mass M (kg)
+  double sigma;    // sqrt(k T / M), spread of each target velocity component
+  double loss;     // 2 eps_k M / ((m + M) m): the threshold in |V1 - Vcm|^2
+  double pad;
+};
+
 // Saved electron state at a real-collision boundary (serving epochs resume from it).
 struct SavedState {
   double r[3], t;
@@ -83,6 +92,8 @@ struct InstanceDesc {
   int32_t n_raw_channels;
   int32_t precision, secondaries;
   double E, B, B_angle, N, eps0, user_majorant;
+  double T_K;                 // gas temperature (moving targets)
+  int32_t thermal_targets;    // 1: moving targets
   int32_t trial_strategy;     // swarm_trial_strategy
   uint32_t trial_grace;       // variable and binned: trials between updates of nu'
   double trial_zeta;          // variable: nu' = (1 + zeta) nu(eps)
@@ -108,6 +119,7 @@ struct InstanceDesc {
   double2* cum64;             // G x nc pairs, node major
   float2* cum32;
   ChannelDev* chan;
+  ThermalChannel* chan_th;    // moving targets: per-channel constants (nc)
   double* bin_nup64;          // binned: nu' of every bin (built on the device)
   float* bin_nup32;
   // run parameters
@@ -167,17 +179,17 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
 // service_waves > 0 (and no trace): the pooled schedule, pool at LDS offset pool_off.
 hipError_t launch_swarm_dummy(const InstanceDesc* d_desc, const WorkItem* d_items, int32_t n_items,
                               int32_t* d_item_counter, int precision, bool has_b, bool trace,
-                              bool var, int service_waves, int block_size, int grid, int pending_trigger,
+                              int ext, int service_waves, int block_size, int grid, int pending_trigger,
                               size_t lds_bytes, int ch_off, int pool_off, int cum_off, hipStream_t s);
 size_t swarm_pool_slot_bytes(int precision);
 hipError_t launch_swarm_real(const InstanceDesc* d_desc, int precision, bool has_b, bool trace,
-                             bool var, int block_size, int grid, int pending_trigger, size_t lds_bytes,
+                             int ext, int block_size, int grid, int pending_trigger, size_t lds_bytes,
                              int ch_off, int cum_off, hipStream_t s);
 hipError_t launch_tallies(const InstanceDesc* d_desc, const TallyTile* d_tiles, int32_t n_tiles,
                           const int32_t* d_tile_base, const int64_t* d_nrec, int32_t n_inst,
                           double* d_part1, double* d_part2, double* d_tot1,
                           swarm_tallies_t* d_out, hipStream_t s);
-int swarm_kernel_max_blocks_per_cu(int precision, bool has_b, bool trace, bool real, bool var,
+int swarm_kernel_max_blocks_per_cu(int precision, bool has_b, bool trace, bool real, int ext,
                                    int service_waves, int block_size,
                                    size_t lds_bytes);
 

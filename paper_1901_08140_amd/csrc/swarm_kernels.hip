@@ -30,6 +30,7 @@ constexpr double kAmu = 1.66053906660e-27;  // kg
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kHartreeEV = 27.211386245988;   // Hartree energy in eV (CODATA 2018)
 constexpr double kLn2 = 0.69314718055994530942;
+constexpr double kKb = 1.380649e-23;         // J/K
 
 // ---------------------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 multiplications
@@ -73,7 +74,8 @@ __device__ __forceinline__ W4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
 }
 
 enum : uint32_t { TAG_TRIAL_HI = 0, TAG_TRIAL_LO = 1, TAG_SCAT_HI = 2, TAG_SCAT_LO = 3,
-                  TAG_INIT_HI = 4, TAG_INIT_LO = 5, TAG_CHILD = 6 };
+                  TAG_INIT_HI = 4, TAG_INIT_LO = 5, TAG_CHILD = 6, TAG_THERMAL_HI = 7,
+                  TAG_THERMAL_LO = 8 };
 
 struct Key { uint32_t k0, k1; };
 
@@ -356,6 +358,13 @@ __global__ void k_build_constants(InstanceDesc* desc) {
     ch.xi = ch.scat == SWARM_SCATTER_CONSTANT_XI ? xi_of_ratio(d.comp_ratio[comp]) : 0.0;
     ch.xi_f = static_cast<float>(ch.xi);
     d.chan[c] = ch;
+    ThermalChannel th;
+    th.mass = M;
+    th.sigma = sqrt(kKb * d.T_K / M);
+    th.loss = (ch.kind == SWARM_EXCITATION || ch.kind == SWARM_IONIZATION) ? 2.0 * (ch.thr * kQe) / (mm + M) * (M / mm)
+                                                                           : 0.0;
+    th.pad = 0.0;
+    d.chan_th[c] = th;
   }
   if (threadIdx.x == 0) {
     const double numax = smax[0];
@@ -460,6 +469,7 @@ struct Consts {
   bool magnetic; // B > 0 (kernels built for B may also serve B = 0 instances)
   bool variable; // a per-lane trial frequency: the variable or the binned strategy
   bool binned;   // the binned strategy
+  bool thermal;  // moving targets
   uint32_t grace0;
   int G, nc, off, p;
   int off1;      // off - 1: raw index of entry 0 of the padded LDS table
@@ -468,6 +478,7 @@ struct Consts {
   Key key;
   const typename Pair<R>::T* cum;
   const ChannelDev* chan;
+  const ThermalChannel* chan_th;
   const int32_t* bin_of;   // binned: bin of every padded table entry
   const R* bin_nup;        // binned: nu' of every bin
 };
@@ -498,6 +509,7 @@ __device__ __forceinline__ Consts<R> load_consts(const InstanceDesc& d) {
   c.magnetic = d.B > 0.0;
   c.variable = d.trial_strategy != SWARM_TRIAL_CONSTANT;
   c.binned = d.trial_strategy == SWARM_TRIAL_BINNED;
+  c.thermal = d.thermal_targets != 0;
   c.bin_of = d.bin_of;
   if constexpr (sizeof(R) == 8) c.bin_nup = d.bin_nup64;
   else c.bin_nup = d.bin_nup32;
@@ -508,6 +520,7 @@ __device__ __forceinline__ Consts<R> load_consts(const InstanceDesc& d) {
   c.n_coll = d.n_collisions; c.quantum = d.quantum;
   c.key = {static_cast<uint32_t>(d.seed), static_cast<uint32_t>(d.seed >> 32)};
   c.chan = d.chan;
+  c.chan_th = d.chan_th;
   c.off1 = c.off - 1;
   c.off1G = c.off1 + c.G;
   return c;
@@ -707,13 +720,14 @@ __device__ __forceinline__ void fail_trial_frequency(Lane<R>& L, const Consts<R>
   }
   L.grace = C.grace0;
 }
-// VAR: the kernel is built for instances that may use the variable strategy.  Kernels
-// built without it keep nu' in the instance constants and carry no per-lane frequency.
-template <typename R, bool VAR>
+// EXT: what the kernel is built for.  0: constant trial frequency, targets at rest (nu' in
+// the instance constants, no per-lane frequency).  1: also the adaptive trial frequencies.
+// 2: also moving targets.  Each level serves every instance of the levels below it.
+template <typename R, int EXT>
 __device__ __forceinline__ void start_trial_frequency(Lane<R>& L, const Consts<R>& C,
                                                       const typename Pair<R>::T* __restrict__ s_nu, R eps) {
   L.nfail = 0;
-  if constexpr (VAR) {
+  if constexpr (EXT) {
     if (C.variable) {
       int raw;
       R w;
@@ -773,7 +787,7 @@ __device__ __forceinline__ void move_full(const Lane<R>& L, const Consts<R>& C, 
 }
 
 // Start a primary: at the origin, energy eps0, isotropic direction from the INIT stream.
-template <typename R, bool HB, bool VAR>
+template <typename R, bool HB, int EXT>
 __device__ __forceinline__ void init_primary(Lane<R>& L, const Consts<R>& C,
                                              const typename Pair<R>::T* __restrict__ s_nu, uint64_t id) {
   const W4 h = draw(C.key, id, TAG_INIT_HI, 0);
@@ -793,7 +807,7 @@ __device__ __forceinline__ void init_primary(Lane<R>& L, const Consts<R>& C,
   L.se = L.sep = 0.0;
   L.T = R(0);
   set_anchor<R, HB>(L, C);
-  start_trial_frequency<R, VAR>(L, C, s_nu, C.eps0);
+  start_trial_frequency<R, EXT>(L, C, s_nu, C.eps0);
 }
 
 template <typename R>
@@ -819,7 +833,7 @@ __device__ __forceinline__ void write_record(const InstanceDesc& d, const Lane<R
   d.records[L.rec] = r;
 }
 
-template <typename R, bool VAR>
+template <typename R, int EXT>
 __device__ __forceinline__ void save_state(const InstanceDesc& d, const Lane<R>& L, const Consts<R>& C,
                                            int64_t e) {
   SavedState s;
@@ -832,13 +846,13 @@ __device__ __forceinline__ void save_state(const InstanceDesc& d, const Lane<R>&
   s.block = L.block; s.k = L.k; s.k_start = L.k_start; s.G = L.G; s.D = L.D;
   s.n_forb = L.nforb; s.n_over = L.nover; s.n_first = L.nfirst;
   s.started = 1; s.pad = L.flags;
-  s.nup = static_cast<double>(VAR ? L.nup : C.nup);
-  s.grace = VAR ? L.grace : 0u;
+  s.nup = static_cast<double>(EXT ? L.nup : C.nup);
+  s.grace = EXT ? L.grace : 0u;
   s.n_fail = L.nfail;
   d.saved[e] = s;
 }
 
-template <typename R, bool HB, bool VAR>
+template <typename R, bool HB, int EXT>
 __device__ __forceinline__ void load_state(const InstanceDesc& d, Lane<R>& L, const Consts<R>& C, int64_t e) {
   const SavedState s = d.saved[e];
   L.rx = s.r[0]; L.ry = s.r[1]; L.rz = s.r[2];
@@ -849,7 +863,7 @@ __device__ __forceinline__ void load_state(const InstanceDesc& d, Lane<R>& L, co
   L.block = s.block; L.k = s.k; L.k_start = s.k_start; L.G = s.G; L.D = s.D;
   L.nforb = s.n_forb; L.nover = s.n_over; L.nfirst = s.n_first; L.flags = s.pad;
   L.T = R(0);
-  if constexpr (VAR) {
+  if constexpr (EXT) {
     // the same derived values as when nu' was set (at the cap: the constant strategy's)
     const R v = static_cast<R>(s.nup);
     if (C.variable && v < C.nup) apply_trial_frequency(L, C, v);
@@ -891,25 +905,25 @@ __device__ __forceinline__ void trace_event(const InstanceDesc& d, Lane<R>& L, i
 // the flight time grows by -ln(1-u)/nu' (eq. random_time), the energy at the new time is
 // looked up in the LDS rate table, and the trial is real when x = u_r nu' < nu(eps)
 // (eq. null_fraction).  Leaves eps, x and the table position in the candidate fields.
-template <typename R, bool HB, bool VAR>
+template <typename R, bool HB, int EXT>
 __device__ __forceinline__ bool one_trial(Lane<R>& L, const Consts<R>& C,
                                           const typename Pair<R>::T* __restrict__ s_nu,
                                           uint32_t hf, uint32_t hr, uint32_t lf, uint32_t lr) {
   if constexpr (sizeof(R) == 4) {
     // u = (hf >> 8) 2^-24: -ln(1-u)/nu' = (24 - log2(2^24 - (hf >> 8))) ln2/nu'
     const float l2 = __builtin_amdgcn_logf(static_cast<float>(0x1000000u - (hf >> 8)));
-    L.T = fmaf(l2 - 24.0f, -(VAR ? L.cT : C.cT), L.T);
-    L.p_x = static_cast<float>(hr >> 8) * (VAR ? L.nup24 : C.nup24);    // = u_r nu' exactly
+    L.T = fmaf(l2 - 24.0f, -(EXT ? L.cT : C.cT), L.T);
+    L.p_x = static_cast<float>(hr >> 8) * (EXT ? L.nup24 : C.nup24);    // = u_r nu' exactly
   } else {
-    L.T = L.T + flight(uni(hf, lf, R(0)), VAR ? L.cT : C.cT);
-    L.p_x = uni(hr, lr, R(0)) * (VAR ? L.nup : C.nup);
+    L.T = L.T + flight(uni(hf, lf, R(0)), EXT ? L.cT : C.cT);
+    L.p_x = uni(hr, lr, R(0)) * (EXT ? L.nup : C.nup);
   }
   L.p_eps = energy_at<R, HB>(L, C, L.T);
   const R nu = lds_rate(s_nu, L.p_eps, C, &L.p_gi, &L.p_w);
   // Not null when x < nu.  That includes nu > nu' (then x < nu' < nu), a fail of an
   // adaptive strategy, which the collision phase tells apart.
   const bool hit = L.p_x < nu;
-  if (VAR && C.variable) {
+  if (EXT && C.variable) {
     L.grace -= 1u;
     if (!hit && L.grace == 0u) renew_trial_frequency(L, C, nu, L.p_gi - C.off1);   // after a null
   }
@@ -924,7 +938,7 @@ __device__ __forceinline__ bool one_trial(Lane<R>& L, const Consts<R>& C,
 // with the counter of their scattering block (k, SCAT) instead of a trial block: they
 // would be masked off here anyway, so the scattering words cost the wave nothing and the
 // collision phase needs no generator call of its own.  The streams are unchanged.
-template <typename R, bool HB, bool VAR>
+template <typename R, bool HB, int EXT>
 __device__ __forceinline__ void trial_block(Lane<R>& L, const Consts<R>& C,
                                             const typename Pair<R>::T* __restrict__ s_nu) {
   const bool waiting = L.state == ST_PENDING;
@@ -953,10 +967,10 @@ __device__ __forceinline__ void trial_block(Lane<R>& L, const Consts<R>& C,
   // The trial writes the candidate fields of the lane directly: a lane that finds a real
   // candidate becomes PENDING and stops writing them until it is served, so they need no
   // copy, and the second trial runs only on the lanes whose first one was null.
-  bool hit = one_trial<R, HB, VAR>(L, C, s_nu, h.x, h.y, l.x, l.y);
+  bool hit = one_trial<R, HB, EXT>(L, C, s_nu, h.x, h.y, l.x, l.y);
   L.p_sub = 0;
   if (!hit) {
-    hit = one_trial<R, HB, VAR>(L, C, s_nu, h.z, h.w, l.z, l.w);
+    hit = one_trial<R, HB, EXT>(L, C, s_nu, h.z, h.w, l.z, l.w);
     L.p_sub = 1;
   }
   if (hit) L.state = ST_PENDING;
@@ -966,11 +980,86 @@ __device__ __forceinline__ void trial_block(Lane<R>& L, const Consts<R>& C,
 constexpr int kScanChannels = 8;   // up to this many channels, selection scans the whole row
 enum : int { RC_CONTINUE = 0, RC_STOP = 1 };
 
+// Moving targets (section "Effect of gas temperature"), in FP64 for both precisions.  The
+// target velocity of collision k has three normal components of spread sqrt(kT/M), from the
+// four uniforms of the THERMAL block by Box-Muller.  moving_target() returns the centre-of-
+// momentum velocity Vcm = (m V1 + M V2)/(m + M) and the electron's squared speed in that
+// frame after the threshold loss, |V1 - Vcm|^2 - 2 eps_k M / ((m + M) m) (negative: the
+// process cannot happen).
+template <typename R>
+__device__ __forceinline__ void moving_target(const Lane<R>& L, const Consts<R>& C, int c,
+                                              R vx, R vy, R vz, double* vcm, double* g2) {
+  const ThermalChannel th = C.chan_th[c];
+  const W4 h = draw(C.key, L.id, TAG_THERMAL_HI, L.k);
+  double u0, u1, u2, u3;
+  if constexpr (sizeof(R) == 8) {
+    const W4 l = draw(C.key, L.id, TAG_THERMAL_LO, L.k);
+    u0 = uni(h.x, l.x, 0.0); u1 = uni(h.y, l.y, 0.0); u2 = uni(h.z, l.z, 0.0); u3 = uni(h.w, l.w, 0.0);
+  } else {
+    u0 = uni(h.x, 0u, 0.0f); u1 = uni(h.y, 0u, 0.0f); u2 = uni(h.z, 0u, 0.0f); u3 = uni(h.w, 0u, 0.0f);
+  }
+  const double r01 = sqrt(-2.0 * log(1.0 - u0));
+  const double r23 = sqrt(-2.0 * log(1.0 - u2));
+  double s1, c1, s3, c3;
+  sincos_rev(u1, &s1, &c1);
+  sincos_rev(u3, &s3, &c3);
+  const double M = th.mass, inv = 1.0 / (kMe + M);
+  const double ax = vx, ay = vy, az = vz;
+  vcm[0] = (ax * kMe + th.sigma * r01 * c1 * M) * inv;
+  vcm[1] = (ay * kMe + th.sigma * r01 * s1 * M) * inv;
+  vcm[2] = (az * kMe + th.sigma * r23 * c3 * M) * inv;
+  const double ux = ax - vcm[0], uy = ay - vcm[1], uz = az - vcm[2];
+  *g2 = (ux * ux + uy * uy + uz * uz) - th.loss;
+}
+
+// The paper's equation for the electron after a collision with a moving target: V1' = Vcm +
+// sqrt(g2) u, u the new direction in the centre-of-momentum frame (isotropic from the
+// scattering block's first two uniforms, or theta about V1 - Vcm for the anisotropic
+// models).  Gives the direction of V1' and the energy after (zero for attachment).
+template <typename R>
+__device__ __forceinline__ void moving_target_outcome(const ChannelDev& ch, const Consts<R>& C, R eps, R u_c, R u_p,
+                                                      R vx, R vy, R vz, const double* vcm, double g2,
+                                                      R* nx, R* ny, R* nz, R* epsp) {
+  const double ux = static_cast<double>(vx) - vcm[0], uy = static_cast<double>(vy) - vcm[1],
+               uz = static_cast<double>(vz) - vcm[2];
+  const double g = sqrt(ux * ux + uy * uy + uz * uz);
+  double hx, hy, hz;
+  if (ch.scat == SWARM_SCATTER_ISOTROPIC || !(g > 0.0)) {
+    iso_dir<double>(u_c, u_p, &hx, &hy, &hz);
+  } else {
+    const double ig = 1.0 / g;
+    rotate_dir<double>(ux * ig, uy * ig, uz * ig, scatter_cos(ch.scat, ch.xi, static_cast<double>(eps), static_cast<double>(u_c)), u_p,
+                       &hx, &hy, &hz);
+  }
+  const double sp = sqrt(fmax(g2, 0.0));
+  const double px = vcm[0] + hx * sp, py = vcm[1] + hy * sp, pz = vcm[2] + hz * sp;
+  const double p2 = px * px + py * py + pz * pz;
+  const double s1 = sqrt(p2);
+  if (s1 > 0.0) {
+    const double is = 1.0 / s1;
+    *nx = static_cast<R>(px * is); *ny = static_cast<R>(py * is); *nz = static_cast<R>(pz * is);
+  } else {
+    *nx = static_cast<R>(hx); *ny = static_cast<R>(hy); *nz = static_cast<R>(hz);
+  }
+  *epsp = ch.kind == SWARM_ATTACHMENT ? R(0) : static_cast<R>(0.5 * kMe * p2 / kQe);
+}
+
+// A forbidden channel pick: counted, traced and treated as a null trial.
+template <typename R, bool TR, int EXT>
+__device__ __forceinline__ int forbidden_pick(const InstanceDesc& d, Lane<R>& L, const Consts<R>& C, int lo, R eps,
+                                              R nu_eps) {
+  L.nforb += 1;
+  trace_event<R, TR>(d, L, 2, lo, eps, eps, L.t + static_cast<double>(L.T), L.rx, L.ry, L.rz);
+  if (EXT && C.variable && L.grace == 0u) renew_trial_frequency(L, C, nu_eps, L.p_gi - C.off1);   // as after a null
+  L.state = ST_ACTIVE;
+  return RC_CONTINUE;
+}
+
 // A pending candidate: channel selection (min c with x < C_c(eps)), the kinematic onset
 // check, isotropic scattering with Fraser-Mathieson energy transfer, ionisation and
 // attachment, then the anchor moves to the collision point.  Returns RC_STOP when the
 // electron has reached its stop count or was removed.
-template <typename R, bool HB, bool TR, bool REAL, bool VAR>
+template <typename R, bool HB, bool TR, bool REAL, int EXT>
 __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L, const Consts<R>& C,
                                               const typename Pair<R>::T* __restrict__ s_nu,
                                               bool* spawn, ChildState* child) {
@@ -979,7 +1068,7 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
   const R x = L.p_x;
   L.nfirst += L.p_sub == 0 ? 1u : 0u;
   R nu_eps = R(0);
-  if (VAR && C.variable) {
+  if (EXT && C.variable) {
     // the total rate the trial compared with (same table entry and weight)
     nu_eps = lerp_pair(s_nu[L.p_gi - C.off1], L.p_w);
     if (nu_eps > L.nup) {
@@ -1025,8 +1114,17 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
   R vx, vy, vz;
   double rx, ry, rz;
   move_full<R, HB>(L, C, L.T, &vx, &vy, &vz, &rx, &ry, &rz);
-  if (ch.kind == SWARM_EXCITATION || ch.kind == SWARM_IONIZATION) {
-    // Energy versus the inelastic onset eps_k (m+M)/M, compared in FP64.
+  // Forbidden: with moving targets, below the threshold in the centre-of-momentum frame;
+  // with targets at rest, an energy below the inelastic onset eps_k (m+M)/M (compared in
+  // FP64).
+  double vcm[3] = {0.0, 0.0, 0.0}, g2 = 0.0;
+  if constexpr (EXT == 2) {
+    if (C.thermal) {
+      moving_target<R>(L, C, lo, vx, vy, vz, vcm, &g2);
+      if (ch.kind != SWARM_ATTACHMENT && g2 < 0.0) return forbidden_pick<R, TR, EXT>(d, L, C, lo, eps, nu_eps);
+    }
+  }
+  if (!(EXT == 2 && C.thermal) && (ch.kind == SWARM_EXCITATION || ch.kind == SWARM_IONIZATION)) {
     double e64;
     if constexpr (sizeof(R) == 8) {
       e64 = eps;
@@ -1034,51 +1132,49 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
       const double dx = vx, dy = vy, dz = vz;
       e64 = d.c_eps * (dx * dx + dy * dy + dz * dz);
     }
-    if (e64 < ch.onset) {
-      L.nforb += 1;
-      trace_event<R, TR>(d, L, 2, lo, eps, eps, L.t + static_cast<double>(L.T), L.rx, L.ry, L.rz);
-      if (VAR && C.variable && L.grace == 0u) renew_trial_frequency(L, C, nu_eps, L.p_gi - C.off1);   // as after a null
-      L.state = ST_ACTIVE;
-      return RC_CONTINUE;
-    }
+    if (e64 < ch.onset) return forbidden_pick<R, TR, EXT>(d, L, C, lo, eps, nu_eps);
   }
   if (over) L.nover += 1;
   const W4 h = L.sh;        // scattering block k, drawn while the candidate waited
   const W4 l = L.sl;
   R nx, ny, nz;
   const R u_c = uni(h.x, l.x, R(0)), u_p = uni(h.y, l.y, R(0));
-  const R v2 = vx * vx + vy * vy + vz * vz;
-  R cos_t;
-  if (ch.scat == SWARM_SCATTER_ISOTROPIC || !(v2 > R(0))) {
-    // isotropic in the lab frame; theta is the angle to the incoming velocity
-    iso_dir<R>(u_c, u_p, &nx, &ny, &nz);
-    if constexpr (sizeof(R) == 8) cos_t = v2 > 0.0 ? (nx * vx + ny * vy + nz * vz) / sqrt(v2) : 0.0;
-    else cos_t = v2 > 0.0f ? (nx * vx + ny * vy + nz * vz) * rsqrt_(v2) : 0.0f;
-  } else {
-    // anisotropic: theta about the incoming direction, azimuth 2 pi u'
-    R xi;
-    if constexpr (sizeof(R) == 8) xi = ch.xi;
-    else xi = ch.xi_f;
-    cos_t = scatter_cos(ch.scat, xi, eps, u_c);
-    R inv;
-    if constexpr (sizeof(R) == 8) inv = 1.0 / sqrt(v2);
-    else inv = rsqrt_(v2);
-    rotate_dir<R>(vx * inv, vy * inv, vz * inv, cos_t, u_p, &nx, &ny, &nz);
-  }
-  R c_ela, c_M, c_mM, thr;
-  if constexpr (sizeof(R) == 8) { c_ela = ch.c_ela; c_M = ch.c_M; c_mM = ch.c_mM; thr = ch.thr; }
-  else { c_ela = ch.c_ela_f; c_M = ch.c_M_f; c_mM = ch.c_mM_f; thr = ch.thr_f; }
   R epsp;
-  if (ch.kind == SWARM_ELASTIC) {
-    epsp = eps * (R(1) - c_ela * (R(1) - cos_t));                       // eq. delta_energy_ela
-  } else if (ch.kind == SWARM_ATTACHMENT) {
-    epsp = R(0);                                                       // plastic collision
+  if (EXT == 2 && C.thermal) {
+    moving_target_outcome<R>(ch, C, eps, u_c, u_p, vx, vy, vz, vcm, g2, &nx, &ny, &nz, &epsp);
   } else {
-    R ratio;
-    if constexpr (sizeof(R) == 4) ratio = thr * __builtin_amdgcn_rcpf(eps);
-    else ratio = thr / eps;
-    const R root = sqrt_(fmax(R(0), R(1) - c_mM * ratio));
-    epsp = eps * (R(1) - c_M * ratio + c_ela * (root * cos_t - R(1)));  // eq. delta_energy_ine
+    const R v2 = vx * vx + vy * vy + vz * vz;
+    R cos_t;
+    if (ch.scat == SWARM_SCATTER_ISOTROPIC || !(v2 > R(0))) {
+      // isotropic in the lab frame; theta is the angle to the incoming velocity
+      iso_dir<R>(u_c, u_p, &nx, &ny, &nz);
+      if constexpr (sizeof(R) == 8) cos_t = v2 > 0.0 ? (nx * vx + ny * vy + nz * vz) / sqrt(v2) : 0.0;
+      else cos_t = v2 > 0.0f ? (nx * vx + ny * vy + nz * vz) * rsqrt_(v2) : 0.0f;
+    } else {
+      // anisotropic: theta about the incoming direction, azimuth 2 pi u'
+      R xi;
+      if constexpr (sizeof(R) == 8) xi = ch.xi;
+      else xi = ch.xi_f;
+      cos_t = scatter_cos(ch.scat, xi, eps, u_c);
+      R inv;
+      if constexpr (sizeof(R) == 8) inv = 1.0 / sqrt(v2);
+      else inv = rsqrt_(v2);
+      rotate_dir<R>(vx * inv, vy * inv, vz * inv, cos_t, u_p, &nx, &ny, &nz);
+    }
+    R c_ela, c_M, c_mM, thr;
+    if constexpr (sizeof(R) == 8) { c_ela = ch.c_ela; c_M = ch.c_M; c_mM = ch.c_mM; thr = ch.thr; }
+    else { c_ela = ch.c_ela_f; c_M = ch.c_M_f; c_mM = ch.c_mM_f; thr = ch.thr_f; }
+    if (ch.kind == SWARM_ELASTIC) {
+      epsp = eps * (R(1) - c_ela * (R(1) - cos_t));                       // eq. delta_energy_ela
+    } else if (ch.kind == SWARM_ATTACHMENT) {
+      epsp = R(0);                                                       // plastic collision
+    } else {
+      R ratio;
+      if constexpr (sizeof(R) == 4) ratio = thr * __builtin_amdgcn_rcpf(eps);
+      else ratio = thr / eps;
+      const R root = sqrt_(fmax(R(0), R(1) - c_mM * ratio));
+      epsp = eps * (R(1) - c_M * ratio + c_ela * (root * cos_t - R(1)));  // eq. delta_energy_ine
+    }
   }
   epsp = fmax(epsp, R(0));
   L.se += static_cast<double>(eps);
@@ -1113,7 +1209,7 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
   L.T = R(0);
   const R sp = C.c_speed * sqrt_(epsp);
   L.vx = sp * nx; L.vy = sp * ny; L.vz = sp * nz;
-  if (VAR && C.variable) {
+  if (EXT && C.variable) {
     L.flags &= ~kRetryFlag;     // a binned retry ends at the next real collision
     if (L.grace == 0u) {        // renewed after a real collision: from the energy after it
       int raw;
@@ -1153,7 +1249,7 @@ __device__ __forceinline__ void stage_cum(const InstanceDesc& d, unsigned char* 
 // wait (or no lane can make progress otherwise), which keeps the costly collision code
 // from running for one lane at a time.
 // ---------------------------------------------------------------------------------------
-template <typename R, bool HB, bool TR, bool VAR>
+template <typename R, bool HB, bool TR, int EXT>
 __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restrict__ descs,
                                                      const WorkItem* __restrict__ items, int n_items,
                                                      int* __restrict__ item_ctr, int pend_trig,
@@ -1203,8 +1299,8 @@ __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restr
           const uint32_t started = d.saved != nullptr ? d.saved[ei].started : 0u;
           if (started != 2u) {          // 2: finished in an earlier launch
             L.rec = ei;
-            if (started == 1u) load_state<R, HB, VAR>(d, L, C, ei);
-            else init_primary<R, HB, VAR>(L, C, s_nu, static_cast<uint64_t>(ei));
+            if (started == 1u) load_state<R, HB, EXT>(d, L, C, ei);
+            else init_primary<R, HB, EXT>(L, C, s_nu, static_cast<uint64_t>(ei));
             L.k_stop = C.quantum ? min(C.n_coll, L.k + C.quantum) : C.n_coll;
             if constexpr (TR) {
               L.trace_slot = find_trace<TR>(d, L.id);
@@ -1219,7 +1315,7 @@ __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restr
       // Trial phase: random-number blocks until enough lanes of the wave wait on a
       // real-collision candidate (or none can go on), then serve them together.
       for (;;) {
-        if (L.state == ST_ACTIVE || L.state == ST_PENDING) trial_block<R, HB, VAR>(L, C, s_nu);
+        if (L.state == ST_ACTIVE || L.state == ST_PENDING) trial_block<R, HB, EXT>(L, C, s_nu);
         const uint64_t ready = __ballot(L.state == ST_READY);
         const uint64_t busy = __ballot(L.state == ST_ACTIVE || L.state == ST_PENDING);
         if (busy == 0 || __popcll(ready) >= pend_trig) break;
@@ -1227,7 +1323,7 @@ __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restr
       if (L.state == ST_READY) {
         bool spawn;
         ChildState child;
-        if (real_collision<R, HB, TR, false, VAR>(d, L, C, s_nu, &spawn, &child) == RC_STOP) L.state = ST_STOPPED;
+        if (real_collision<R, HB, TR, false, EXT>(d, L, C, s_nu, &spawn, &child) == RC_STOP) L.state = ST_STOPPED;
       }
       // An electron that stopped leaves its final record (budget reached or block cap) or
       // its resumable state (end of the launch's quantum).
@@ -1238,7 +1334,7 @@ __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restr
           atomicAdd(reinterpret_cast<unsigned long long*>(&d.ctr->n_done), 1ull);
           if (d.saved != nullptr) d.saved[L.rec].started = 2u;
         } else {
-          save_state<R, VAR>(d, L, C, L.rec);
+          save_state<R, EXT>(d, L, C, L.rec);
         }
         L.state = ST_IDLE;
       }
@@ -1281,7 +1377,7 @@ struct Pool {
 };
 
 // Owner -> pool: the candidate and everything the collision code reads or updates.
-template <typename R, bool VAR>
+template <typename R, int EXT>
 __device__ __forceinline__ void pool_put(const Pool<R>& P, int s, const Lane<R>& L) {
   P.D(PD_RX, s) = L.rx; P.D(PD_RY, s) = L.ry; P.D(PD_RZ, s) = L.rz; P.D(PD_T, s) = L.t;
   P.D(PD_SE, s) = L.se; P.D(PD_SEP, s) = L.sep;
@@ -1292,23 +1388,23 @@ __device__ __forceinline__ void pool_put(const Pool<R>& P, int s, const Lane<R>&
   P.U(PU_G, s) = L.G; P.U(PU_D, s) = L.D; P.U(PU_K, s) = L.k; P.U(PU_KSTOP, s) = L.k_stop;
   P.U(PU_FLAGS, s) = L.flags; P.U(PU_NFAIL, s) = L.nfail;
   P.U(PU_IDLO, s) = static_cast<uint32_t>(L.id); P.U(PU_IDHI, s) = static_cast<uint32_t>(L.id >> 32);
-  if constexpr (VAR) {
+  if constexpr (EXT) {
     P.V(PR_NUP, s) = L.nup;
     P.U(PU_GRACE, s) = L.grace;
   }
 }
 
 // Per-lane trial frequency from a stored nu' (at the cap: the constant strategy's values).
-template <typename R, bool VAR>
+template <typename R, int EXT>
 __device__ __forceinline__ void restore_trial_frequency(Lane<R>& L, const Consts<R>& C, R v) {
-  if constexpr (VAR) {
+  if constexpr (EXT) {
     if (C.variable && v < C.nup) apply_trial_frequency(L, C, v);
     else constant_trial_frequency(L, C);
   }
 }
 
 // Service lane <- pool: a lane state complete enough for real_collision.
-template <typename R, bool HB, bool VAR>
+template <typename R, bool HB, int EXT>
 __device__ __forceinline__ void pool_take(const Pool<R>& P, int s, Lane<R>& S, const Consts<R>& C) {
   S.rx = P.D(PD_RX, s); S.ry = P.D(PD_RY, s); S.rz = P.D(PD_RZ, s); S.t = P.D(PD_T, s);
   S.se = P.D(PD_SE, s); S.sep = P.D(PD_SEP, s);
@@ -1319,8 +1415,8 @@ __device__ __forceinline__ void pool_take(const Pool<R>& P, int s, Lane<R>& S, c
   S.G = P.U(PU_G, s); S.D = P.U(PU_D, s); S.k = P.U(PU_K, s); S.k_stop = P.U(PU_KSTOP, s);
   S.flags = P.U(PU_FLAGS, s); S.nfail = P.U(PU_NFAIL, s);
   S.id = static_cast<uint64_t>(P.U(PU_IDLO, s)) | (static_cast<uint64_t>(P.U(PU_IDHI, s)) << 32);
-  if constexpr (VAR) {
-    restore_trial_frequency<R, VAR>(S, C, P.V(PR_NUP, s));
+  if constexpr (EXT) {
+    restore_trial_frequency<R, EXT>(S, C, P.V(PR_NUP, s));
     S.grace = P.U(PU_GRACE, s);
   }
   S.trace_slot = -1;
@@ -1334,7 +1430,7 @@ __device__ __forceinline__ void pool_take(const Pool<R>& P, int s, Lane<R>& S, c
 }
 
 // Service lane -> pool: the outcome.
-template <typename R, bool VAR>
+template <typename R, int EXT>
 __device__ __forceinline__ void pool_give(const Pool<R>& P, int s, const Lane<R>& S) {
   P.D(PD_RX, s) = S.rx; P.D(PD_RY, s) = S.ry; P.D(PD_RZ, s) = S.rz; P.D(PD_T, s) = S.t;
   P.D(PD_SE, s) = S.se; P.D(PD_SEP, s) = S.sep;
@@ -1342,14 +1438,14 @@ __device__ __forceinline__ void pool_give(const Pool<R>& P, int s, const Lane<R>
   P.U(PU_NFIRST, s) = S.nfirst; P.U(PU_NFORB, s) = S.nforb; P.U(PU_NOVER, s) = S.nover;
   P.U(PU_G, s) = S.G; P.U(PU_D, s) = S.D; P.U(PU_K, s) = S.k; P.U(PU_FLAGS, s) = S.flags;
   P.U(PU_STATE, s) = static_cast<uint32_t>(S.state); P.U(PU_NFAIL, s) = S.nfail;
-  if constexpr (VAR) {
+  if constexpr (EXT) {
     P.V(PR_NUP, s) = S.nup;
     P.U(PU_GRACE, s) = S.grace;
   }
 }
 
 // Owner <- pool: take the served electron back.
-template <typename R, bool HB, bool VAR>
+template <typename R, bool HB, int EXT>
 __device__ __forceinline__ void pool_back(const Pool<R>& P, int s, Lane<R>& L, const Consts<R>& C) {
   L.rx = P.D(PD_RX, s); L.ry = P.D(PD_RY, s); L.rz = P.D(PD_RZ, s); L.t = P.D(PD_T, s);
   L.se = P.D(PD_SE, s); L.sep = P.D(PD_SEP, s);
@@ -1357,8 +1453,8 @@ __device__ __forceinline__ void pool_back(const Pool<R>& P, int s, Lane<R>& L, c
   L.nfirst = P.U(PU_NFIRST, s); L.nforb = P.U(PU_NFORB, s); L.nover = P.U(PU_NOVER, s);
   L.G = P.U(PU_G, s); L.D = P.U(PU_D, s); L.k = P.U(PU_K, s); L.flags = P.U(PU_FLAGS, s);
   L.state = static_cast<int>(P.U(PU_STATE, s)); L.nfail = P.U(PU_NFAIL, s);
-  if constexpr (VAR) {
-    restore_trial_frequency<R, VAR>(L, C, P.V(PR_NUP, s));
+  if constexpr (EXT) {
+    restore_trial_frequency<R, EXT>(L, C, P.V(PR_NUP, s));
     L.grace = P.U(PU_GRACE, s);
   }
   set_anchor<R, HB>(L, C);
@@ -1366,7 +1462,7 @@ __device__ __forceinline__ void pool_back(const Pool<R>& P, int s, Lane<R>& L, c
 
 // One random-number block of an ACTIVE lane in the pooled schedule: a real candidate
 // leaves the lane in CAND (the scattering words are drawn by the service wave).
-template <typename R, bool HB, bool VAR>
+template <typename R, bool HB, int EXT>
 __device__ __forceinline__ void trial_block_pooled(Lane<R>& L, const Consts<R>& C,
                                                    const typename Pair<R>::T* __restrict__ s_nu) {
   if (L.block >= kMaxBlocks) {
@@ -1378,16 +1474,16 @@ __device__ __forceinline__ void trial_block_pooled(Lane<R>& L, const Consts<R>& 
   W4 l = {0, 0, 0, 0};
   if constexpr (sizeof(R) == 8) l = draw_trial(C.key, L.pre_lo, L.block);
   L.block += 1;
-  bool hit = one_trial<R, HB, VAR>(L, C, s_nu, h.x, h.y, l.x, l.y);
+  bool hit = one_trial<R, HB, EXT>(L, C, s_nu, h.x, h.y, l.x, l.y);
   L.p_sub = 0;
   if (!hit) {
-    hit = one_trial<R, HB, VAR>(L, C, s_nu, h.z, h.w, l.z, l.w);
+    hit = one_trial<R, HB, EXT>(L, C, s_nu, h.z, h.w, l.z, l.w);
     L.p_sub = 1;
   }
   if (hit) L.state = ST_CAND;
 }
 
-template <typename R, bool HB, bool VAR>
+template <typename R, bool HB, int EXT>
 __global__ void __launch_bounds__(512) k_swarm_pooled(const InstanceDesc* __restrict__ descs,
                                                       const WorkItem* __restrict__ items, int n_items,
                                                       int* __restrict__ item_ctr, int n_service,
@@ -1453,13 +1549,13 @@ __global__ void __launch_bounds__(512) k_swarm_pooled(const InstanceDesc* __rest
         const int s = (wave - n_trial) * 64 + lane;
         if (s < n) {
           Lane<R> S;
-          pool_take<R, HB, VAR>(P, s, S, C);
+          pool_take<R, HB, EXT>(P, s, S, C);
           bool spawn;
           ChildState child;
           S.state = ST_ACTIVE;
-          if (real_collision<R, HB, false, false, VAR>(d, S, C, s_nu, &spawn, &child) == RC_STOP)
+          if (real_collision<R, HB, false, false, EXT>(d, S, C, s_nu, &spawn, &child) == RC_STOP)
             S.state = ST_STOPPED;
-          pool_give<R, VAR>(P, s, S);
+          pool_give<R, EXT>(P, s, S);
         }
         __syncthreads();
         if (s_live[round % 3] == 0) break;
@@ -1473,7 +1569,7 @@ __global__ void __launch_bounds__(512) k_swarm_pooled(const InstanceDesc* __rest
       L.n_ev = 0;
       int slot = 0;
       for (int round = 0;; ++round) {
-        if (L.state == ST_WAIT) pool_back<R, HB, VAR>(P, slot, L, C);   // served last round
+        if (L.state == ST_WAIT) pool_back<R, HB, EXT>(P, slot, L, C);   // served last round
         if (L.state == ST_STOPPED) {
           if (L.k >= C.n_coll || (L.flags & 4u)) {
             if (L.k >= C.n_coll) L.flags |= 1u;
@@ -1481,7 +1577,7 @@ __global__ void __launch_bounds__(512) k_swarm_pooled(const InstanceDesc* __rest
             atomicAdd(reinterpret_cast<unsigned long long*>(&d.ctr->n_done), 1ull);
             if (d.saved != nullptr) d.saved[L.rec].started = 2u;
           } else {
-            save_state<R, VAR>(d, L, C, L.rec);
+            save_state<R, EXT>(d, L, C, L.rec);
           }
           L.state = ST_IDLE;
         }
@@ -1492,8 +1588,8 @@ __global__ void __launch_bounds__(512) k_swarm_pooled(const InstanceDesc* __rest
             const uint32_t started = d.saved != nullptr ? d.saved[ei].started : 0u;
             if (started != 2u) {
               L.rec = ei;
-              if (started == 1u) load_state<R, HB, VAR>(d, L, C, ei);
-              else init_primary<R, HB, VAR>(L, C, s_nu, static_cast<uint64_t>(ei));
+              if (started == 1u) load_state<R, HB, EXT>(d, L, C, ei);
+              else init_primary<R, HB, EXT>(L, C, s_nu, static_cast<uint64_t>(ei));
               L.k_stop = C.quantum ? min(C.n_coll, L.k + C.quantum) : C.n_coll;
               L.state = ST_ACTIVE;
             }
@@ -1502,7 +1598,7 @@ __global__ void __launch_bounds__(512) k_swarm_pooled(const InstanceDesc* __rest
           }
         }
         __syncthreads();      // every served electron is back: the pool slots are free
-        if (L.state == ST_ACTIVE) trial_block_pooled<R, HB, VAR>(L, C, s_nu);
+        if (L.state == ST_ACTIVE) trial_block_pooled<R, HB, EXT>(L, C, s_nu);
         // candidates into the pool: one LDS reservation per wave, ranks from the lane mask
         const uint64_t m = __ballot(L.state == ST_CAND);
         if (m != 0) {
@@ -1513,7 +1609,7 @@ __global__ void __launch_bounds__(512) k_swarm_pooled(const InstanceDesc* __rest
           if (L.state == ST_CAND) {
             const int s = base + static_cast<int>(__popcll(m & lane_lt));
             if (s < P.cap) {
-              pool_put<R, VAR>(P, s, L);
+              pool_put<R, EXT>(P, s, L);
               slot = s;
               L.state = ST_WAIT;
             }
@@ -1536,7 +1632,7 @@ __global__ void __launch_bounds__(512) k_swarm_pooled(const InstanceDesc* __rest
 // after its state is written.  The kernel ends when every electron has stopped (`live`
 // reaches 0); idle waves sleep between polls and give up after a bounded number of polls.
 // ---------------------------------------------------------------------------------------
-template <typename R, bool HB, bool TR, bool VAR>
+template <typename R, bool HB, bool TR, int EXT>
 __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restrict__ desc, int pend_trig,
                                                     int ch_off, int cum_off) {
   using PT = typename Pair<R>::T;
@@ -1574,7 +1670,7 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
     if (L.state == ST_IDLE && prim_left) {
       const uint64_t e = atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->prim_next), 1ull);
       if (static_cast<int64_t>(e) < N) {
-        init_primary<R, HB, VAR>(L, C, s_nu, e);
+        init_primary<R, HB, EXT>(L, C, s_nu, e);
         L.rec = static_cast<int64_t>(e);
         L.k_stop = C.n_coll;
         if constexpr (TR) {
@@ -1611,7 +1707,7 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
           L.T = R(0);
           L.rec = N + slot;
           set_anchor<R, HB>(L, C);
-          start_trial_frequency<R, VAR>(L, C, s_nu, static_cast<R>(cs.eps_birth));
+          start_trial_frequency<R, EXT>(L, C, s_nu, static_cast<R>(cs.eps_birth));
           if constexpr (TR) {
             L.trace_slot = find_trace<TR>(d, L.id);
             L.n_ev = 0;
@@ -1628,7 +1724,7 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
     }
     uint64_t ready;
     for (;;) {
-      if (L.state == ST_ACTIVE || L.state == ST_PENDING) trial_block<R, HB, VAR>(L, C, s_nu);
+      if (L.state == ST_ACTIVE || L.state == ST_PENDING) trial_block<R, HB, EXT>(L, C, s_nu);
       ready = __ballot(L.state == ST_READY);
       const uint64_t busy = __ballot(L.state == ST_ACTIVE || L.state == ST_PENDING);
       if (busy == 0 || __popcll(ready) >= pend_trig) break;
@@ -1637,7 +1733,7 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
       bool spawn = false;
       ChildState child;
       if (L.state == ST_READY) {
-        if (real_collision<R, HB, TR, true, VAR>(d, L, C, s_nu, &spawn, &child) == RC_STOP) L.state = ST_STOPPED;
+        if (real_collision<R, HB, TR, true, EXT>(d, L, C, s_nu, &spawn, &child) == RC_STOP) L.state = ST_STOPPED;
       }
       // append the secondaries of this wave: one reservation, ranks from the lane mask
       const uint64_t sm = __ballot(spawn);
@@ -1909,36 +2005,39 @@ __global__ void k_tally_final(const InstanceDesc* __restrict__ descs, const doub
 }
 
 template <typename R, bool HB, bool TR>
-void* dummy_fn(bool var) {
-  return var ? reinterpret_cast<void*>(&k_swarm_dummy<R, HB, TR, true>)
-             : reinterpret_cast<void*>(&k_swarm_dummy<R, HB, TR, false>);
+void* dummy_fn(int ext) {
+  return ext == 2 ? reinterpret_cast<void*>(&k_swarm_dummy<R, HB, TR, 2>)
+       : ext == 1 ? reinterpret_cast<void*>(&k_swarm_dummy<R, HB, TR, 1>)
+                  : reinterpret_cast<void*>(&k_swarm_dummy<R, HB, TR, 0>);
 }
 template <typename R, bool HB, bool TR>
-void* real_fn(bool var) {
-  return var ? reinterpret_cast<void*>(&k_swarm_real<R, HB, TR, true>)
-             : reinterpret_cast<void*>(&k_swarm_real<R, HB, TR, false>);
+void* real_fn(int ext) {
+  return ext == 2 ? reinterpret_cast<void*>(&k_swarm_real<R, HB, TR, 2>)
+       : ext == 1 ? reinterpret_cast<void*>(&k_swarm_real<R, HB, TR, 1>)
+                  : reinterpret_cast<void*>(&k_swarm_real<R, HB, TR, 0>);
 }
 
 template <typename R, bool HB>
-void* pooled_fn(bool var) {
-  return var ? reinterpret_cast<void*>(&k_swarm_pooled<R, HB, true>)
-             : reinterpret_cast<void*>(&k_swarm_pooled<R, HB, false>);
+void* pooled_fn(int ext) {
+  return ext == 2 ? reinterpret_cast<void*>(&k_swarm_pooled<R, HB, 2>)
+       : ext == 1 ? reinterpret_cast<void*>(&k_swarm_pooled<R, HB, 1>)
+                  : reinterpret_cast<void*>(&k_swarm_pooled<R, HB, 0>);
 }
 
-void* pick_pooled(int precision, bool has_b, bool var) {
-  if (precision == SWARM_FP32_MIXED) return has_b ? pooled_fn<float, true>(var) : pooled_fn<float, false>(var);
-  return has_b ? pooled_fn<double, true>(var) : pooled_fn<double, false>(var);
+void* pick_pooled(int precision, bool has_b, int ext) {
+  if (precision == SWARM_FP32_MIXED) return has_b ? pooled_fn<float, true>(ext) : pooled_fn<float, false>(ext);
+  return has_b ? pooled_fn<double, true>(ext) : pooled_fn<double, false>(ext);
 }
 
-void* pick_kernel(int precision, bool has_b, bool trace, bool real, bool var) {
+void* pick_kernel(int precision, bool has_b, bool trace, bool real, int ext) {
   const bool f32 = precision == SWARM_FP32_MIXED;
 #define SW_PICK(R)                                                                            \
   if (real) {                                                                                 \
-    if (has_b) return trace ? real_fn<R, true, true>(var) : real_fn<R, true, false>(var);     \
-    return trace ? real_fn<R, false, true>(var) : real_fn<R, false, false>(var);              \
+    if (has_b) return trace ? real_fn<R, true, true>(ext) : real_fn<R, true, false>(ext);     \
+    return trace ? real_fn<R, false, true>(ext) : real_fn<R, false, false>(ext);              \
   }                                                                                           \
-  if (has_b) return trace ? dummy_fn<R, true, true>(var) : dummy_fn<R, true, false>(var);     \
-  return trace ? dummy_fn<R, false, true>(var) : dummy_fn<R, false, false>(var);
+  if (has_b) return trace ? dummy_fn<R, true, true>(ext) : dummy_fn<R, true, false>(ext);     \
+  return trace ? dummy_fn<R, false, true>(ext) : dummy_fn<R, false, false>(ext);
   if (f32) { SW_PICK(float) }
   SW_PICK(double)
 #undef SW_PICK
@@ -1986,25 +2085,25 @@ size_t swarm_pool_slot_bytes(int precision) {
 
 hipError_t launch_swarm_dummy(const InstanceDesc* d_desc, const WorkItem* d_items, int32_t n_items,
                               int32_t* d_item_counter, int precision, bool has_b, bool trace,
-                              bool var, int service_waves, int block_size, int grid, int pending_trigger,
+                              int ext, int service_waves, int block_size, int grid, int pending_trigger,
                               size_t lds_bytes, int ch_off, int pool_off, int cum_off, hipStream_t s) {
   if (service_waves > 0 && !trace) {
     if (service_waves >= block_size / 64) return hipErrorInvalidValue;
-    void* fn = pick_pooled(precision, has_b, var);
+    void* fn = pick_pooled(precision, has_b, ext);
     void* args[] = {const_cast<InstanceDesc**>(&d_desc), const_cast<WorkItem**>(&d_items), &n_items,
                     &d_item_counter, &service_waves, &ch_off, &pool_off, &cum_off};
     return hipLaunchKernel(fn, dim3(grid), dim3(block_size), args, lds_bytes, s);
   }
-  void* fn = pick_kernel(precision, has_b, trace, false, var);
+  void* fn = pick_kernel(precision, has_b, trace, false, ext);
   void* args[] = {const_cast<InstanceDesc**>(&d_desc), const_cast<WorkItem**>(&d_items), &n_items,
                   &d_item_counter, &pending_trigger, &ch_off, &cum_off};
   return hipLaunchKernel(fn, dim3(grid), dim3(block_size), args, lds_bytes, s);
 }
 
 hipError_t launch_swarm_real(const InstanceDesc* d_desc, int precision, bool has_b, bool trace,
-                             bool var, int block_size, int grid, int pending_trigger, size_t lds_bytes,
+                             int ext, int block_size, int grid, int pending_trigger, size_t lds_bytes,
                              int ch_off, int cum_off, hipStream_t s) {
-  void* fn = pick_kernel(precision, has_b, trace, true, var);
+  void* fn = pick_kernel(precision, has_b, trace, true, ext);
   void* args[] = {const_cast<InstanceDesc**>(&d_desc), &pending_trigger, &ch_off, &cum_off};
   return hipLaunchKernel(fn, dim3(grid), dim3(block_size), args, lds_bytes, s);
 }
@@ -2022,11 +2121,11 @@ hipError_t launch_tallies(const InstanceDesc* d_desc, const TallyTile* d_tiles, 
   return hipGetLastError();
 }
 
-int swarm_kernel_max_blocks_per_cu(int precision, bool has_b, bool trace, bool real, bool var,
+int swarm_kernel_max_blocks_per_cu(int precision, bool has_b, bool trace, bool real, int ext,
                                    int service_waves, int block_size, size_t lds_bytes) {
   int n = 0;
-  void* fn = service_waves > 0 && !trace && !real ? pick_pooled(precision, has_b, var)
-                                                  : pick_kernel(precision, has_b, trace, real, var);
+  void* fn = service_waves > 0 && !trace && !real ? pick_pooled(precision, has_b, ext)
+                                                  : pick_kernel(precision, has_b, trace, real, ext);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn,
                                                    block_size, lds_bytes) != hipSuccess)
     return 1;

@@ -228,7 +228,8 @@ void scheduler(swarm_server* s) {
     descs.clear();
     std::vector<int64_t> ne, nc;
     int G = 0, n_ch = 0;
-    bool magnetic = false, variable = false;
+    bool magnetic = false;
+    int extended = 0;
     for (auto& r : act) {
       InstanceDesc d = r->h->desc;
       d.quantum = static_cast<uint32_t>(std::min<int64_t>(q, 0xffffffffLL));
@@ -238,13 +239,13 @@ void scheduler(swarm_server* s) {
       G = std::max(G, d.G);
       n_ch = std::max(n_ch, d.nc);
       magnetic |= r->h->has_b;
-      variable |= d.trial_strategy != SWARM_TRIAL_CONSTANT;
+      extended = std::max(extended, d.thermal_targets ? 2 : d.trial_strategy != SWARM_TRIAL_CONSTANT ? 1 : 0);
       r->epochs += 1;
     }
     const swarm_launch_opts o = resolve_opts(&s->p.opts, s->p.precision);
     const LdsLayout ll = lds_layout(s->p.precision, G, n_ch, o.service_waves, o.table_layout);
     const size_t lds = ll.bytes;
-    const int per_cu = swarm_kernel_max_blocks_per_cu(s->p.precision, magnetic, false, false, variable,
+    const int per_cu = swarm_kernel_max_blocks_per_cu(s->p.precision, magnetic, false, false, extended,
                                                       o.service_waves, o.block_size, lds);
     make_items(ne, nc, o.chunk, items, static_cast<int64_t>(device_info().n_cu) * per_cu, o.block_size);
     hipError_t e;
@@ -258,7 +259,7 @@ void scheduler(swarm_server* s) {
     if (ok) {
       const int grid = std::max(1, std::min<int>(static_cast<int>(items.size()), device_info().n_cu * per_cu));
       ok = (e = launch_swarm_dummy(static_cast<const InstanceDesc*>(s->descs.p), static_cast<const WorkItem*>(s->items.p),
-                                   static_cast<int32_t>(items.size()), item_ctr, s->p.precision, magnetic, false, variable,
+                                   static_cast<int32_t>(items.size()), item_ctr, s->p.precision, magnetic, false, extended,
                                    o.service_waves, o.block_size, grid, o.pending_trigger, lds, ll.ch_off,
                                    ll.pool_off, ll.cum_off, s->compute)) == hipSuccess &&
            (e = hipEventRecord(ev1, s->compute)) == hipSuccess;
