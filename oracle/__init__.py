@@ -57,7 +57,8 @@ class _Params(ctypes.Structure):
                 ("grid_emin", ctypes.c_int32), ("grid_emax", ctypes.c_int32),
                 ("user_majorant", ctypes.c_double), ("trial_strategy", ctypes.c_int32),
                 ("trial_zeta", ctypes.c_double), ("trial_grace", ctypes.c_int64),
-                ("trial_bins", ctypes.c_int32), ("thermal_targets", ctypes.c_int32)]
+                ("trial_bins", ctypes.c_int32), ("thermal_targets", ctypes.c_int32),
+                ("relativistic", ctypes.c_int32)]
 
 
 _lib = None
@@ -91,6 +92,8 @@ def lib():
             "or_select": (i32, [vp, d, d]),
             "or_move": (None, [vp, P(d), P(d), d, P(d), P(d)]),
             "or_energy_after": (d, [i32, d, d, d, d]),
+            "or_kinetic": (d, [vp, P(d)]),
+            "or_speed": (d, [vp, d, i32]),
             "or_const": (d, [i32]),
             "or_xi_from_ratio": (d, [d]),
             "or_target_velocity": (None, [d, P(d), P(d)]),
@@ -153,6 +156,10 @@ def boltzmann():
     return lib().or_const(4)
 
 
+def light_speed():
+    return lib().or_const(5)
+
+
 def target_velocity(sigma, u):
     """Velocity of a moving target: three normals of spread sigma from four uniforms."""
     P = ctypes.POINTER(ctypes.c_double)
@@ -212,7 +219,7 @@ class OracleModel:
     def __init__(self, components, E_V_per_m, B_T=0.0, B_angle_rad=0.0, N_per_m3=2.5e25,
                  T_K=293.0, init_energy_eV=0.1, secondaries=0, grid_P=64, grid_emin=-14,
                  grid_emax=12, user_majorant=0.0, trial_strategy=0, trial_zeta=0.25,
-                 trial_grace=5000, trial_bins=10, thermal_targets=0):
+                 trial_grace=5000, trial_bins=10, thermal_targets=0, relativistic=0):
         L = lib()
         self._keep = []
         comps = (_Component * len(components))()
@@ -238,7 +245,7 @@ class OracleModel:
             comps[ci].mt_over_el = float(getattr(c, "mt_over_el", 1.0))
         p = _Params(E_V_per_m, B_T, B_angle_rad, N_per_m3, T_K, init_energy_eV, secondaries,
                     grid_P, grid_emin, grid_emax, user_majorant, trial_strategy, trial_zeta,
-                    trial_grace, trial_bins, thermal_targets)
+                    trial_grace, trial_bins, thermal_targets, relativistic)
         st = ctypes.c_int32(0)
         self.h = L.or_create(comps, len(components), ctypes.byref(p), ctypes.byref(st))
         if not self.h:
@@ -254,6 +261,7 @@ class OracleModel:
         kw.setdefault("trial_grace", cfg.trial_grace)
         kw.setdefault("trial_bins", cfg.trial_bins)
         kw.setdefault("thermal_targets", cfg.thermal_targets)
+        kw.setdefault("relativistic", cfg.relativistic)
         return cls(cfg.components, cfg.E_V_per_m, cfg.B_T, cfg.B_angle_rad, cfg.N_per_m3, cfg.T_K,
                    cfg.init_energy_eV, cfg.secondaries, **kw)
 
@@ -303,6 +311,15 @@ class OracleModel:
         ov = ctypes.c_int32(0)
         v = lib().or_nu_grid(self.h, eps, ctypes.byref(ov))
         return v, bool(ov.value)
+
+    def kinetic(self, u):
+        """Kinetic energy (eV) of a held velocity (the proper velocity u = gamma v for the
+        relativistic mover)."""
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        return lib().or_kinetic(self.h, u.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+
+    def speed(self, eps, proper=False):
+        return lib().or_speed(self.h, eps, int(proper))
 
     def channel_cum(self, c, eps):
         return lib().or_channel_cum(self.h, c, eps)

@@ -42,6 +42,7 @@ constexpr double kAmu = 1.66053906660e-27;  // kg
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kHartreeEV = 27.211386245988;   // Hartree energy in eV (CODATA 2018)
 constexpr double kKb = 1.380649e-23;         // J/K
+constexpr double kC = 299792458.0;           // m/s
 
 enum Kind { ELASTIC = 0, EXCITATION = 1, IONIZATION = 2, ATTACHMENT = 3 };
 
@@ -204,10 +205,23 @@ double sigma_raw(const Channel& ch, double eps) {
   return s[i - 1] + (s[i] - s[i - 1]) * t;
 }
 
+// Speed of an electron of kinetic energy eps (eV; joule inside).  Classically sqrt(2 eps/m),
+// the factor of eq. (frequency).  Relativistically |u|/gamma with gamma = 1 + eps/(m c^2)
+// and the proper speed |u| = gamma |v| = sqrt(2 eps/m (1 + eps/(2 m c^2))) (from
+// gamma^2 - 1 = |u|^2/c^2); this equals c sqrt(1 - 1/gamma^2) without its cancellation.
+double proper_speed(double eps, bool rel) {
+  const double e = eps * kQe;
+  return rel ? std::sqrt(2.0 * e / kMe * (1.0 + e / (2.0 * kMe * kC * kC))) : std::sqrt(2.0 * e / kMe);
+}
+double speed_of(double eps, bool rel) {
+  return rel ? proper_speed(eps, true) / (1.0 + eps * kQe / (kMe * kC * kC)) : proper_speed(eps, false);
+}
+
 // Rate of one channel, the summand of the paper's eq. (frequency):
-// nu_c(eps) = n_k sigma_c(eps) sqrt(2 eps / m), eps converted from eV to joule.
-double rate_raw(const Channel& ch, double eps) {
-  return ch.density * sigma_raw(ch, eps) * std::sqrt(2.0 * eps * kQe / kMe);
+// nu_c(eps) = n_k sigma_c(eps) v(eps), eps converted from eV to joule, v = sqrt(2 eps/m)
+// (the relativistic mover takes the electron's true speed).
+double rate_raw(const Channel& ch, double eps, bool rel) {
+  return ch.density * sigma_raw(ch, eps) * speed_of(eps, rel);
 }
 
 struct Params {
@@ -221,6 +235,7 @@ struct Params {
   int64_t grace;        // variable and binned: trials between updates of nu'
   int bins;             // binned: bins per decade of energy
   int thermal;          // 1: targets move (Maxwell-Boltzmann at temperature T), 0: at rest
+  int relativistic;     // 1: relativistic motion (B = 0), velocities held as u = gamma v
 };
 
 struct Model {
@@ -307,7 +322,45 @@ void move(const Model& m, Vec3 r0, Vec3 v0, double T, Vec3* r, Vec3* v) {
 }
 
 double energy_eV(Vec3 v) { return 0.5 * kMe * dot(v, v) / kQe; }
-double speed_from_energy(double eps) { return std::sqrt(2.0 * eps * kQe / kMe); }
+
+// Relativistic motion in a uniform static E (the paper's UniformFieldRelativisticChin, B =
+// 0), in the proper velocity u = gamma v: u(T) = u0 + a T with a = -(e/m) E z^ (from dp/dt
+// = -e E), and the position is the time integral of u/gamma, gamma = sqrt(1 + |u|^2/c^2):
+//   z(T) = z0 + c^2 (gamma(T) - gamma0) / a        (the work of the field)
+//        = z0 + (u_z0 + u_z(T)) T / (gamma0 + gamma(T))
+//   (gamma(T)^2 - gamma0^2 = (u_z(T)^2 - u_z0^2)/c^2 and u_z(T) - u_z0 = a T), and across E,
+//   with gamma = sqrt(A^2 + u_z^2)/c, A^2 = c^2 + u_x^2 + u_y^2,
+//   x(T) = x0 + u_x (c/a) (asinh(u_z(T)/A) - asinh(u_z0/A))   (likewise y);
+// without a field the motion is straight, r0 + u0 T / gamma0.
+void move_rel(const Model& m, Vec3 r0, Vec3 u0, double T, Vec3* r, Vec3* u) {
+  const double a = m.a.z;
+  const Vec3 uT{u0.x, u0.y, u0.z + a * T};
+  if (u) *u = uT;
+  if (!r) return;
+  const double c2 = kC * kC;
+  const double g0 = std::sqrt(1.0 + dot(u0, u0) / c2), g1 = std::sqrt(1.0 + dot(uT, uT) / c2);
+  if (a == 0.0) {
+    *r = add(r0, scale(u0, T / g0));
+    return;
+  }
+  const double A = std::sqrt(c2 + u0.x * u0.x + u0.y * u0.y);
+  const double s = kC / a * (std::asinh(uT.z / A) - std::asinh(u0.z / A));
+  *r = {r0.x + u0.x * s, r0.y + u0.y * s, r0.z + (u0.z + uT.z) * T / (g0 + g1)};
+}
+
+// Kinetic energy (eV) of the velocity held: classically m |v|^2 / 2; relativistically
+// (gamma - 1) m c^2 = m |u|^2 / (gamma + 1), gamma = sqrt(1 + |u|^2/c^2).
+double kinetic_eV(Vec3 u, bool rel) {
+  if (!rel) return energy_eV(u);
+  const double u2 = dot(u, u);
+  return kMe * u2 / (std::sqrt(1.0 + u2 / (kC * kC)) + 1.0) / kQe;
+}
+
+// Motion of either mover.
+void advance(const Model& m, Vec3 r0, Vec3 v0, double T, Vec3* r, Vec3* v) {
+  if (m.p.relativistic) move_rel(m, r0, v0, T, r, v);
+  else move(m, r0, v0, T, r, v);
+}
 
 // Energy after an elastic collision (Fraser-Mathieson, the paper's eq. delta_energy_ela).
 double energy_after_elastic(double eps, double cos_t, double M) {
@@ -473,8 +526,8 @@ Record simulate(const RunCtx& cx, const Electron& e0, std::vector<Electron>& chi
       // Flight time against the trial frequency nu' (eq. random_time).
       T += -std::log(1.0 - u_f) / nup;
       Vec3 vT;
-      move(m, r, v, T, nullptr, &vT);
-      const double eps = energy_eV(vT);
+      advance(m, r, v, T, nullptr, &vT);
+      const double eps = kinetic_eV(vT, m.p.relativistic);
       bool over = false;
       const double nu = nu_total(m, eps, &over);
       if (adaptive && nu > nup) {
@@ -498,7 +551,7 @@ Record simulate(const RunCtx& cx, const Electron& e0, std::vector<Electron>& chi
             rec.flags |= FLAG_RETRY_FAILED;
             nup = m.majorant;
           } else {
-            nup = binned_retry_nup(m, energy_eV(v), eps);
+            nup = binned_retry_nup(m, kinetic_eV(v, m.p.relativistic), eps);
           }
           retry = true;
         } else {
@@ -554,7 +607,7 @@ Record simulate(const RunCtx& cx, const Electron& e0, std::vector<Electron>& chi
       // Real collision.
       if (over) ++rec.n_over;
       Vec3 rT;
-      move(m, r, v, T, &rT, nullptr);
+      advance(m, r, v, T, &rT, nullptr);
       const Words sh = stream_block(cx.seed, e0.id, SCAT_HI, k);
       const Words sl = stream_block(cx.seed, e0.id, SCAT_LO, k);
       const double v2 = dot(vT, vT);
@@ -609,7 +662,7 @@ Record simulate(const RunCtx& cx, const Electron& e0, std::vector<Electron>& chi
           child.t = t + T;
           child.k = k + 1;
           child.v = scale(iso_direction(uniform53(sh.w[2], sl.w[2]), uniform53(sh.w[3], sl.w[3])),
-                          speed_from_energy(epsp));
+                          proper_speed(epsp, m.p.relativistic));
           child.eps_birth = epsp;
           const int64_t n_created = cx.created->fetch_add(1) + 1;
           if (n_created > cx.capacity) {
@@ -635,7 +688,7 @@ Record simulate(const RunCtx& cx, const Electron& e0, std::vector<Electron>& chi
       r = rT;
       t += T;
       T = 0.0;
-      v = scale(n, speed_from_energy(epsp));
+      v = scale(n, proper_speed(epsp, m.p.relativistic));
       retry = false;
       if (adaptive && --grace == 0) renew(epsp, nu_total(m, epsp));
       break;
@@ -658,7 +711,7 @@ Electron primary(const Model& m, uint64_t seed, uint64_t id) {
   e.t = 0.0;
   e.k = 0;
   e.v = scale(iso_direction(uniform53(hi.w[0], lo.w[0]), uniform53(hi.w[1], lo.w[1])),
-              speed_from_energy(m.p.eps0));
+              proper_speed(m.p.eps0, m.p.relativistic));
   e.eps_birth = m.p.eps0;
   return e;
 }
@@ -683,7 +736,7 @@ struct or_component { double mass_amu; double fraction; int32_t n_channels; cons
 struct or_params { double E_V_per_m, B_T, B_angle_rad, N_per_m3, T_K, init_energy_eV;
                    int32_t secondaries, grid_P, grid_emin, grid_emax; double user_majorant;
                    int32_t trial_strategy; double trial_zeta; int64_t trial_grace;
-                   int32_t trial_bins; int32_t thermal_targets; };
+                   int32_t trial_bins; int32_t thermal_targets; int32_t relativistic; };
 
 enum { OR_OK = 0, OR_INVALID = -1, OR_CAPACITY = -3 };
 
@@ -710,11 +763,16 @@ void* or_create(const or_component* comps, int32_t n_comps, const or_params* p, 
     return nullptr;
   if (p->trial_strategy == 2 && (p->trial_bins < 1 || p->trial_bins > 100 || p->trial_grace < 1)) return nullptr;
   if (p->thermal_targets < 0 || p->thermal_targets > 1 || !(p->T_K >= 0.0) || !std::isfinite(p->T_K)) return nullptr;
+  // the relativistic mover: uniform E only, and not with moving targets (whose kinematics
+  // take laboratory velocities)
+  if (p->relativistic < 0 || p->relativistic > 1) return nullptr;
+  if (p->relativistic && (p->B_T != 0.0 || p->thermal_targets)) return nullptr;
   double fsum = 0.0;
   auto* m = new Model();
   m->p = {p->E_V_per_m, p->B_T, p->B_angle_rad, p->N_per_m3, p->T_K, p->init_energy_eV,
           p->secondaries, p->grid_P, p->grid_emin, p->grid_emax, p->user_majorant,
-          p->trial_strategy, p->trial_zeta, p->trial_grace, p->trial_bins, p->thermal_targets};
+          p->trial_strategy, p->trial_zeta, p->trial_grace, p->trial_bins, p->thermal_targets,
+          p->relativistic};
   for (int k = 0; k < n_comps; ++k) {
     const or_component& c = comps[k];
     if (!(c.mass_amu > 0.0) || !(c.fraction >= 0.0) || c.n_channels <= 0) { delete m; return nullptr; }
@@ -756,7 +814,7 @@ void* or_create(const or_component* comps, int32_t n_comps, const or_params* p, 
     m->nodes[g] = eps;
     double acc = 0.0;
     for (int c = 0; c < nc; ++c) {
-      acc += rate_raw(m->ch[c], eps);       // running sum in channel order (eq. frequency)
+      acc += rate_raw(m->ch[c], eps, p->relativistic);   // running sum in channel order (eq. frequency)
       m->C[static_cast<size_t>(c) * m->G + g] = acc;
     }
     if (!(acc > 0.0)) { delete m; return nullptr; }   // every electron must be able to collide
@@ -826,7 +884,7 @@ double or_sigma_raw(void* h, int32_t c, double eps) { return sigma_raw(static_ca
 double or_rate_raw_total(void* h, double eps) {
   const Model& m = *static_cast<Model*>(h);
   double acc = 0.0;
-  for (const auto& ch : m.ch) acc += rate_raw(ch, eps);
+  for (const auto& ch : m.ch) acc += rate_raw(ch, eps, m.p.relativistic);
   return acc;
 }
 double or_nu_grid(void* h, double eps, int32_t* over) {
@@ -852,9 +910,19 @@ int32_t or_select(void* h, double eps, double x) {
 void or_move(void* h, const double* r0, const double* v0, double T, double* r, double* v) {
   const Model& m = *static_cast<Model*>(h);
   Vec3 rr, vv;
-  move(m, {r0[0], r0[1], r0[2]}, {v0[0], v0[1], v0[2]}, T, &rr, &vv);
+  advance(m, {r0[0], r0[1], r0[2]}, {v0[0], v0[1], v0[2]}, T, &rr, &vv);
   r[0] = rr.x; r[1] = rr.y; r[2] = rr.z;
   v[0] = vv.x; v[1] = vv.y; v[2] = vv.z;
+}
+
+// Kinetic energy (eV) of a held velocity, and speed / proper speed at an energy, for the
+// model's mover.
+double or_kinetic(void* h, const double* u) {
+  return kinetic_eV({u[0], u[1], u[2]}, static_cast<Model*>(h)->p.relativistic);
+}
+double or_speed(void* h, double eps, int32_t proper) {
+  const bool rel = static_cast<Model*>(h)->p.relativistic;
+  return proper ? proper_speed(eps, rel) : speed_of(eps, rel);
 }
 
 double or_energy_after(int32_t kind, double eps, double eps_k, double cos_t, double mass_amu) {
@@ -900,6 +968,7 @@ double or_const(int32_t which) {
     case 2: return kAmu;
     case 3: return kHartreeEV;
     case 4: return kKb;
+    case 5: return kC;
     default: return 0.0;
   }
 }

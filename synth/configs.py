@@ -44,6 +44,7 @@ class SwarmConfig:
     trial_grace: int = 5000
     trial_bins: int = 10
     thermal_targets: int = 0     # 1: targets with Maxwell-Boltzmann velocities at T_K
+    relativistic: int = 0        # 1: relativistic motion (B = 0)
     label: str = ""
     extra: dict = field(default_factory=dict)
 
