@@ -155,6 +155,12 @@ typedef struct {
                               models).  A process below its threshold in that frame is
                               forbidden (counted in n_forbidden).  Rates and the null test keep
                               the laboratory energy. */
+  int32_t relativistic;    /* 0: classical motion (UniformFieldClassic); 1: relativistic
+                              motion in a uniform E (the paper's UniformFieldRelativisticChin,
+                              B = 0 only): lanes hold the proper velocity u = gamma v, the
+                              rates of eq. (frequency) take the true speed |u|/gamma, and the
+                              energy-transfer equations are unchanged.  Needs SWARM_FP64,
+                              B_T = 0 and thermal_targets = 0 (else SWARM_ERR_INVALID_ARG). */
 } swarm_params;
 
 /* Per-electron result record (one per electron that existed in the run), as stored on

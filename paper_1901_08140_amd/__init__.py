@@ -50,7 +50,7 @@ class swarm_params(ctypes.Structure):
                 ("grid_points_per_octave", _i32), ("grid_min_exp2", _i32), ("grid_max_exp2", _i32),
                 ("user_majorant", _d), ("capacity", _i64), ("stream", _vp),
                 ("trial_strategy", _i32), ("trial_zeta", _d), ("trial_grace", _i64),
-                ("trial_bins", _i32), ("thermal_targets", _i32)]
+                ("trial_bins", _i32), ("thermal_targets", _i32), ("relativistic", _i32)]
 
 
 class swarm_stat(ctypes.Structure):
@@ -187,7 +187,8 @@ class _Marshalled:
 def make_params(E_V_per_m, B_T=0.0, B_angle_rad=0.0, N_per_m3=2.5e25, T_K=293.0, init_energy_eV=0.1,
                 precision=SWARM_FP64, secondaries=SWARM_DUMMY, grid_points_per_octave=0, grid_min_exp2=0,
                 grid_max_exp2=0, user_majorant=0.0, capacity=0, stream=None,
-                trial_strategy=0, trial_zeta=0.0, trial_grace=0, trial_bins=0, thermal_targets=0):
+                trial_strategy=0, trial_zeta=0.0, trial_grace=0, trial_bins=0, thermal_targets=0,
+                relativistic=0):
     p = swarm_params()
     p.E_V_per_m, p.B_T, p.B_angle_rad, p.N_per_m3, p.T_K = E_V_per_m, B_T, B_angle_rad, N_per_m3, T_K
     p.init_energy_eV, p.precision, p.secondaries = init_energy_eV, int(precision), int(secondaries)
@@ -197,6 +198,7 @@ def make_params(E_V_per_m, B_T=0.0, B_angle_rad=0.0, N_per_m3=2.5e25, T_K=293.0,
     p.trial_strategy, p.trial_zeta, p.trial_grace = int(trial_strategy), float(trial_zeta), int(trial_grace)
     p.trial_bins = int(trial_bins)
     p.thermal_targets = int(thermal_targets)
+    p.relativistic = int(relativistic)
     return p
 
 
@@ -208,6 +210,7 @@ def params_from_config(cfg, precision=SWARM_FP64, **kw):
     kw.setdefault("trial_grace", getattr(cfg, "trial_grace", 0))
     kw.setdefault("trial_bins", getattr(cfg, "trial_bins", 0))
     kw.setdefault("thermal_targets", getattr(cfg, "thermal_targets", 0))
+    kw.setdefault("relativistic", getattr(cfg, "relativistic", 0))
     return make_params(cfg.E_V_per_m, cfg.B_T, cfg.B_angle_rad, cfg.N_per_m3, cfg.T_K, cfg.init_energy_eV,
                        precision, cfg.secondaries, **kw)
 

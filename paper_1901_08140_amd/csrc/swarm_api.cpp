@@ -157,6 +157,13 @@ swarm_status validate(const swarm_component* comps, int32_t n_comps, const swarm
     return fail(SWARM_ERR_INVALID_ARG, "thermal_targets must be 0 or 1");
   if (p->thermal_targets && (!(p->T_K >= 0.0) || !std::isfinite(p->T_K)))
     return fail(SWARM_ERR_INVALID_ARG, "moving targets need a gas temperature T_K >= 0");
+  if (p->relativistic != 0 && p->relativistic != 1) return fail(SWARM_ERR_INVALID_ARG, "relativistic must be 0 or 1");
+  if (p->relativistic && p->B_T != 0.0)
+    return fail(SWARM_ERR_INVALID_ARG, "the relativistic mover takes a uniform E only (B_T = 0)");
+  if (p->relativistic && p->thermal_targets)
+    return fail(SWARM_ERR_INVALID_ARG, "the relativistic mover does not take moving targets");
+  if (p->relativistic && p->precision != SWARM_FP64)
+    return fail(SWARM_ERR_INVALID_ARG, "the relativistic mover runs in SWARM_FP64");
   const int P = p->grid_points_per_octave ? p->grid_points_per_octave : 64;
   if (P <= 0 || P > 1024 || (P & (P - 1)) != 0)
     return fail(SWARM_ERR_INVALID_ARG, "grid points per octave must be a power of two <= 1024");
@@ -383,7 +390,7 @@ swarm_status swarm_create(const swarm_component* comps, int32_t n_comps, const s
   d.precision = params->precision; d.secondaries = params->secondaries;
   d.E = params->E_V_per_m; d.B = params->B_T; d.B_angle = params->B_angle_rad; d.N = params->N_per_m3;
   d.eps0 = params->init_energy_eV; d.user_majorant = params->user_majorant;
-  d.T_K = params->T_K; d.thermal_targets = params->thermal_targets;
+  d.T_K = params->T_K; d.thermal_targets = params->thermal_targets; d.relativistic = params->relativistic;
   d.trial_strategy = params->trial_strategy;
   d.trial_zeta = params->trial_zeta > 0.0 ? params->trial_zeta : 0.25;
   d.trial_grace = static_cast<uint32_t>(params->trial_grace > 0 ? params->trial_grace : 5000);
@@ -558,7 +565,7 @@ swarm_status swarm_run(swarm_t h, int64_t n_electrons, int64_t n_collisions, uin
   const size_t lds = ll.bytes;
   const int ch_off = ll.ch_off;
   DeviceInfo& dev = device_info();
-  const int ext = d.thermal_targets ? 2 : d.trial_strategy != SWARM_TRIAL_CONSTANT ? 1 : 0;
+  const int ext = d.thermal_targets || d.relativistic ? 2 : d.trial_strategy != SWARM_TRIAL_CONSTANT ? 1 : 0;
   const int per_cu = swarm_kernel_max_blocks_per_cu(d.precision, h->has_b, trace, real, ext, svc, o.block_size, lds);
   if ((e = hipEventRecord(h->ev[0], s)) != hipSuccess) return hip_fail(e, "event");
   if (!real) {

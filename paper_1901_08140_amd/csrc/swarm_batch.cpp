@@ -18,7 +18,7 @@ struct swarm_batch {
   int precision = 0;
   bool magnetic = false;
   int extended = 0;   // kernel level: 1 some instance uses an adaptive trial frequency,
-                      // 2 some instance has moving targets
+                      // 2 some instance has moving targets or the relativistic mover
   hipStream_t stream = nullptr;
   DevBuf descs, items;
   std::vector<InstanceDesc> h_descs;
@@ -88,7 +88,8 @@ swarm_status swarm_batch_create(swarm_t* handles, const swarm_job* jobs, int32_t
     for (int j = 0; j < i; ++j)
       if (handles[j] == h) return fail(SWARM_ERR_INVALID_ARG, "handle %d appears twice", i);
     b->magnetic |= h->has_b;
-    b->extended = std::max(b->extended, h->desc.thermal_targets ? 2 : h->desc.trial_strategy != SWARM_TRIAL_CONSTANT ? 1 : 0);
+    b->extended = std::max(b->extended, h->desc.thermal_targets || h->desc.relativistic ? 2
+                                        : h->desc.trial_strategy != SWARM_TRIAL_CONSTANT ? 1 : 0);
     G = std::max(G, h->desc.G);
     n_ch = std::max(n_ch, h->desc.nc);
     b->hs.push_back(h);

@@ -94,6 +94,7 @@ struct InstanceDesc {
   double E, B, B_angle, N, eps0, user_majorant;
   double T_K;                 // gas temperature (moving targets)
   int32_t thermal_targets;    // 1: moving targets
+  int32_t relativistic;       // 1: relativistic mover (FP64, B = 0)
   int32_t trial_strategy;     // swarm_trial_strategy
   uint32_t trial_grace;       // variable and binned: trials between updates of nu'
   double trial_zeta;          // variable: nu' = (1 + zeta) nu(eps)

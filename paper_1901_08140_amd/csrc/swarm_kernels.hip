@@ -31,6 +31,7 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr double kHartreeEV = 27.211386245988;   // Hartree energy in eV (CODATA 2018)
 constexpr double kLn2 = 0.69314718055994530942;
 constexpr double kKb = 1.380649e-23;         // J/K
+constexpr double kC = 299792458.0;           // m/s
 
 // ---------------------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 multiplications
@@ -286,12 +287,17 @@ __global__ void k_build_rates(InstanceDesc* desc) {
   const int P = 1 << d.p_log2;
   const int o = g / P, i = g % P;
   const double eps = ldexp(1.0 + static_cast<double>(i) / P, d.emin + o);
+  const double ej = eps * kQe;
+  const double speed = d.relativistic ? sqrt(2.0 * ej / kMe * (1.0 + ej / (2.0 * kMe * kC * kC))) / (1.0 + ej / (kMe * kC * kC))
+                                      : sqrt(2.0 * ej / kMe);
   double acc = 0.0;
   for (int c = 0; c < d.nc; ++c) {
     const int comp = d.raw_comp[c];
     const double dens = d.comp_frac[comp] * d.N;
-    // eq. frequency: nu_c = n_k sigma_c(eps) sqrt(2 eps / m), eps in joule
-    acc += dens * sigma_ext(d, c, eps) * sqrt(2.0 * eps * kQe / kMe);
+    // eq. frequency: nu_c = n_k sigma_c(eps) v, eps in joule, v = sqrt(2 eps / m); the
+    // relativistic mover takes the true speed |u|/gamma, |u| = sqrt(2 eps/m (1 + eps/(2 m c^2)))
+    // the proper speed and gamma = 1 + eps/(m c^2)
+    acc += dens * sigma_ext(d, c, eps) * speed;
     d.cum_cm[static_cast<size_t>(c) * d.G + g] = acc;
   }
   d.nodes[g] = eps;
@@ -382,7 +388,8 @@ __global__ void k_build_constants(InstanceDesc* desc) {
     d.cT_f = static_cast<float>(kLn2 / nup);
     d.c_eps = 0.5 * kMe / kQe;
     d.c_speed = sqrt(2.0 * kQe / kMe);
-    d.speed0 = sqrt(2.0 * d.eps0 * kQe / kMe);
+    // (relativistic mover: the proper speed gamma |v|)
+    d.speed0 = sqrt(2.0 * d.eps0 * kQe / kMe * (d.relativistic ? 1.0 + d.eps0 * kQe / (2.0 * kMe * kC * kC) : 1.0));
     d.az = -kQe * d.E / kMe;
     d.omega = kQe * d.B / kMe;
     d.bx = sin(d.B_angle);
@@ -470,6 +477,7 @@ struct Consts {
   bool variable; // a per-lane trial frequency: the variable or the binned strategy
   bool binned;   // the binned strategy
   bool thermal;  // moving targets
+  bool relativistic;  // relativistic mover (FP64, B = 0): lanes hold u = gamma v
   uint32_t grace0;
   int G, nc, off, p;
   int off1;      // off - 1: raw index of entry 0 of the padded LDS table
@@ -510,6 +518,7 @@ __device__ __forceinline__ Consts<R> load_consts(const InstanceDesc& d) {
   c.variable = d.trial_strategy != SWARM_TRIAL_CONSTANT;
   c.binned = d.trial_strategy == SWARM_TRIAL_BINNED;
   c.thermal = d.thermal_targets != 0;
+  c.relativistic = d.relativistic != 0;
   c.bin_of = d.bin_of;
   if constexpr (sizeof(R) == 8) c.bin_nup = d.bin_nup64;
   else c.bin_nup = d.bin_nup32;
@@ -603,12 +612,22 @@ __device__ __forceinline__ void set_anchor(Lane<R>& L, const Consts<R>& C) {
 
 // Energy (eV) during free flight, eps = (m/2e) |v(T)|^2 (classical motion in uniform E
 // and B).
-template <typename R, bool HB>
+// With the relativistic mover (EXT == 2, FP64, B = 0) the lane holds the proper velocity u =
+// gamma v, which grows like v does classically, and the kinetic energy is (gamma - 1) m c^2 =
+// m |u|^2 / (gamma + 1), gamma = sqrt(1 + |u|^2/c^2).
+template <typename R, bool HB, int EXT = 0>
 __device__ __forceinline__ R energy_at(const Lane<R>& L, const Consts<R>& C, R T) {
   if (!HB || !C.magnetic) {
     const R vz = fma_(C.aze, T, L.e_vz);
-    if constexpr (sizeof(R) == 4) return fmaf(vz, vz, L.e_q0);
-    else return C.c_eps * fma(vz, vz, L.e_q0);
+    if constexpr (sizeof(R) == 4) {
+      return fmaf(vz, vz, L.e_q0);
+    } else {
+      const double u2 = fma(vz, vz, L.e_q0);
+      if constexpr (EXT == 2) {
+        if (C.relativistic) return C.c_eps * (2.0 * u2) / (1.0 + sqrt(1.0 + u2 * (1.0 / (kC * kC))));
+      }
+      return C.c_eps * u2;
+    }
   } else {
     R s, c;
     if constexpr (sizeof(R) == 4) {
@@ -703,7 +722,7 @@ __device__ __forceinline__ void renew_trial_frequency(Lane<R>& L, const Consts<R
 // Variable: (1 + zeta) nu from the rate that failed.  Binned: the largest nu' of the bins
 // from the anchor energy's bin to the failing energy's bin; a fail during that retry, where
 // the paper throws, sets record flag 16 and takes the constant nu'.
-template <typename R, bool HB>
+template <typename R, bool HB, int EXT>
 __device__ __forceinline__ void fail_trial_frequency(Lane<R>& L, const Consts<R>& C, R nu) {
   if (!C.binned) {
     set_trial_frequency(L, C, C.zeta1 * nu);
@@ -711,7 +730,7 @@ __device__ __forceinline__ void fail_trial_frequency(Lane<R>& L, const Consts<R>
     L.flags |= 16u;
     constant_trial_frequency(L, C);
   } else {
-    const int a = C.bin_of[raw_index(energy_at<R, HB>(L, C, R(0)), C) - C.off1];
+    const int a = C.bin_of[raw_index(energy_at<R, HB, EXT>(L, C, R(0)), C) - C.off1];
     const int f = C.bin_of[L.p_gi - C.off1];
     R v = R(0);
     for (int k = min(a, f); k <= max(a, f); ++k) v = C.bin_nup[k] > v ? C.bin_nup[k] : v;
@@ -720,9 +739,10 @@ __device__ __forceinline__ void fail_trial_frequency(Lane<R>& L, const Consts<R>
   }
   L.grace = C.grace0;
 }
-// EXT: what the kernel is built for.  0: constant trial frequency, targets at rest (nu' in
-// the instance constants, no per-lane frequency).  1: also the adaptive trial frequencies.
-// 2: also moving targets.  Each level serves every instance of the levels below it.
+// EXT: what the kernel is built for.  0: constant trial frequency, targets at rest, classical
+// motion (nu' in the instance constants, no per-lane frequency).  1: also the adaptive trial
+// frequencies.  2: also moving targets and the relativistic mover.  Each level serves every
+// instance of the levels below it.
 template <typename R, int EXT>
 __device__ __forceinline__ void start_trial_frequency(Lane<R>& L, const Consts<R>& C,
                                                       const typename Pair<R>::T* __restrict__ s_nu, R eps) {
@@ -741,9 +761,34 @@ __device__ __forceinline__ void start_trial_frequency(Lane<R>& L, const Consts<R
 
 // Velocity and displacement after a flight of duration T from the anchor (the same
 // equations of motion, written per component).
-template <typename R, bool HB>
+template <typename R, bool HB, int EXT = 0>
 __device__ __forceinline__ void move_full(const Lane<R>& L, const Consts<R>& C, R T,
                                           R* vx, R* vy, R* vz, double* rx, double* ry, double* rz) {
+  if constexpr (EXT == 2 && sizeof(R) == 8) {
+    if (C.relativistic) {
+      // Relativistic, B = 0 (the lane holds u = gamma v): u_z grows by a T; z advances by
+      // c^2 (gamma1 - gamma0)/a = (u_z0 + u_z1) T / (gamma0 + gamma1), and x, y by
+      // u_x (c/a) (asinh(u_z1/A) - asinh(u_z0/A)), A^2 = c^2 + u_x^2 + u_y^2, with the
+      // difference taken as one asinh of c a T (gamma0 - u_z0 (u_z0 + u_z1)/(c^2 (gamma0 +
+      // gamma1))) / A^2 (no cancellation).  Without a field, straight at u0/gamma0.
+      const double c2 = kC * kC, a = C.az;
+      const double uz0 = L.vz, uz1 = L.vz + a * T;
+      const double up2 = L.vx * L.vx + L.vy * L.vy;
+      const double g0 = sqrt(1.0 + (up2 + uz0 * uz0) / c2), g1 = sqrt(1.0 + (up2 + uz1 * uz1) / c2);
+      *vx = L.vx; *vy = L.vy; *vz = uz1;
+      double sx;
+      if (a == 0.0) {
+        sx = T / g0;
+      } else {
+        const double arg = kC * a * T * (g0 - uz0 * (uz0 + uz1) / (c2 * (g0 + g1))) / (c2 + up2);
+        sx = kC / a * asinh(arg);
+      }
+      *rx = L.rx + L.vx * sx;
+      *ry = L.ry + L.vy * sx;
+      *rz = L.rz + (uz0 + uz1) * T / (g0 + g1);
+      return;
+    }
+  }
   if (!HB || !C.magnetic) {
     *vx = L.vx;
     *vy = L.vy;
@@ -918,7 +963,7 @@ __device__ __forceinline__ bool one_trial(Lane<R>& L, const Consts<R>& C,
     L.T = L.T + flight(uni(hf, lf, R(0)), EXT ? L.cT : C.cT);
     L.p_x = uni(hr, lr, R(0)) * (EXT ? L.nup : C.nup);
   }
-  L.p_eps = energy_at<R, HB>(L, C, L.T);
+  L.p_eps = energy_at<R, HB, EXT>(L, C, L.T);
   const R nu = lds_rate(s_nu, L.p_eps, C, &L.p_gi, &L.p_w);
   // Not null when x < nu.  That includes nu > nu' (then x < nu' < nu), a fail of an
   // adaptive strategy, which the collision phase tells apart.
@@ -1044,6 +1089,16 @@ __device__ __forceinline__ void moving_target_outcome(const ChannelDev& ch, cons
   *epsp = ch.kind == SWARM_ATTACHMENT ? R(0) : static_cast<R>(0.5 * kMe * p2 / kQe);
 }
 
+// Speed held by a lane after a collision to energy eps: sqrt(2 eps/m), or with the
+// relativistic mover the proper speed sqrt(2 eps/m (1 + eps/(2 m c^2))).
+template <typename R, int EXT>
+__device__ __forceinline__ R speed_of_energy(const Consts<R>& C, R eps) {
+  if constexpr (EXT == 2 && sizeof(R) == 8) {
+    if (C.relativistic) return C.c_speed * sqrt(eps * (1.0 + eps * (kQe / (2.0 * kMe * kC * kC))));
+  }
+  return C.c_speed * sqrt_(eps);
+}
+
 // A forbidden channel pick: counted, traced and treated as a null trial.
 template <typename R, bool TR, int EXT>
 __device__ __forceinline__ int forbidden_pick(const InstanceDesc& d, Lane<R>& L, const Consts<R>& C, int lo, R eps,
@@ -1077,7 +1132,7 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
       L.nfail += 1u;
       trace_event<R, TR>(d, L, 3, -1, eps, eps, L.t + static_cast<double>(L.T), L.rx, L.ry, L.rz);
       L.T = R(0);
-      fail_trial_frequency<R, HB>(L, C, nu_eps);
+      fail_trial_frequency<R, HB, EXT>(L, C, nu_eps);
       L.state = ST_ACTIVE;
       return RC_CONTINUE;
     }
@@ -1113,7 +1168,7 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
   const ChannelDev ch = C.chan[lo];     // channel descriptors are staged in LDS
   R vx, vy, vz;
   double rx, ry, rz;
-  move_full<R, HB>(L, C, L.T, &vx, &vy, &vz, &rx, &ry, &rz);
+  move_full<R, HB, EXT>(L, C, L.T, &vx, &vy, &vz, &rx, &ry, &rz);
   // Forbidden: with moving targets, below the threshold in the centre-of-momentum frame;
   // with targets at rest, an energy below the inelastic onset eps_k (m+M)/M (compared in
   // FP64).
@@ -1186,7 +1241,7 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
       const W4 cw = draw(C.key, L.id, TAG_CHILD, L.k);
       R sx, sy, sz;
       iso_dir<R>(uni(h.z, l.z, R(0)), uni(h.w, l.w, R(0)), &sx, &sy, &sz);
-      const R sp = C.c_speed * sqrt_(epsp);
+      const R sp = speed_of_energy<R, EXT>(C, epsp);
       child->r[0] = rx; child->r[1] = ry; child->r[2] = rz;
       child->t = L.t + static_cast<double>(L.T);
       child->v[0] = sp * sx; child->v[1] = sp * sy; child->v[2] = sp * sz;
@@ -1207,7 +1262,7 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
   L.rx = rx; L.ry = ry; L.rz = rz;
   L.t = tn;
   L.T = R(0);
-  const R sp = C.c_speed * sqrt_(epsp);
+  const R sp = speed_of_energy<R, EXT>(C, epsp);
   L.vx = sp * nx; L.vy = sp * ny; L.vz = sp * nz;
   if (EXT && C.variable) {
     L.flags &= ~kRetryFlag;     // a binned retry ends at the next real collision

@@ -239,7 +239,7 @@ void scheduler(swarm_server* s) {
       G = std::max(G, d.G);
       n_ch = std::max(n_ch, d.nc);
       magnetic |= r->h->has_b;
-      extended = std::max(extended, d.thermal_targets ? 2 : d.trial_strategy != SWARM_TRIAL_CONSTANT ? 1 : 0);
+      extended = std::max(extended, d.thermal_targets || d.relativistic ? 2 : d.trial_strategy != SWARM_TRIAL_CONSTANT ? 1 : 0);
       r->epochs += 1;
     }
     const swarm_launch_opts o = resolve_opts(&s->p.opts, s->p.precision);
