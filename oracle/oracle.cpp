@@ -323,8 +323,8 @@ void move(const Model& m, Vec3 r0, Vec3 v0, double T, Vec3* r, Vec3* v) {
 
 double energy_eV(Vec3 v) { return 0.5 * kMe * dot(v, v) / kQe; }
 
-// Relativistic motion in a uniform static E (the paper's UniformFieldRelativisticChin, B =
-// 0), in the proper velocity u = gamma v: u(T) = u0 + a T with a = -(e/m) E z^ (from dp/dt
+// Relativistic motion in a uniform static E (the paper's UniformFieldRelativisticChin with
+// B = 0), in the proper velocity u = gamma v: u(T) = u0 + a T with a = -(e/m) E z^ (from dp/dt
 // = -e E), and the position is the time integral of u/gamma, gamma = sqrt(1 + |u|^2/c^2):
 //   z(T) = z0 + c^2 (gamma(T) - gamma0) / a        (the work of the field)
 //        = z0 + (u_z0 + u_z(T)) T / (gamma0 + gamma(T))
@@ -348,6 +348,101 @@ void move_rel(const Model& m, Vec3 r0, Vec3 u0, double T, Vec3* r, Vec3* u) {
   *r = {r0.x + u0.x * s, r0.y + u0.y * s, r0.z + (u0.z + uT.z) * T / (g0 + g1)};
 }
 
+// Relativistic motion in uniform static E and B (the paper's UniformFieldRelativisticChin):
+// in proper time tau the 4-velocity Y = (w, u) = (gamma c, gamma v) obeys the linear system
+// dY/dtau = M Y, with (charge -e)
+//   M (w, u) = k (E.u / c, E w / c + u x B),  k = -e/m,
+// so Y(tau) = exp(M tau) Y0 and the 4-position X(tau) = X0 + (integral of exp(M s) ds from
+// 0 to tau) Y0, X = (c t, r).  Both come from one exponential of the 8x8 block matrix
+// [[M tau, I tau], [0, 0]] (Van Loan), whose upper blocks are exp(M tau) and the integral.
+// The exponential is the Taylor series after scaling by 2^-s (squared back s times).  The
+// proper time of a flight of laboratory duration T solves c t(tau) = c T, by Newton's method
+// (d(c t)/dtau = w > 0).
+void expm8(const double A[8][8], double E8[8][8]) {
+  double nrm = 0.0;
+  for (int i = 0; i < 8; ++i) {
+    double row = 0.0;
+    for (int j = 0; j < 8; ++j) row += std::fabs(A[i][j]);
+    nrm = std::max(nrm, row);
+  }
+  int s = 0;
+  while (nrm > 0.25) { nrm *= 0.5; ++s; }
+  const double scale_ = std::ldexp(1.0, -s);
+  double B[8][8], term[8][8], sum[8][8], tmp[8][8];
+  for (int i = 0; i < 8; ++i)
+    for (int j = 0; j < 8; ++j) {
+      B[i][j] = A[i][j] * scale_;
+      term[i][j] = (i == j) ? 1.0 : 0.0;
+      sum[i][j] = term[i][j];
+    }
+  for (int n = 1; n <= 24; ++n) {
+    for (int i = 0; i < 8; ++i)
+      for (int j = 0; j < 8; ++j) {
+        double acc = 0.0;
+        for (int l = 0; l < 8; ++l) acc += term[i][l] * B[l][j];
+        tmp[i][j] = acc / n;
+      }
+    for (int i = 0; i < 8; ++i)
+      for (int j = 0; j < 8; ++j) {
+        term[i][j] = tmp[i][j];
+        sum[i][j] += term[i][j];
+      }
+  }
+  for (int q = 0; q < s; ++q) {
+    for (int i = 0; i < 8; ++i)
+      for (int j = 0; j < 8; ++j) {
+        double acc = 0.0;
+        for (int l = 0; l < 8; ++l) acc += sum[i][l] * sum[l][j];
+        tmp[i][j] = acc;
+      }
+    std::memcpy(sum, tmp, sizeof(sum));
+  }
+  std::memcpy(E8, sum, sizeof(sum));
+}
+
+void move_rel_eb(const Model& m, Vec3 r0, Vec3 u0, double T, Vec3* r, Vec3* u) {
+  const double k = -kQe / kMe;
+  const Vec3 E{0.0, 0.0, m.p.E};
+  const Vec3 B = scale(m.bhat, m.p.B);
+  // the generator M on (w, u_x, u_y, u_z)
+  double M[4][4] = {{0.0, k * E.x / kC, k * E.y / kC, k * E.z / kC},
+                    {k * E.x / kC, 0.0, k * B.z, -k * B.y},
+                    {k * E.y / kC, -k * B.z, 0.0, k * B.x},
+                    {k * E.z / kC, k * B.y, -k * B.x, 0.0}};
+  const double Y0[4] = {kC * std::sqrt(1.0 + dot(u0, u0) / (kC * kC)), u0.x, u0.y, u0.z};
+  double E8[8][8];
+  auto eval = [&](double tau) {
+    double A[8][8] = {};
+    for (int i = 0; i < 4; ++i) {
+      for (int j = 0; j < 4; ++j) A[i][j] = M[i][j] * tau;
+      A[i][4 + i] = tau;
+    }
+    expm8(A, E8);
+  };
+  // Newton for the proper time: c t(tau) = c T
+  double tau = T * kC / Y0[0];
+  for (int it = 0; it < 50; ++it) {
+    eval(tau);
+    double ct = 0.0, w = 0.0;
+    for (int j = 0; j < 4; ++j) {
+      ct += E8[0][4 + j] * Y0[j];
+      w += E8[0][j] * Y0[j];
+    }
+    const double d = (ct - kC * T) / w;
+    tau -= d;
+    if (std::fabs(d) <= 1e-15 * std::fabs(tau)) break;
+  }
+  eval(tau);
+  double Y[4] = {}, X[4] = {};
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      Y[i] += E8[i][j] * Y0[j];
+      X[i] += E8[i][4 + j] * Y0[j];
+    }
+  if (u) *u = {Y[1], Y[2], Y[3]};
+  if (r) *r = {r0.x + X[1], r0.y + X[2], r0.z + X[3]};
+}
+
 // Kinetic energy (eV) of the velocity held: classically m |v|^2 / 2; relativistically
 // (gamma - 1) m c^2 = m |u|^2 / (gamma + 1), gamma = sqrt(1 + |u|^2/c^2).
 double kinetic_eV(Vec3 u, bool rel) {
@@ -358,7 +453,8 @@ double kinetic_eV(Vec3 u, bool rel) {
 
 // Motion of either mover.
 void advance(const Model& m, Vec3 r0, Vec3 v0, double T, Vec3* r, Vec3* v) {
-  if (m.p.relativistic) move_rel(m, r0, v0, T, r, v);
+  if (m.p.relativistic && m.p.B > 0.0) move_rel_eb(m, r0, v0, T, r, v);
+  else if (m.p.relativistic) move_rel(m, r0, v0, T, r, v);
   else move(m, r0, v0, T, r, v);
 }
 
@@ -763,10 +859,10 @@ void* or_create(const or_component* comps, int32_t n_comps, const or_params* p, 
     return nullptr;
   if (p->trial_strategy == 2 && (p->trial_bins < 1 || p->trial_bins > 100 || p->trial_grace < 1)) return nullptr;
   if (p->thermal_targets < 0 || p->thermal_targets > 1 || !(p->T_K >= 0.0) || !std::isfinite(p->T_K)) return nullptr;
-  // the relativistic mover: uniform E only, and not with moving targets (whose kinematics
-  // take laboratory velocities)
+  // the relativistic mover, not with moving targets (whose kinematics take laboratory
+  // velocities)
   if (p->relativistic < 0 || p->relativistic > 1) return nullptr;
-  if (p->relativistic && (p->B_T != 0.0 || p->thermal_targets)) return nullptr;
+  if (p->relativistic && p->thermal_targets) return nullptr;
   double fsum = 0.0;
   auto* m = new Model();
   m->p = {p->E_V_per_m, p->B_T, p->B_angle_rad, p->N_per_m3, p->T_K, p->init_energy_eV,

@@ -1,9 +1,10 @@
 """Pins of the oracle's relativistic mover (section "Theoretical framework" and the
-UniformFieldRelativisticChin field of section "Software architecture", for a uniform static
-E): the motion against a numerical integration of the relativistic Lorentz force,
-hyperbolic motion from rest, the classical limit, the work-energy theorem, the electron
-speed at the rest energy, and whole runs that reduce to the classical ones at swarm energies
-and never exceed c at high energies."""
+UniformFieldRelativisticChin field of section "Software architecture", uniform static E and
+B): the motion against a numerical integration of the relativistic Lorentz force,
+hyperbolic motion from rest, the relativistic cyclotron period, the classical limits of both
+movers, the work-energy theorem (B does no work), the electron speed at the rest energy, and
+whole runs that reduce to the classical ones at swarm energies and never exceed c at high
+energies."""
 import math
 
 import numpy as np
@@ -22,14 +23,17 @@ def _model(E, rel=1, **kw):
     return oracle.OracleModel([synth.maxwell_component(4.0)], E, relativistic=rel, **kw)
 
 
-def _ode(E, u0, T):
-    """du/dt = -(e/m) E z^, dr/dt = u / sqrt(1 + u^2/c^2), integrated numerically."""
-    a = -QE * E / ME
+def _ode(E, u0, T, B=0.0, th=0.0):
+    """du/dt = -(e/m) (E z^ + v x B), dr/dt = v = u / sqrt(1 + u^2/c^2), integrated
+    numerically (B in the xz plane at angle th from E)."""
+    k = -QE / ME
+    Ev = np.array([0.0, 0.0, E])
+    Bv = B * np.array([math.sin(th), 0.0, math.cos(th)])
 
     def f(t, y):
         u = y[3:]
-        g = math.sqrt(1.0 + u @ u / C ** 2)
-        return np.concatenate([u / g, [0.0, 0.0, a]])
+        v = u / math.sqrt(1.0 + u @ u / C ** 2)
+        return np.concatenate([v, k * (Ev + np.cross(v, Bv))])
 
     sol = solve_ivp(f, (0.0, T), np.concatenate([np.zeros(3), u0]), method="DOP853", rtol=1e-12,
                     atol=1e-30)
@@ -48,6 +52,53 @@ def test_motion_matches_lorentz_force_integration(E):
         r_ref, u_ref = _ode(E, u0, T)
         np.testing.assert_allclose(u, u_ref, rtol=1e-10, atol=1e-9 * speed)
         np.testing.assert_allclose(r, r_ref, rtol=1e-9, atol=1e-9 * np.abs(r_ref).max())
+
+
+@pytest.mark.parametrize("E,B,th", [(1e5, 0.5, 0.7), (3e8, 2.0, 1.2), (0.0, 1.0, 0.3), (2e4, 1.0, math.pi / 2),
+                                    (3e8, 1.0, math.pi / 2), (1e3, 3.0, 0.0)])
+def test_crossed_fields_match_lorentz_force_integration(E, B, th):
+    # (3e8 V/m, 1 T, crossed: |E| = c|B|, the degenerate case of the field invariants)
+    m = _model(E, B_T=B, B_angle_rad=th)
+    rng = np.random.default_rng(int(E) % 97 + int(B * 10))
+    for _ in range(5):
+        u0 = rng.normal(size=3) * C * rng.choice([1e-3, 0.5, 3.0])
+        T = float(rng.uniform(0.3, 3.0) / (QE * B / ME))
+        r, u = m.move(np.zeros(3), u0, T)
+        r_ref, u_ref = _ode(E, u0, T, B, th)
+        np.testing.assert_allclose(u, u_ref, rtol=0, atol=1e-11 * np.abs(u_ref).max())
+        np.testing.assert_allclose(r, r_ref, rtol=0, atol=1e-11 * np.abs(r_ref).max())
+
+
+def test_relativistic_cyclotron_period():
+    # E = 0: gamma is constant and the transverse motion closes after T = 2 pi gamma m / (e B)
+    B = 1.5
+    m = _model(0.0, B_T=B, B_angle_rad=0.0)
+    for beta_gamma in (1e-3, 0.7, 5.0):
+        u0 = np.array([beta_gamma * C, 0.0, 0.2 * beta_gamma * C])
+        g = math.sqrt(1 + u0 @ u0 / C ** 2)
+        T = 2 * math.pi * g * ME / (QE * B)
+        r, u = m.move(np.zeros(3), u0, T)
+        np.testing.assert_allclose(u, u0, rtol=0, atol=1e-12 * np.linalg.norm(u0))
+        assert abs(r[0]) < 1e-11 * np.linalg.norm(r) and abs(r[1]) < 1e-11 * np.linalg.norm(r)
+        assert r[2] == pytest.approx(u0[2] / g * T, rel=1e-12)
+
+
+def test_crossed_fields_classical_limit_and_work():
+    E, B, th = 2e4, 0.8, 1.0
+    rel, cl = _model(E, 1, B_T=B, B_angle_rad=th), _model(E, 0, B_T=B, B_angle_rad=th)
+    u0 = np.array([2e5, -1e5, 3e5])
+    for T in (1e-13, 1e-11, 3e-11):
+        r1, u1 = rel.move(np.zeros(3), u0, T)
+        r0, v0 = cl.move(np.zeros(3), u0, T)
+        beta2 = max(u0 @ u0, u1 @ u1) / C ** 2
+        np.testing.assert_allclose(r1, r0, rtol=0, atol=10 * beta2 * np.abs(r0).max())
+        # the magnetic force does no work: the energy gain is the work of E alone
+        assert rel.kinetic(u1) - rel.kinetic(u0) == pytest.approx(-E * r1[2], rel=1e-9)
+    # B -> 0 joins the uniform-E closed form
+    tiny, none = _model(E, B_T=1e-12), _model(E)
+    r1, u1 = tiny.move(np.zeros(3), u0, 1e-11)
+    r2, u2 = none.move(np.zeros(3), u0, 1e-11)
+    np.testing.assert_allclose(r1, r2, rtol=1e-9)
 
 
 def test_hyperbolic_motion_from_rest():
@@ -127,9 +178,16 @@ def test_fast_electrons_stay_below_c():
     assert np.max(np.linalg.norm(c["r"], axis=1) / c["t"]) > C   # the classical mover would not
 
 
+def test_crossed_field_swarm_matches_classical():
+    cfg = synth.cfg1_maxwell(n_electrons=3000, n_collisions=2000).scaled(B_T=2.0, B_angle_rad=math.pi / 4)
+    a = tallies(oracle.OracleModel.from_config(cfg).run(cfg.n_electrons, cfg.n_collisions, 1).records)
+    b = tallies(oracle.OracleModel.from_config(cfg.scaled(relativistic=1)).run(cfg.n_electrons, cfg.n_collisions,
+                                                                               1).records)
+    for key in ("W", "Wx", "Wy", "mean_energy"):
+        assert abs(a[key][0] - b[key][0]) < 3 * math.hypot(a[key][1], b[key][1]) + 1e-4 * abs(a[key][0]), key
+
+
 def test_invalid_relativistic_refused():
-    with pytest.raises(ValueError):
-        oracle.OracleModel.from_config(synth.cfg1_maxwell().scaled(relativistic=1, B_T=1.0))
     with pytest.raises(ValueError):
         oracle.OracleModel.from_config(synth.cfg1_maxwell().scaled(relativistic=1, thermal_targets=1))
     with pytest.raises(ValueError):
