@@ -307,7 +307,7 @@ def main():
         "device_ms_per_step": avg_ms,
         "roofline": {"bound": "alu", "achieved": achieved / 1e9, "peak": PEAK_LANE_OPS / 1e9, "unit": "Gop/s",
                      "frac": achieved / PEAK_LANE_OPS, "traffic": committed_traffic(),
-                     "kernel": "k_swarm_dummy<float,false,false,false>",
+                     "kernel": "k_swarm_dummy<float,false,false,0>",
                      "ops_per_trial": OPS_PER_TRIAL, "ops_per_real": OPS_PER_REAL},
     }
     if not args.no_variable:

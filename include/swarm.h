@@ -156,11 +156,14 @@ typedef struct {
                               forbidden (counted in n_forbidden).  Rates and the null test keep
                               the laboratory energy. */
   int32_t relativistic;    /* 0: classical motion (UniformFieldClassic); 1: relativistic
-                              motion in a uniform E (the paper's UniformFieldRelativisticChin,
-                              B = 0 only): lanes hold the proper velocity u = gamma v, the
-                              rates of eq. (frequency) take the true speed |u|/gamma, and the
-                              energy-transfer equations are unchanged.  Needs SWARM_FP64,
-                              B_T = 0 and thermal_targets = 0 (else SWARM_ERR_INVALID_ARG). */
+                              motion in the uniform E and B (the paper's
+                              UniformFieldRelativisticChin): lanes hold the proper velocity
+                              u = gamma v, moved exactly (closed forms for B = 0; with B, the
+                              exponential of the field generator in proper time, whose
+                              duration is solved from the laboratory flight time); the rates
+                              of eq. (frequency) take the true speed |u|/gamma, and the
+                              energy-transfer equations are unchanged.  Needs SWARM_FP64 and
+                              thermal_targets = 0 (else SWARM_ERR_INVALID_ARG). */
 } swarm_params;
 
 /* Per-electron result record (one per electron that existed in the run), as stored on

@@ -419,18 +419,39 @@ void move_rel_eb(const Model& m, Vec3 r0, Vec3 u0, double T, Vec3* r, Vec3* u) {
     }
     expm8(A, E8);
   };
-  // Newton for the proper time: c t(tau) = c T
-  double tau = T * kC / Y0[0];
-  for (int it = 0; it < 50; ++it) {
-    eval(tau);
-    double ct = 0.0, w = 0.0;
+  // The proper time of the flight solves f(tau) = c t(tau) - c T = 0 with tau in [0, T] (dt/dtau
+  // = gamma >= 1), f increasing (f' = w > 0).  Newton's method from T/gamma0, safeguarded: a
+  // bisection step of the bracket whenever the Newton step would leave it or would not halve
+  // the step before (in a strong E, gamma grows like exp(l tau) and Newton alone crawls down
+  // from a far guess), or the exponential overflows.
+  double lo = 0.0, hi = T, tau = std::min(T * kC / Y0[0], T), step_old = T, step = T;
+  auto f_w = [&](double t, double* f, double* w) {
+    eval(t);
+    double ct = 0.0, ww = 0.0;
     for (int j = 0; j < 4; ++j) {
       ct += E8[0][4 + j] * Y0[j];
-      w += E8[0][j] * Y0[j];
+      ww += E8[0][j] * Y0[j];
     }
-    const double d = (ct - kC * T) / w;
-    tau -= d;
-    if (std::fabs(d) <= 1e-15 * std::fabs(tau)) break;
+    *f = ct - kC * T;
+    *w = ww;
+    return std::isfinite(*f) && std::isfinite(*w) && *w > 0.0;
+  };
+  double f, w;
+  bool ok = f_w(tau, &f, &w);
+  for (int it = 0; it < 400 && T > 0.0; ++it) {
+    if (!ok || f > 0.0) hi = tau; else lo = tau;
+    const double newton = ok ? tau - f / w : -1.0;
+    if (!ok || !(newton >= lo && newton <= hi) || std::fabs(2.0 * f) > std::fabs(step_old * w)) {
+      step_old = step;
+      step = 0.5 * (hi - lo);
+      tau = lo + step;
+    } else {
+      step_old = step;
+      step = tau - newton;
+      tau = newton;
+    }
+    if (std::fabs(step) <= 1e-12 * tau || hi - lo <= 1e-15 * hi) break;
+    ok = f_w(tau, &f, &w);
   }
   eval(tau);
   double Y[4] = {}, X[4] = {};

@@ -158,8 +158,6 @@ swarm_status validate(const swarm_component* comps, int32_t n_comps, const swarm
   if (p->thermal_targets && (!(p->T_K >= 0.0) || !std::isfinite(p->T_K)))
     return fail(SWARM_ERR_INVALID_ARG, "moving targets need a gas temperature T_K >= 0");
   if (p->relativistic != 0 && p->relativistic != 1) return fail(SWARM_ERR_INVALID_ARG, "relativistic must be 0 or 1");
-  if (p->relativistic && p->B_T != 0.0)
-    return fail(SWARM_ERR_INVALID_ARG, "the relativistic mover takes a uniform E only (B_T = 0)");
   if (p->relativistic && p->thermal_targets)
     return fail(SWARM_ERR_INVALID_ARG, "the relativistic mover does not take moving targets");
   if (p->relativistic && p->precision != SWARM_FP64)

@@ -154,6 +154,8 @@ struct InstanceDesc {
   float c_eps_f, c_speed_f, speed0_f, az_f, omega_rev_f, bx_f, bz_f, vDy_f, apar_f;
   float sceps_f, aze_f, apare_f, nup24_f, Pf_f, twoPf_f;   // FP32 energy-unit constants
   double Pf_d, twoPf_d;
+  double rel_kEc, rel_kBx, rel_kBz;       // relativistic mover in E and B: generator and
+  double rel_l1, rel_l2, rel_p1, rel_p2, rel_K;   // field invariants
   int32_t built_ok;           // 1 after a successful build, -1 if a node has zero rate
   int32_t pad_;
 };

@@ -396,6 +396,32 @@ __global__ void k_build_constants(InstanceDesc* desc) {
     d.bz = cos(d.B_angle);
     d.vDy = d.B > 0.0 ? d.E * d.B * d.bx / (d.B * d.B) : 0.0;   // (E z^ x B b^)/B^2 = (0, E sin th / B, 0)
     d.apar = d.az * d.bz;
+    {
+      // relativistic mover in E and B: the generator M (k = -e/m; E along z, B in the xz
+      // plane) and the invariants of the field, l1^2 - l2^2 = k^2 (E^2/c^2 - B^2) and
+      // l1 l2 = k^2 |E.B|/c (the smaller of l1^2, l2^2 from their product, no cancellation)
+      const double k = -kQe / kMe, k2 = k * k;
+      const double Bx = d.B * d.bx, Bz = d.B * d.bz;
+      d.rel_kEc = k * d.E / kC;
+      d.rel_kBx = k * Bx;
+      d.rel_kBz = k * Bz;
+      const double F1 = (d.E / kC) * (d.E / kC) - d.B * d.B, F2 = d.E * Bz / kC;
+      const double sq = sqrt(F1 * F1 + 4.0 * F2 * F2);
+      double l1s, l2s;
+      if (F1 >= 0.0) {
+        l1s = 0.5 * k2 * (F1 + sq);
+        l2s = l1s > 0.0 ? k2 * k2 * F2 * F2 / l1s : 0.0;
+      } else {
+        l2s = 0.5 * k2 * (sq - F1);
+        l1s = k2 * k2 * F2 * F2 / l2s;
+      }
+      const double sum = l1s + l2s;
+      d.rel_l1 = sqrt(l1s);
+      d.rel_l2 = sqrt(l2s);
+      d.rel_p1 = sum > 0.0 ? l1s / sum : 0.5;
+      d.rel_p2 = sum > 0.0 ? l2s / sum : 0.5;
+      d.rel_K = sum > 0.0 ? l1s * l2s / sum : 0.0;
+    }
     d.c_eps_f = static_cast<float>(d.c_eps);
     d.c_speed_f = static_cast<float>(d.c_speed);
     d.speed0_f = static_cast<float>(d.speed0);
@@ -477,7 +503,9 @@ struct Consts {
   bool variable; // a per-lane trial frequency: the variable or the binned strategy
   bool binned;   // the binned strategy
   bool thermal;  // moving targets
-  bool relativistic;  // relativistic mover (FP64, B = 0): lanes hold u = gamma v
+  bool relativistic;  // relativistic mover (FP64): lanes hold u = gamma v
+  double rel_kEc, rel_kBx, rel_kBz;       // relativistic in E and B: the generator M
+  double rel_l1, rel_l2, rel_p1, rel_p2, rel_K;   // and its invariants
   uint32_t grace0;
   int G, nc, off, p;
   int off1;      // off - 1: raw index of entry 0 of the padded LDS table
@@ -519,6 +547,8 @@ __device__ __forceinline__ Consts<R> load_consts(const InstanceDesc& d) {
   c.binned = d.trial_strategy == SWARM_TRIAL_BINNED;
   c.thermal = d.thermal_targets != 0;
   c.relativistic = d.relativistic != 0;
+  c.rel_kEc = d.rel_kEc; c.rel_kBx = d.rel_kBx; c.rel_kBz = d.rel_kBz;
+  c.rel_l1 = d.rel_l1; c.rel_l2 = d.rel_l2; c.rel_p1 = d.rel_p1; c.rel_p2 = d.rel_p2; c.rel_K = d.rel_K;
   c.bin_of = d.bin_of;
   if constexpr (sizeof(R) == 8) c.bin_nup = d.bin_nup64;
   else c.bin_nup = d.bin_nup32;
@@ -612,11 +642,131 @@ __device__ __forceinline__ void set_anchor(Lane<R>& L, const Consts<R>& C) {
 
 // Energy (eV) during free flight, eps = (m/2e) |v(T)|^2 (classical motion in uniform E
 // and B).
-// With the relativistic mover (EXT == 2, FP64, B = 0) the lane holds the proper velocity u =
-// gamma v, which grows like v does classically, and the kinetic energy is (gamma - 1) m c^2 =
+// Relativistic motion in uniform static E and B (the paper's UniformFieldRelativisticChin),
+// FP64.  In proper time tau the 4-velocity Y = (w, u) = (gamma c, u) obeys dY/dtau = M Y,
+// M (w, u) = k (E.u/c, E w/c + u x B), k = -e/m.  M^2 has the eigenvalues l1^2 and -l2^2 (from
+// the field invariants), so exp(M tau) = a0 + a1 M + a2 M^2 + a3 M^3 with
+//   a0 = 1 + K (Ch - Ct), a1 = tau + K (Sh - St), a2 = p1 Ch + p2 Ct, a3 = p1 Sh + p2 St,
+//   p1 = l1^2/(l1^2 + l2^2), p2 = l2^2/(l1^2 + l2^2), K = l1^2 l2^2/(l1^2 + l2^2),
+//   Ch = (cosh l1 tau - 1)/l1^2, Ct = (1 - cos l2 tau)/l2^2,
+//   Sh = (sinh(l1 tau)/l1 - tau)/l1^2, St = (tau - sin(l2 tau)/l2)/l2^2,
+// and its integral over [0, tau] has b0 = tau + K (Sh - St), b1 = tau^2/2 + K (Qh - Qt),
+// b2 = p1 Sh + p2 St, b3 = p1 Qh + p2 Qt with Qh = (Ch - tau^2/2)/l1^2, Qt = (tau^2/2 - Ct)/l2^2.
+// The C, S, Q functions are tau^n g(l tau) with g taken from its series for small arguments
+// (their tau -> 0 limits tau^2/2, tau^3/6, tau^4/24 without cancellation).  With l1 = l2 = 0
+// (no field, or crossed fields with |E| = c|B|) p1 = p2 = 1/2 and K = 0 give the polynomial
+// exp of the nilpotent M.  The laboratory time of a flight fixes tau through c t(tau) = b0 Y0^0
+// + ... + b3 Y3^0 (Newton; d(c t)/dtau = w > 0).
+
+// g_n(x) = (cosh x - sum_{j<n, j even} x^j/j!) / x^n for n = 2, 4 and (sinh x - x)/x^3 (n = 3),
+// and their trigonometric partners with alternating signs, from the series for |x| < 1.
+__device__ __forceinline__ void rel_coeffs(double x, bool hyperbolic, double* c2, double* c3, double* c4) {
+  const double x2 = x * x;
+  if (fabs(x) < 1.0) {
+    const double s = hyperbolic ? x2 : -x2;
+    // sum_n s^n / (2n + k)! for k = 2, 3, 4, n = 0..9
+    double a2 = 0.0, a3 = 0.0, a4 = 0.0;
+    double t = 1.0;
+    double d2 = 2.0, d3 = 6.0, d4 = 24.0;   // (k)!
+    for (int n = 0; n < 10; ++n) {
+      a2 += t / d2; a3 += t / d3; a4 += t / d4;
+      t *= s;
+      d2 *= (2 * n + 3) * (2 * n + 4);
+      d3 *= (2 * n + 4) * (2 * n + 5);
+      d4 *= (2 * n + 5) * (2 * n + 6);
+    }
+    *c2 = a2; *c3 = a3; *c4 = a4;
+  } else if (hyperbolic) {
+    const double ch = cosh(x), sh = sinh(x);
+    *c2 = (ch - 1.0) / x2;
+    *c3 = (sh - x) / (x2 * x);
+    *c4 = (ch - 1.0 - 0.5 * x2) / (x2 * x2);
+  } else {
+    double sn, cs;
+    sincos(x, &sn, &cs);
+    *c2 = (1.0 - cs) / x2;
+    *c3 = (x - sn) / (x2 * x);
+    *c4 = (cs - 1.0 + 0.5 * x2) / (x2 * x2);
+  }
+}
+
+// State after a flight of laboratory duration T from the anchor: proper velocity u and, if
+// wanted, the displacement.  The anchor holds u0; M^k Y0 are formed by the map above.
+__device__ __forceinline__ void rel_eb_state(const Lane<double>& L, const Consts<double>& C, double T, double* u,
+                                             double* dr) {
+  const double c = kC;
+  double y[4][4];   // y[k] = M^k Y0 as (w, u_x, u_y, u_z)
+  y[0][1] = L.vx; y[0][2] = L.vy; y[0][3] = L.vz;
+  y[0][0] = c * sqrt(1.0 + (L.vx * L.vx + L.vy * L.vy + L.vz * L.vz) / (c * c));
+#pragma unroll
+  for (int k = 1; k < 4; ++k) {
+    const double* a = y[k - 1];
+    y[k][0] = C.rel_kEc * a[3];
+    y[k][1] = C.rel_kBz * a[2];
+    y[k][2] = C.rel_kBx * a[3] - C.rel_kBz * a[1];
+    y[k][3] = C.rel_kEc * a[0] - C.rel_kBx * a[2];
+  }
+  double a0, a1, a2, a3, b0, b1, b2, b3;
+  auto coeffs = [&](double tau) {
+    double g2, g3, g4, t2, t3, t4;
+    rel_coeffs(C.rel_l1 * tau, true, &g2, &g3, &g4);
+    rel_coeffs(C.rel_l2 * tau, false, &t2, &t3, &t4);
+    const double tt = tau * tau;
+    const double Ch = tt * g2, Sh = tt * tau * g3, Qh = tt * tt * g4;
+    const double Ct = tt * t2, St = tt * tau * t3, Qt = tt * tt * t4;
+    a0 = 1.0 + C.rel_K * (Ch - Ct);
+    a1 = tau + C.rel_K * (Sh - St);
+    a2 = C.rel_p1 * Ch + C.rel_p2 * Ct;
+    a3 = C.rel_p1 * Sh + C.rel_p2 * St;
+    b0 = a1;
+    b1 = 0.5 * tt + C.rel_K * (Qh - Qt);
+    b2 = a3;
+    b3 = C.rel_p1 * Qh + C.rel_p2 * Qt;
+  };
+  // Proper time of the flight: f(tau) = c t(tau) - c T = 0 on [0, T] (dt/dtau = gamma >= 1),
+  // f increasing with f' = w.  Newton from T c / w0, with a bisection of the bracket instead
+  // whenever the Newton step would leave it, would not halve the step before, or the
+  // hyperbolic functions overflow (gamma can grow like exp(l1 tau): Newton alone would crawl
+  // down from a far guess by about 1/l1 per step).  Every path ends within 200 steps.
+  double lo = 0.0, hi = T, tau = fmin(T * c / y[0][0], T), step = T, step_old = T;
+  for (int it = 0; it < 200 && T > 0.0; ++it) {
+    coeffs(tau);
+    const double f = (b0 * y[0][0] + b1 * y[1][0] + b2 * y[2][0] + b3 * y[3][0]) - c * T;
+    const double w = a0 * y[0][0] + a1 * y[1][0] + a2 * y[2][0] + a3 * y[3][0];
+    const bool ok = isfinite(f) && isfinite(w) && w > 0.0;
+    if (!ok || f > 0.0) hi = tau; else lo = tau;
+    const double newton = ok ? tau - f / w : -1.0;
+    step_old = step;
+    if (!ok || !(newton >= lo && newton <= hi) || fabs(2.0 * f) > fabs(step_old * w)) {
+      step = 0.5 * (hi - lo);
+      tau = lo + step;
+    } else {
+      step = tau - newton;
+      tau = newton;
+    }
+    if (fabs(step) <= 1e-12 * tau || hi - lo <= 1e-15 * hi) break;
+  }
+  coeffs(tau);
+#pragma unroll
+  for (int i = 1; i < 4; ++i) {
+    u[i - 1] = a0 * y[0][i] + a1 * y[1][i] + a2 * y[2][i] + a3 * y[3][i];
+    if (dr) dr[i - 1] = b0 * y[0][i] + b1 * y[1][i] + b2 * y[2][i] + b3 * y[3][i];
+  }
+}
+
+// With the relativistic mover (EXT == 2, FP64) the lane holds the proper velocity u = gamma v
+// (with B = 0 it grows like v does classically), and the kinetic energy is (gamma - 1) m c^2 =
 // m |u|^2 / (gamma + 1), gamma = sqrt(1 + |u|^2/c^2).
 template <typename R, bool HB, int EXT = 0>
 __device__ __forceinline__ R energy_at(const Lane<R>& L, const Consts<R>& C, R T) {
+  if constexpr (EXT == 2 && HB && sizeof(R) == 8) {
+    if (C.relativistic && C.magnetic) {
+      double u[3];
+      rel_eb_state(L, C, T, u, nullptr);
+      const double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+      return C.c_eps * (2.0 * u2) / (1.0 + sqrt(1.0 + u2 * (1.0 / (kC * kC))));
+    }
+  }
   if (!HB || !C.magnetic) {
     const R vz = fma_(C.aze, T, L.e_vz);
     if constexpr (sizeof(R) == 4) {
@@ -765,6 +915,13 @@ template <typename R, bool HB, int EXT = 0>
 __device__ __forceinline__ void move_full(const Lane<R>& L, const Consts<R>& C, R T,
                                           R* vx, R* vy, R* vz, double* rx, double* ry, double* rz) {
   if constexpr (EXT == 2 && sizeof(R) == 8) {
+    if (HB && C.relativistic && C.magnetic) {
+      double u[3], dr[3];
+      rel_eb_state(L, C, T, u, dr);
+      *vx = u[0]; *vy = u[1]; *vz = u[2];
+      *rx = L.rx + dr[0]; *ry = L.ry + dr[1]; *rz = L.rz + dr[2];
+      return;
+    }
     if (C.relativistic) {
       // Relativistic, B = 0 (the lane holds u = gamma v): u_z grows by a T; z advances by
       // c^2 (gamma1 - gamma0)/a = (u_z0 + u_z1) T / (gamma0 + gamma1), and x, y by

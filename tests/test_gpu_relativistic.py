@@ -1,8 +1,9 @@
-"""The relativistic mover (UniformFieldRelativisticChin in a uniform E) on the GPU, through the
-C ABI, against the FP64 oracle on the same seeded inputs: per-electron records and event
+"""The relativistic mover (UniformFieldRelativisticChin, uniform E and B) on the GPU, through
+the C ABI, against the FP64 oracle on the same seeded inputs: per-electron records and event
 sequences element by element, from swarm energies to MeV electrons on a grid up to 2^24 eV,
-with the binned trial frequency and real secondaries; batches that mix kernel levels, the
-pooled schedule and serving epochs that change no bit; and the refused combinations."""
+in crossed and oblique magnetic fields (the |E| = c|B| degenerate case included), with the
+binned trial frequency and real secondaries; batches that mix kernel levels, the pooled
+schedule and serving epochs that change no bit; and the refused combinations."""
 import time
 
 import numpy as np
@@ -34,6 +35,10 @@ CASES = [
     ("argon-1000Td", lambda: _rel(synth.cfg2_argon_sweep()[31]), {}),
     ("argon-100Td-binned", lambda: _rel(synth.cfg2_argon_sweep()[21]).scaled(trial_strategy=2, trial_grace=50), {}),
     ("fast-keV-MeV", _fast, GRID24),
+    ("maxwell-10Td-B2T-45deg", lambda: _rel(synth.cfg1_maxwell().scaled(B_T=2.0, B_angle_rad=0.785)), {}),
+    ("argon-100Td-B1T-crossed", lambda: _rel(synth.cfg2_argon_sweep()[21].scaled(B_T=1.0, B_angle_rad=1.5707963267948966)), {}),
+    ("fast-crossed-E=cB", lambda: _fast().scaled(B_T=0.1, B_angle_rad=1.5707963267948966), GRID24),
+    ("fast-oblique", lambda: _fast().scaled(B_T=0.05, B_angle_rad=0.4), GRID24),
 ]
 
 
@@ -59,7 +64,7 @@ def test_fp64_records_and_events(gpu, name, mk, grid):
 
 def test_fp64_real_secondaries_relativistic(gpu):
     sw = gpu
-    cfg = _rel(synth.cfg3_mixture_real(n_electrons=48, n_collisions=1200).scaled(B_T=0.0))
+    cfg = _rel(synth.cfg3_mixture_real(n_electrons=48, n_collisions=1200))
     s = sw.Swarm.from_config(cfg, sw.SWARM_FP64)
     s.run(48, 1200, 4)
     r = oracle.OracleModel.from_config(cfg).run(48, 1200, 4)
@@ -73,8 +78,6 @@ def test_refused_combinations(gpu):
     cfg = _rel(synth.cfg1_maxwell())
     with pytest.raises(sw.SwarmError):
         sw.Swarm.from_config(cfg, sw.SWARM_FP32_MIXED)
-    with pytest.raises(sw.SwarmError):
-        sw.Swarm.from_config(cfg.scaled(B_T=0.5), sw.SWARM_FP64)
     with pytest.raises(sw.SwarmError):
         sw.Swarm.from_config(cfg.scaled(thermal_targets=1), sw.SWARM_FP64)
     with pytest.raises(sw.SwarmError):
@@ -100,7 +103,7 @@ def test_batch_and_pooled_keep_relativistic_results(gpu):
 
 def test_server_epochs_keep_relativistic_results(gpu):
     sw = gpu
-    reqs = [_rel(synth.cfg5_request(i).scaled(n_electrons=3000, n_collisions=700, B_T=0.0)) for i in range(3)]
+    reqs = [_rel(synth.cfg5_request(i).scaled(n_electrons=3000, n_collisions=700)) for i in range(3)]
     alone = []
     for c in reqs:
         s = sw.Swarm.from_config(c, sw.SWARM_FP64)

@@ -69,6 +69,20 @@ def test_crossed_fields_match_lorentz_force_integration(E, B, th):
         np.testing.assert_allclose(r, r_ref, rtol=0, atol=1e-11 * np.abs(r_ref).max())
 
 
+@pytest.mark.parametrize("T", [3e-8, 1e-6])
+def test_long_flight_in_strong_oblique_field(T):
+    # gamma grows like exp(l tau) in proper time: a first guess tau = T is hundreds of e-folds
+    # too far, and the proper time must still be found
+    E, B, th = 3e7, 0.05, 0.4
+    m = _model(E, B_T=B, B_angle_rad=th)
+    u0 = np.array([3e5, -1e5, 2e5])
+    r, u = m.move(np.zeros(3), u0, T)
+    r_ref, u_ref = _ode(E, u0, T, B, th)
+    np.testing.assert_allclose(u, u_ref, rtol=0, atol=1e-10 * np.abs(u_ref).max())
+    np.testing.assert_allclose(r, r_ref, rtol=0, atol=1e-10 * np.abs(r_ref).max())
+    assert math.sqrt(1 + u @ u / C ** 2) > 100
+
+
 def test_relativistic_cyclotron_period():
     # E = 0: gamma is constant and the transverse motion closes after T = 2 pi gamma m / (e B)
     B = 1.5
