@@ -56,6 +56,8 @@ def parse():
                     help="skip the leg with screened-Coulomb scattering")
     ap.add_argument("--serve-rate", type=float, default=5.0)
     ap.add_argument("--serve-seconds", type=float, default=8.0)
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving leg (one JSON line), e.g. for a sweep of --serve-rate")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the launch shape with the autotuner first (default: the library default)")
     ap.add_argument("--quiet", action="store_true")
@@ -251,6 +253,10 @@ def main():
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.serve_only:
+        import paper_1901_08140_amd as sw
+        print(json.dumps({"serving": serve(sw, args)}), flush=True)
+        return
     if args.copy_probe:
         n = args.copy_probe // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
