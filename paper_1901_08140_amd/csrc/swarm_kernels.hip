@@ -850,6 +850,14 @@ __device__ __forceinline__ void apply_trial_frequency(Lane<R>& L, const Consts<R
     L.nup24 = 0.0;
   }
 }
+// The lane's nu'.  FP32 lanes read it back from nu' 2^-24 (exact: a power-of-two scale), so
+// the compiler need not keep both in registers.
+template <typename R>
+__device__ __forceinline__ R lane_nup(const Lane<R>& L) {
+  if constexpr (sizeof(R) == 4) return L.nup24 * 0x1.0p24f;
+  else return L.nup;
+}
+
 template <typename R>
 __device__ __forceinline__ void set_trial_frequency(Lane<R>& L, const Consts<R>& C, R v) {
   if (v < C.nup) apply_trial_frequency(L, C, v);
@@ -1048,7 +1056,7 @@ __device__ __forceinline__ void save_state(const InstanceDesc& d, const Lane<R>&
   s.block = L.block; s.k = L.k; s.k_start = L.k_start; s.G = L.G; s.D = L.D;
   s.n_forb = L.nforb; s.n_over = L.nover; s.n_first = L.nfirst;
   s.started = 1; s.pad = L.flags;
-  s.nup = static_cast<double>(EXT ? L.nup : C.nup);
+  s.nup = static_cast<double>(EXT ? lane_nup(L) : C.nup);
   s.grace = EXT ? L.grace : 0u;
   s.n_fail = L.nfail;
   d.saved[e] = s;
@@ -1283,7 +1291,7 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
   if (EXT && C.variable) {
     // the total rate the trial compared with (same table entry and weight)
     nu_eps = lerp_pair(s_nu[L.p_gi - C.off1], L.p_w);
-    if (nu_eps > L.nup) {
+    if (nu_eps > lane_nup(L)) {
       // Fail: nu(eps) <= nu' does not hold.  Back to the state of the last real collision
       // (the anchor: T = 0) with a new nu'; the grace count restarts.
       L.nfail += 1u;
@@ -1601,7 +1609,7 @@ __device__ __forceinline__ void pool_put(const Pool<R>& P, int s, const Lane<R>&
   P.U(PU_FLAGS, s) = L.flags; P.U(PU_NFAIL, s) = L.nfail;
   P.U(PU_IDLO, s) = static_cast<uint32_t>(L.id); P.U(PU_IDHI, s) = static_cast<uint32_t>(L.id >> 32);
   if constexpr (EXT) {
-    P.V(PR_NUP, s) = L.nup;
+    P.V(PR_NUP, s) = lane_nup(L);
     P.U(PU_GRACE, s) = L.grace;
   }
 }
@@ -1651,7 +1659,7 @@ __device__ __forceinline__ void pool_give(const Pool<R>& P, int s, const Lane<R>
   P.U(PU_G, s) = S.G; P.U(PU_D, s) = S.D; P.U(PU_K, s) = S.k; P.U(PU_FLAGS, s) = S.flags;
   P.U(PU_STATE, s) = static_cast<uint32_t>(S.state); P.U(PU_NFAIL, s) = S.nfail;
   if constexpr (EXT) {
-    P.V(PR_NUP, s) = S.nup;
+    P.V(PR_NUP, s) = lane_nup(S);
     P.U(PU_GRACE, s) = S.grace;
   }
 }
