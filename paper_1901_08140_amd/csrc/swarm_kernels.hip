@@ -202,30 +202,6 @@ __device__ __forceinline__ void iso_dir(R uc, R up, R* nx, R* ny, R* nz) {
   *nz = ct;
 }
 
-// Octave-grid position of an energy: eps = 2^e (1 + f), node g = (e - emin) P + floor(f P),
-// weight w = f P - floor(f P).  Both come straight from the binary representation (P is a
-// power of two), so they are exact.  Below the grid: node 0, w = 0; at or above the top
-// node 2^emax: the last node, w = 0 (`over` set).
-__device__ __forceinline__ void grid_pos(float eps, int off, int p, int G, int* g, float* w, bool* over) {
-  const uint32_t b = __float_as_uint(eps);
-  const int graw = static_cast<int>(b >> (23 - p)) - off;
-  const float w1 = __uint_as_float(((b << (9 + p)) >> 9) | 0x3F800000u) - 1.0f;
-  const bool in = (graw >= 0) & (graw < G - 1);
-  *g = graw < 0 ? 0 : (graw > G - 1 ? G - 1 : graw);
-  *w = in ? w1 : 0.0f;
-  *over = graw >= G - 1;
-}
-__device__ __forceinline__ void grid_pos(double eps, int off, int p, int G, int* g, double* w, bool* over) {
-  const uint64_t b = static_cast<uint64_t>(__double_as_longlong(eps));
-  const int64_t graw = static_cast<int64_t>(b >> (52 - p)) - off;
-  const uint64_t mb = ((b << (12 + p)) >> 12) | 0x3FF0000000000000ull;
-  const double w1 = __longlong_as_double(static_cast<long long>(mb)) - 1.0;
-  const bool in = (graw >= 0) & (graw < G - 1);
-  *g = graw < 0 ? 0 : (graw > G - 1 ? G - 1 : static_cast<int>(graw));
-  *w = in ? w1 : 0.0;
-  *over = graw >= G - 1;
-}
-
 template <typename R> struct Pair;
 template <> struct Pair<float> { using T = float2; };
 template <> struct Pair<double> { using T = double2; };
@@ -840,7 +816,7 @@ __device__ __forceinline__ void constant_trial_frequency(Lane<R>& L, const Const
   L.nup24 = C.nup24;
 }
 template <typename R>
-__device__ __forceinline__ void apply_trial_frequency(Lane<R>& L, const Consts<R>& C, R v) {
+__device__ __forceinline__ void apply_trial_frequency(Lane<R>& L, R v) {
   L.nup = v;
   if constexpr (sizeof(R) == 4) {
     L.cT = 0.693147180559945309f / v;
@@ -860,7 +836,7 @@ __device__ __forceinline__ R lane_nup(const Lane<R>& L) {
 
 template <typename R>
 __device__ __forceinline__ void set_trial_frequency(Lane<R>& L, const Consts<R>& C, R v) {
-  if (v < C.nup) apply_trial_frequency(L, C, v);
+  if (v < C.nup) apply_trial_frequency(L, v);
   else constant_trial_frequency(L, C);     // at the cap: exactly the constant strategy
 }
 
@@ -1076,7 +1052,7 @@ __device__ __forceinline__ void load_state(const InstanceDesc& d, Lane<R>& L, co
   if constexpr (EXT) {
     // the same derived values as when nu' was set (at the cap: the constant strategy's)
     const R v = static_cast<R>(s.nup);
-    if (C.variable && v < C.nup) apply_trial_frequency(L, C, v);
+    if (C.variable && v < C.nup) apply_trial_frequency(L, v);
     else constant_trial_frequency(L, C);
     L.grace = s.grace;
   }
@@ -1227,7 +1203,7 @@ __device__ __forceinline__ void moving_target(const Lane<R>& L, const Consts<R>&
 // scattering block's first two uniforms, or theta about V1 - Vcm for the anisotropic
 // models).  Gives the direction of V1' and the energy after (zero for attachment).
 template <typename R>
-__device__ __forceinline__ void moving_target_outcome(const ChannelDev& ch, const Consts<R>& C, R eps, R u_c, R u_p,
+__device__ __forceinline__ void moving_target_outcome(const ChannelDev& ch, R eps, R u_c, R u_p,
                                                       R vx, R vy, R vz, const double* vcm, double g2,
                                                       R* nx, R* ny, R* nz, R* epsp) {
   const double ux = static_cast<double>(vx) - vcm[0], uy = static_cast<double>(vy) - vcm[1],
@@ -1361,7 +1337,7 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
   const R u_c = uni(h.x, l.x, R(0)), u_p = uni(h.y, l.y, R(0));
   R epsp;
   if (EXT == 2 && C.thermal) {
-    moving_target_outcome<R>(ch, C, eps, u_c, u_p, vx, vy, vz, vcm, g2, &nx, &ny, &nz, &epsp);
+    moving_target_outcome<R>(ch, eps, u_c, u_p, vx, vy, vz, vcm, g2, &nx, &ny, &nz, &epsp);
   } else {
     const R v2 = vx * vx + vy * vy + vz * vz;
     R cos_t;
@@ -1618,7 +1594,7 @@ __device__ __forceinline__ void pool_put(const Pool<R>& P, int s, const Lane<R>&
 template <typename R, int EXT>
 __device__ __forceinline__ void restore_trial_frequency(Lane<R>& L, const Consts<R>& C, R v) {
   if constexpr (EXT) {
-    if (C.variable && v < C.nup) apply_trial_frequency(L, C, v);
+    if (C.variable && v < C.nup) apply_trial_frequency(L, v);
     else constant_trial_frequency(L, C);
   }
 }

@@ -193,7 +193,7 @@ def test_fast_electrons_stay_below_c():
 
 
 def test_crossed_field_swarm_matches_classical():
-    cfg = synth.cfg1_maxwell(n_electrons=3000, n_collisions=2000).scaled(B_T=2.0, B_angle_rad=math.pi / 4)
+    cfg = synth.cfg1_maxwell(n_electrons=1500, n_collisions=1000).scaled(B_T=2.0, B_angle_rad=math.pi / 4)
     a = tallies(oracle.OracleModel.from_config(cfg).run(cfg.n_electrons, cfg.n_collisions, 1).records)
     b = tallies(oracle.OracleModel.from_config(cfg.scaled(relativistic=1)).run(cfg.n_electrons, cfg.n_collisions,
                                                                                1).records)
