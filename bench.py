@@ -52,6 +52,10 @@ def parse():
                     help="skip the leg with the variable trial frequency")
     ap.add_argument("--no-binned", action="store_true",
                     help="skip the leg with the binned trial frequency")
+    ap.add_argument("--no-thermal", action="store_true",
+                    help="skip the leg with moving targets")
+    ap.add_argument("--no-relativistic", action="store_true",
+                    help="skip the FP64 leg with the relativistic mover")
     ap.add_argument("--no-anisotropic", action="store_true",
                     help="skip the leg with screened-Coulomb scattering")
     ap.add_argument("--serve-rate", type=float, default=5.0)
@@ -219,6 +223,58 @@ def adaptive_leg(sw, args, cfgs, jobs, opts, tall_const, ms_const, strategy):
     return out
 
 
+def batched_run(sw, args, cfgs, jobs, opts, precision, steps=None):
+    """One warm-up and `steps` (default args.steps) timed batched launches of the configs;
+    (avg ms, tallies)."""
+    hs = [sw.Swarm.from_config(c, precision) for c in cfgs]
+    b = sw.swarm_batch_create([h.h for h in hs], jobs, opts)
+    try:
+        sw.swarm_batch_launch(b)
+        sw.swarm_batch_wait(b)
+        ms = []
+        for _ in range(max(1, args.steps if steps is None else steps)):
+            sw.swarm_batch_launch(b)
+            ms.append(sw.swarm_batch_wait(b))
+        tl = [sw.swarm_batch_tallies(b, i) for i in range(len(cfgs))]
+    finally:
+        sw.swarm_batch_destroy(b)
+    return sum(ms) / len(ms), tl
+
+
+def ratio_range(ta, tb, keys):
+    out = {}
+    for k in keys:
+        r = [a[k][0] / b[k][0] for a, b in zip(ta, tb) if b[k][0] != 0 and math.isfinite(a[k][0])]
+        out[k] = {"min": min(r), "max": max(r)} if r else None
+    return out
+
+
+def thermal_leg(sw, args, cfgs, jobs, opts, tall_const, ms_const, T_K=293.0):
+    """The batched FP32 step with moving targets (Maxwell-Boltzmann at T_K): throughput, time
+    relative to targets at rest, and how the drift velocity and mean energy move (little at
+    these E/N, 1-1000 Td)."""
+    avg, tt = batched_run(sw, args, [c.scaled(thermal_targets=1, T_K=T_K) for c in cfgs], jobs, opts,
+                          sw.SWARM_FP32_MIXED)
+    real = sum(t["n_real"] for t in tt)
+    return {"value": real / (avg * 1e-3), "unit": "real collisions/s", "device_ms_per_step": avg, "T_K": T_K,
+            "time_vs_at_rest": avg / ms_const,
+            "ratio_to_at_rest": ratio_range(tt, tall_const, ("W", "mean_energy"))}
+
+
+def relativistic_leg(sw, args, cfgs, jobs, opts):
+    """The batched FP64 step with the relativistic mover against the classical one: throughput,
+    time ratio and the tally ratios (relativistic corrections are O(eps / m c^2) here)."""
+    o = {k: v for k, v in opts.items() if k != "use_graph"}
+    o["use_graph"] = 1
+    # (FP64 launches of this workload take seconds: one timed launch each)
+    ms_c, tc = batched_run(sw, args, cfgs, jobs, o, sw.SWARM_FP64, steps=1)
+    ms_r, tr = batched_run(sw, args, [c.scaled(relativistic=1) for c in cfgs], jobs, o, sw.SWARM_FP64, steps=1)
+    real = sum(t["n_real"] for t in tr)
+    return {"value": real / (ms_r * 1e-3), "unit": "real collisions/s", "device_ms_per_step": ms_r,
+            "classical_device_ms_per_step": ms_c, "time_vs_classical": ms_r / ms_c,
+            "ratio_to_classical": ratio_range(tr, tc, ("W", "mean_energy"))}
+
+
 def anisotropic_leg(sw, args, cfgs, jobs, opts, tall_const, ms_const):
     """The same batched FP32 step with screened-Coulomb (anisotropic) scattering of the
     argon-like atom: throughput, and how the drift velocity and mean energy move."""
@@ -325,6 +381,12 @@ def main():
         log(args, "variable trial frequency", out["fp32_batched_variable"])
     if not args.no_anisotropic:
         out["fp32_batched_screened_coulomb"] = anisotropic_leg(sw, args, cfgs, jobs, opts, tall32, avg_ms)
+    if not args.no_thermal:
+        out["fp32_batched_moving_targets"] = thermal_leg(sw, args, cfgs, jobs, opts, tall32, avg_ms)
+        log(args, "moving targets", out["fp32_batched_moving_targets"])
+    if not args.no_relativistic:
+        out["fp64_batched_relativistic"] = relativistic_leg(sw, args, cfgs, jobs, opts)
+        log(args, "relativistic", out["fp64_batched_relativistic"])
         log(args, "screened-Coulomb scattering", out["fp32_batched_screened_coulomb"])
     if not args.no_fp64:
         # the plain FP64 form: one swarm per launch, default launch shape
