@@ -47,7 +47,7 @@ struct ThermalChannel {
   double mass;     // target mass M (kg)
   double sigma;    // sqrt(k T / M), spread of each target velocity component
   double loss;     // 2 eps_k M / ((m + M) m): the threshold in |V1 - Vcm|^2
-  double pad;
+  double cM;       // M / (m + M): V1 - Vcm = (M / (m + M)) (V1 - V2)
 };
 
 // Saved electron state at a real-collision boundary (serving epochs resume from it).

@@ -345,7 +345,7 @@ __global__ void k_build_constants(InstanceDesc* desc) {
     th.sigma = sqrt(kKb * d.T_K / M);
     th.loss = (ch.kind == SWARM_EXCITATION || ch.kind == SWARM_IONIZATION) ? 2.0 * (ch.thr * kQe) / (mm + M) * (M / mm)
                                                                            : 0.0;
-    th.pad = 0.0;
+    th.cM = M / (mm + M);
     d.chan_th[c] = th;
   }
   if (threadIdx.x == 0) {
@@ -1166,23 +1166,39 @@ __device__ __forceinline__ void trial_block(Lane<R>& L, const Consts<R>& C,
 constexpr int kScanChannels = 8;   // up to this many channels, selection scans the whole row
 enum : int { RC_CONTINUE = 0, RC_STOP = 1 };
 
-// Moving targets (section "Effect of gas temperature"), in FP64 for both precisions.  The
-// target velocity of collision k has three normal components of spread sqrt(kT/M), from the
-// four uniforms of the THERMAL block by Box-Muller.  moving_target() returns the centre-of-
-// momentum velocity Vcm = (m V1 + M V2)/(m + M) and the electron's squared speed in that
-// frame after the threshold loss, |V1 - Vcm|^2 - 2 eps_k M / ((m + M) m) (negative: the
-// process cannot happen).
+// Moving targets (section "Effect of gas temperature").  The target velocity of collision k
+// has three normal components of spread sqrt(kT/M), from the four uniforms of the THERMAL
+// block by Box-Muller.  moving_target() returns the centre-of-momentum velocity Vcm = (m V1 +
+// M V2)/(m + M) and the electron's squared speed in that frame after the threshold loss,
+// |V1 - Vcm|^2 - 2 eps_k M / ((m + M) m) (negative: the process cannot happen).  FP64 lanes
+// compute in binary64; FP32 lanes in binary32 (hardware log, sqrt, sin and cos), with V1 -
+// Vcm as (M/(m + M)) (V1 - V2) and the threshold compared in binary64, as for the onset.
 template <typename R>
 __device__ __forceinline__ void moving_target(const Lane<R>& L, const Consts<R>& C, int c,
                                               R vx, R vy, R vz, double* vcm, double* g2) {
   const ThermalChannel th = C.chan_th[c];
   const W4 h = draw(C.key, L.id, TAG_THERMAL_HI, L.k);
+  if constexpr (sizeof(R) == 4) {
+    const float u0 = uni(h.x, 0u, 0.0f), u1 = uni(h.y, 0u, 0.0f), u2 = uni(h.z, 0u, 0.0f), u3 = uni(h.w, 0u, 0.0f);
+    // -2 ln(1 - u) = -2 ln2 log2(1 - u); 1 - u is exact for a 24-bit uniform
+    const float r01 = sqrt_(-2.0f * 0.693147180559945309f * __builtin_amdgcn_logf(1.0f - u0));
+    const float r23 = sqrt_(-2.0f * 0.693147180559945309f * __builtin_amdgcn_logf(1.0f - u2));
+    float s1, c1, s3, c3;
+    sincos_rev(u1, &s1, &c1);
+    sincos_rev(u3, &s3, &c3);
+    const float sg = static_cast<float>(th.sigma), cM = static_cast<float>(th.cM);
+    const float ux = cM * (vx - sg * r01 * c1), uy = cM * (vy - sg * r01 * s1), uz = cM * (vz - sg * r23 * c3);
+    vcm[0] = static_cast<double>(vx - ux);
+    vcm[1] = static_cast<double>(vy - uy);
+    vcm[2] = static_cast<double>(vz - uz);
+    const double dx = ux, dy = uy, dz = uz;
+    *g2 = (dx * dx + dy * dy + dz * dz) - th.loss;
+    return;
+  }
   double u0, u1, u2, u3;
-  if constexpr (sizeof(R) == 8) {
+  {
     const W4 l = draw(C.key, L.id, TAG_THERMAL_LO, L.k);
     u0 = uni(h.x, l.x, 0.0); u1 = uni(h.y, l.y, 0.0); u2 = uni(h.z, l.z, 0.0); u3 = uni(h.w, l.w, 0.0);
-  } else {
-    u0 = uni(h.x, 0u, 0.0f); u1 = uni(h.y, 0u, 0.0f); u2 = uni(h.z, 0u, 0.0f); u3 = uni(h.w, 0u, 0.0f);
   }
   const double r01 = sqrt(-2.0 * log(1.0 - u0));
   const double r23 = sqrt(-2.0 * log(1.0 - u2));
@@ -1203,9 +1219,33 @@ __device__ __forceinline__ void moving_target(const Lane<R>& L, const Consts<R>&
 // scattering block's first two uniforms, or theta about V1 - Vcm for the anisotropic
 // models).  Gives the direction of V1' and the energy after (zero for attachment).
 template <typename R>
-__device__ __forceinline__ void moving_target_outcome(const ChannelDev& ch, R eps, R u_c, R u_p,
+__device__ __forceinline__ void moving_target_outcome(const ChannelDev& ch, const Consts<R>& C, R eps, R u_c, R u_p,
                                                       R vx, R vy, R vz, const double* vcm, double g2,
                                                       R* nx, R* ny, R* nz, R* epsp) {
+  if constexpr (sizeof(R) == 4) {
+    const float cx = static_cast<float>(vcm[0]), cy = static_cast<float>(vcm[1]), cz = static_cast<float>(vcm[2]);
+    const float ux = vx - cx, uy = vy - cy, uz = vz - cz;
+    const float g = sqrt_(ux * ux + uy * uy + uz * uz);
+    float hx, hy, hz;
+    if (ch.scat == SWARM_SCATTER_ISOTROPIC || !(g > 0.0f)) {
+      iso_dir<float>(u_c, u_p, &hx, &hy, &hz);
+    } else {
+      const float ig = 1.0f / g;
+      rotate_dir<float>(ux * ig, uy * ig, uz * ig, scatter_cos(ch.scat, ch.xi_f, eps, u_c), u_p, &hx, &hy, &hz);
+    }
+    const float sp = sqrt_(fmaxf(static_cast<float>(g2), 0.0f));
+    const float px = cx + hx * sp, py = cy + hy * sp, pz = cz + hz * sp;
+    const float p2 = px * px + py * py + pz * pz;
+    const float s1 = sqrt_(p2);
+    if (s1 > 0.0f) {
+      const float is = 1.0f / s1;
+      *nx = px * is; *ny = py * is; *nz = pz * is;
+    } else {
+      *nx = hx; *ny = hy; *nz = hz;
+    }
+    *epsp = ch.kind == SWARM_ATTACHMENT ? 0.0f : C.c_eps * p2;
+    return;
+  }
   const double ux = static_cast<double>(vx) - vcm[0], uy = static_cast<double>(vy) - vcm[1],
                uz = static_cast<double>(vz) - vcm[2];
   const double g = sqrt(ux * ux + uy * uy + uz * uz);
@@ -1337,7 +1377,7 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
   const R u_c = uni(h.x, l.x, R(0)), u_p = uni(h.y, l.y, R(0));
   R epsp;
   if (EXT == 2 && C.thermal) {
-    moving_target_outcome<R>(ch, eps, u_c, u_p, vx, vy, vz, vcm, g2, &nx, &ny, &nz, &epsp);
+    moving_target_outcome<R>(ch, C, eps, u_c, u_p, vx, vy, vz, vcm, g2, &nx, &ny, &nz, &epsp);
   } else {
     const R v2 = vx * vx + vy * vy + vz * vz;
     R cos_t;
