@@ -58,6 +58,10 @@ def parse():
                     help="skip the FP64 leg with the relativistic mover")
     ap.add_argument("--no-anisotropic", action="store_true",
                     help="skip the leg with screened-Coulomb scattering")
+    ap.add_argument("--no-real", action="store_true",
+                    help="skip the real-secondaries leg (mixture, 1e6 primaries)")
+    ap.add_argument("--no-batch256", action="store_true",
+                    help="skip the 256-instance batch leg")
     ap.add_argument("--serve-rate", type=float, default=5.0)
     ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--serve-only", action="store_true",
@@ -301,6 +305,63 @@ def anisotropic_leg(sw, args, cfgs, jobs, opts, tall_const, ms_const):
             "ratio_to_isotropic": {k: {"min": min(v), "max": max(v)} for k, v in ratio.items()}}
 
 
+def real_secondaries_leg(sw, args, n_electrons=1_000_000, n_collisions=2000):
+    """The real-secondaries kernel on the 90:10 argon-like:CO2-like mixture at 100 Td, B = 1 T at
+    45 degrees: 1e6 primaries, with the largest collision budget whose lineage growth fits the
+    default capacity.  FP32-mixed and FP64 single runs (one launch of the persistent kernel
+    each, after a small warm-up run): throughput, electrons created and attached, and how the
+    FP32 tallies agree with the FP64 ones."""
+    import torch
+    import synth
+    cfg = synth.cfg3_mixture_real(n_electrons=n_electrons, n_collisions=n_collisions)
+    out = {"workload": f"90:10 argon-like:CO2-like, 100 Td, B = 1 T at 45 deg, real secondaries, "
+                       f"{n_electrons} primaries x {n_collisions} real collisions, seed 0"}
+    tall = {}
+    for name, prec in (("fp32", sw.SWARM_FP32_MIXED), ("fp64", sw.SWARM_FP64)):
+        s = sw.Swarm.from_config(cfg, prec)
+        s.run(n_electrons // 100, n_collisions, 1)        # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.run(n_electrons, n_collisions, 0)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kernel_ms, total_ms = s.timing()
+        t = s.tallies()
+        tall[name] = t
+        out[name] = {"value": t["n_real"] / wall, "unit": "real collisions/s", "seconds": wall,
+                     "kernel_ms": kernel_ms, "device_ms": total_ms, "n_real": t["n_real"],
+                     "efficiency": t["efficiency"], "n_electrons": t["n_electrons"],
+                     "n_created": t["n_created"], "n_attached": t["n_attached"], "n_dropped": t["n_dropped"]}
+        s.close()
+    keys = ["W", "Wx", "Wy", "mean_energy", "D_vec", "alpha"]
+    out["fp32_vs_fp64_within_tolerance"] = f"{agreement(tall['fp32'], tall['fp64'], keys)}/{len(keys)}"
+    out["fp32_speedup"] = out["fp32"]["value"] / out["fp64"]["value"]
+    return out
+
+
+def batch256_leg(sw, args):
+    """The 256-instance sweep (4 mixtures x 64 E/N over 1-1000 Td, B = 0 or 1 T at random
+    angles, electron counts 1e3-1e6 and collision budgets 1e3-1e5 log-uniform) in one
+    persistent FP32 launch: about 8e11 real collisions, timed once."""
+    import synth
+    cfgs = synth.cfg4_batch()
+    jobs = [(c.n_electrons, c.n_collisions, c.seed) for c in cfgs]
+    hs = [sw.Swarm.from_config(c, sw.SWARM_FP32_MIXED) for c in cfgs]
+    b = sw.swarm_batch_create([h.h for h in hs], jobs, {"use_graph": 1})
+    try:
+        # (one launch of about 30 s: the kernels are warm from the other legs)
+        sw.swarm_batch_launch(b)
+        ms = sw.swarm_batch_wait(b)
+        tl = [sw.swarm_batch_tallies(b, i) for i in range(len(cfgs))]
+    finally:
+        sw.swarm_batch_destroy(b)
+    real = sum(t["n_real"] for t in tl)
+    trials = sum(t["n_real"] + t["n_null"] + t["n_forbidden"] + t["n_fail"] for t in tl)
+    return {"value": real / (ms * 1e-3), "unit": "real collisions/s", "device_ms": ms, "instances": len(cfgs),
+            "n_real": real, "efficiency": real / trials,
+            "workload": "4 mixtures x 64 E/N (1-1000 Td), B 0 or 1 T, uneven sizes, FP32-mixed, one launch"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -375,19 +436,26 @@ def main():
     if not args.no_variable:
         out["fp32_batched_variable"] = adaptive_leg(sw, args, cfgs, jobs, opts, tall32, avg_ms,
                                                     dict(trial_strategy=1, trial_zeta=0.25, trial_grace=5000))
+        log(args, "variable trial frequency", out["fp32_batched_variable"])
     if not args.no_binned:
         out["fp32_batched_binned"] = adaptive_leg(sw, args, cfgs, jobs, opts, tall32, avg_ms,
                                                   dict(trial_strategy=2, trial_bins=10, trial_grace=5000))
-        log(args, "variable trial frequency", out["fp32_batched_variable"])
+        log(args, "binned trial frequency", out["fp32_batched_binned"])
     if not args.no_anisotropic:
         out["fp32_batched_screened_coulomb"] = anisotropic_leg(sw, args, cfgs, jobs, opts, tall32, avg_ms)
+        log(args, "screened-Coulomb scattering", out["fp32_batched_screened_coulomb"])
     if not args.no_thermal:
         out["fp32_batched_moving_targets"] = thermal_leg(sw, args, cfgs, jobs, opts, tall32, avg_ms)
         log(args, "moving targets", out["fp32_batched_moving_targets"])
     if not args.no_relativistic:
         out["fp64_batched_relativistic"] = relativistic_leg(sw, args, cfgs, jobs, opts)
         log(args, "relativistic", out["fp64_batched_relativistic"])
-        log(args, "screened-Coulomb scattering", out["fp32_batched_screened_coulomb"])
+    if not args.no_real:
+        out["real_secondaries"] = real_secondaries_leg(sw, args)
+        log(args, "real secondaries", out["real_secondaries"])
+    if not args.no_batch256:
+        out["fp32_batch_256_instances"] = batch256_leg(sw, args)
+        log(args, "256-instance batch", out["fp32_batch_256_instances"])
     if not args.no_fp64:
         # the plain FP64 form: one swarm per launch, default launch shape
         h64 = [sw.Swarm.from_config(c, sw.SWARM_FP64) for c in cfgs]

@@ -230,9 +230,11 @@ swarm_status swarm_create(const swarm_component* comps, int32_t n_comps,
 /* Simulate n_electrons primaries (ids 0..n-1) at the origin, each until it has made
  * n_collisions real collisions (the paper's I; section "Determination of swarm
  * attributes"), with the given seed.  Synchronous.  In REAL mode secondaries inherit the
- * parent's count.  If REAL growth exceeds the capacity the run stops early and returns
+ * parent's count and run in generations: the primaries, then the secondaries each
+ * generation created, one kernel launch per generation.  If REAL growth exceeds the capacity the run stops early and returns
  * SWARM_ERR_CAPACITY: the secondaries that did not fit are counted (n_dropped), electrons
- * still running are recorded with flag 8, and the tallies cover the finished ones.
+ * still running are recorded with flag 8 at their last real collision, those not yet
+ * started with flag 8 as they were created, and the tallies cover the finished ones.
  * Previous results of the handle are replaced. */
 swarm_status swarm_run(swarm_t h, int64_t n_electrons, int64_t n_collisions, uint64_t seed);
 
@@ -257,8 +259,9 @@ swarm_status swarm_trace_events(swarm_t h, swarm_event* out, int32_t* counts);
 swarm_status swarm_tables(swarm_t h, int32_t* grid_size, int32_t* n_channels, double* nodes,
                           double* cum, double* majorant);
 
-/* Device time in milliseconds of the last run's simulation kernel (HIP events on the
- * launch stream) and of its whole device section (simulation plus tallies). */
+/* Device time in milliseconds of the last run's simulation kernel (every generation's
+ * launch in REAL mode; HIP events on the launch stream) and of its whole device section
+ * (simulation plus tallies). */
 swarm_status swarm_last_timing(swarm_t h, double* kernel_ms, double* total_ms);
 
 void swarm_destroy(swarm_t h);             /* NULL-safe */

@@ -529,16 +529,11 @@ swarm_status swarm_run(swarm_t h, int64_t n_electrons, int64_t n_collisions, uin
   d.records = static_cast<swarm_record*>(h->records.p);
   d.saved = nullptr;
   d.children = nullptr;
-  d.child_ready = nullptr;
   const int64_t child_cap = capacity - n_electrons;
   if (real && child_cap > 0) {
     if ((e = h->children.ensure(static_cast<size_t>(child_cap) * sizeof(ChildState))) != hipSuccess)
       return hip_fail(e, "allocating secondary queue");
-    if ((e = h->ready.ensure(static_cast<size_t>(child_cap) * sizeof(uint32_t))) != hipSuccess)
-      return hip_fail(e, "allocating secondary flags");
     d.children = static_cast<ChildState*>(h->children.p);
-    d.child_ready = static_cast<uint32_t*>(h->ready.p);
-    if ((e = launch_fill_u32(d.child_ready, 0u, child_cap, s)) != hipSuccess) return hip_fail(e, "clearing flags");
   }
   if (real && (e = launch_mark_empty(d.records, capacity, s)) != hipSuccess) return hip_fail(e, "clearing records");
   const bool trace = h->n_trace > 0;
@@ -549,10 +544,9 @@ swarm_status swarm_run(swarm_t h, int64_t n_electrons, int64_t n_collisions, uin
   d.trace_count = trace ? static_cast<int32_t*>(h->trace_count.p) : nullptr;
   if (trace && (e = launch_fill_u32(reinterpret_cast<uint32_t*>(d.trace_count), 0u, h->n_trace, s)) != hipSuccess)
     return hip_fail(e, "clearing trace counts");
-  // counters: all zero, live = number of primaries
-  RunCounters rc{};
-  rc.live = n_electrons;
-  if ((e = hipMemcpyAsync(d.ctr, &rc, sizeof(rc), hipMemcpyHostToDevice, s)) != hipSuccess) return hip_fail(e, "counters");
+  // counters: all zero
+  if ((e = launch_fill_u64(reinterpret_cast<uint64_t*>(d.ctr), 0ull, sizeof(RunCounters) / sizeof(uint64_t), s)) != hipSuccess)
+    return hip_fail(e, "counters");
   if ((e = sync_desc_to_device(h)) != hipSuccess) return hip_fail(e, "descriptor");
   const swarm_launch_opts& o = h->opts;
   const int svc = trace || real ? 0 : o.service_waves;
@@ -585,19 +579,34 @@ swarm_status swarm_run(swarm_t h, int64_t n_electrons, int64_t n_collisions, uin
                                 d_ctr, d.precision, h->has_b, trace, ext, svc, o.block_size, grid, o.pending_trigger, lds, ch_off,
                                 ll.pool_off, ll.cum_off, s)) != hipSuccess)
       return hip_fail(e, "swarm kernel launch");
-  } else {
-    const int64_t want = (n_electrons + o.block_size - 1) / o.block_size;
-    const int grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want * 4, static_cast<int64_t>(dev.n_cu) * per_cu)));
-    if ((e = launch_swarm_real(h->d_desc, d.precision, h->has_b, trace, ext, o.block_size, grid, o.pending_trigger, lds, ch_off,
-                               ll.cum_off, s)) != hipSuccess)
-      return hip_fail(e, "swarm kernel launch");
+  }
+  RunCounters hc{};
+  if (real) {
+    // One launch per generation: the primaries, then the secondaries each generation
+    // appended to the queue (slots [first, first + count)), until a generation creates none.
+    // Every generation starts at least one collision later in its lineage budget than the
+    // one before, so there are at most n_collisions + 1.  After an overflow the next launch
+    // records the queued secondaries unstarted (flag 8) and creates none.
+    int64_t first = -1, count = n_electrons, queued = 0;
+    for (;;) {
+      if ((e = launch_fill_u64(&d.ctr->gen_next, 0ull, 1, s)) != hipSuccess) return hip_fail(e, "generation counter");
+      const int64_t want = (count + o.block_size - 1) / o.block_size;
+      const int grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want * 4, static_cast<int64_t>(dev.n_cu) * per_cu)));
+      if ((e = launch_swarm_real(h->d_desc, d.precision, h->has_b, trace, ext, o.block_size, grid, o.pending_trigger, lds,
+                                 ch_off, ll.cum_off, first, count, hc.dropped != 0 ? 1 : 0, s)) != hipSuccess)
+        return hip_fail(e, "swarm kernel launch");
+      if ((e = hipMemcpyAsync(&hc, d.ctr, sizeof(hc), hipMemcpyDeviceToHost, s)) != hipSuccess) return hip_fail(e, "counters");
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "swarm kernel");
+      const int64_t tail = std::min<int64_t>(static_cast<int64_t>(hc.child_tail), child_cap);
+      if (tail == queued) break;
+      first = queued;
+      count = tail - queued;
+      queued = tail;
+    }
   }
   if ((e = hipEventRecord(h->ev[1], s)) != hipSuccess) return hip_fail(e, "event");
-  RunCounters hc{};
   if ((e = hipMemcpyAsync(&hc, d.ctr, sizeof(hc), hipMemcpyDeviceToHost, s)) != hipSuccess) return hip_fail(e, "counters");
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "swarm kernel");
-  if (hc.poll_overrun) return fail(SWARM_ERR_DEVICE, "secondary queue wait limit reached (%llu waves)",
-                                   static_cast<unsigned long long>(hc.poll_overrun));
   h->n_records = n_electrons + (real ? std::min<int64_t>(static_cast<int64_t>(hc.child_tail), child_cap) : 0);
   if ((e = h->tally.prepare({h->n_records}, s)) != hipSuccess) return hip_fail(e, "tally plan");
   if ((e = h->tally.launch(h->d_desc, s)) != hipSuccess) return hip_fail(e, "tally launch");

@@ -64,7 +64,7 @@ struct swarm {
   swarm_impl::InstanceDesc desc{};          // host copy (device constants read back after build)
   swarm_impl::InstanceDesc* d_desc = nullptr;
   swarm_impl::DevBuf arena;                 // raw inputs, tables, descriptor, counters
-  swarm_impl::DevBuf records, children, ready, items;
+  swarm_impl::DevBuf records, children, items;
   std::vector<swarm_impl::WorkItem> h_items;
   swarm_impl::DevBuf trace_ids, trace_out, trace_count;
   int32_t n_trace = 0, max_events = 0;

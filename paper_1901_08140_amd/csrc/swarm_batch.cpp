@@ -115,7 +115,6 @@ swarm_status swarm_batch_create(swarm_t* handles, const swarm_job* jobs, int32_t
     d.records = static_cast<swarm_record*>(h->records.p);
     d.saved = nullptr;
     d.children = nullptr;
-    d.child_ready = nullptr;
     d.trace_ids = nullptr;
     d.n_trace = 0;
     d.max_events = 0;

@@ -19,8 +19,8 @@ constexpr uint32_t kMaxBlocks = 0x7fffffffu;   // per-electron cap on trial bloc
 // Lane states of the swarm kernels.
 // ACTIVE: drawing trials; PENDING: holds a real-collision candidate and draws its
 // scattering block in the next trial pass; READY: candidate and scattering words ready;
-// IDLE: needs an electron; WAIT: holds a secondary-queue slot (or, in the pooled
-// schedule, has its candidate in the work-group pool); CAND: pooled schedule, holds a
+// IDLE: needs an electron; WAIT: pooled schedule, has its candidate in the work-group
+// pool; CAND: pooled schedule, holds a
 // candidate not yet in the pool; STOPPED: must store its record or state; DONE: no more
 // work.
 enum : int { ST_ACTIVE = 0, ST_PENDING = 1, ST_IDLE = 2, ST_WAIT = 3, ST_DONE = 4, ST_STOPPED = 5,
@@ -62,7 +62,8 @@ struct SavedState {
   uint32_t grace, n_fail;     // trials left before its next update; fails so far
 };
 
-// Child electron waiting in the real-secondaries queue.
+// Secondary electron in the real-secondaries queue, written by the generation that
+// created it and run by the next one.
 struct ChildState {
   double r[3], t;
   double v[3];
@@ -71,16 +72,17 @@ struct ChildState {
   double eps_birth;           // energy it was created with (eV), for its first trial frequency
 };
 
-// Device counters of one instance's run.
+// Device counters of one instance's run.  The counters that real-mode waves update
+// concurrently sit on 128-byte lines of their own, so their atomics do not queue behind
+// each other.
 struct RunCounters {
-  uint64_t prim_next;     // real mode: next primary index
-  uint64_t child_tail;    // real mode: reserved child slots
-  uint64_t child_head;    // real mode: claimed child slots
-  int64_t live;           // real mode: electrons not yet stopped (queued or running)
+  uint64_t gen_next;      // real mode: electrons of the running generation taken so far
+  uint64_t pad0[15];
+  uint64_t child_tail;    // real mode: reserved secondary slots
+  uint64_t pad1[15];
   uint64_t dropped;       // secondaries that did not fit the capacity
-  uint64_t n_done;        // electrons that reached their final real collision or stopped
-  uint64_t poll_overrun;  // waves that hit the bounded-wait limit (must stay 0)
-  uint64_t pad;
+  uint64_t n_done;        // dummy mode: electrons that reached their final collision or stopped
+  uint64_t pad2[14];
 };
 
 // One swarm instance as seen by the kernels.  Fields in the first group are written by
@@ -132,7 +134,6 @@ struct InstanceDesc {
   swarm_record* records;      // per-electron results
   SavedState* saved;          // resumable runs (serving); NULL otherwise
   ChildState* children;       // real mode queue
-  uint32_t* child_ready;      // real mode ready flags
   RunCounters* ctr;
   // tracing
   const uint64_t* trace_ids;
@@ -187,7 +188,7 @@ hipError_t launch_swarm_dummy(const InstanceDesc* d_desc, const WorkItem* d_item
 size_t swarm_pool_slot_bytes(int precision);
 hipError_t launch_swarm_real(const InstanceDesc* d_desc, int precision, bool has_b, bool trace,
                              int ext, int block_size, int grid, int pending_trigger, size_t lds_bytes,
-                             int ch_off, int cum_off, hipStream_t s);
+                             int ch_off, int cum_off, int64_t first, int64_t count, int flush, hipStream_t s);
 hipError_t launch_tallies(const InstanceDesc* d_desc, const TallyTile* d_tiles, int32_t n_tiles,
                           const int32_t* d_tile_base, const int64_t* d_nrec, int32_t n_inst,
                           double* d_part1, double* d_part2, double* d_tot1,

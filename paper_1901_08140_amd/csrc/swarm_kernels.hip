@@ -1862,15 +1862,33 @@ __global__ void __launch_bounds__(512) k_swarm_pooled(const InstanceDesc* __rest
 }
 
 // ---------------------------------------------------------------------------------------
-// Real-secondaries kernel (one instance).  Lanes take primaries from a global counter and
-// then secondaries from a queue.  A secondary is appended with one atomic per wave (ballot
-// of the ionising lanes, prefix rank from the lane mask) and published with a ready flag
-// after its state is written.  The kernel ends when every electron has stopped (`live`
-// reaches 0); idle waves sleep between polls and give up after a bounded number of polls.
+// Real-secondaries kernel (one instance, one generation per launch).  Generation 0 is the
+// primaries; generation g + 1 is the secondaries that generation g created.  Lanes take
+// the electrons of their generation from a global counter and run each to the end of its
+// lineage budget.  A secondary is appended to the queue with one atomic per wave (ballot
+// of the ionising lanes, prefix rank from the lane mask) and is not touched again in this
+// launch: the next launch runs it, so the kernel boundary publishes it and no lane ever
+// waits on another.  `first` < 0 selects the primaries [0, count); otherwise the queue
+// slots [first, first + count).  A wave takes its electrons in chunks of 64 with one
+// atomic and hands them to its idle lanes by ballot rank, and it reads the overflow
+// counter once every 64 passes, so no pass waits on device-coherent memory.  With `flush`
+// set (the launch after an overflow) every electron is recorded as it was created.
 // ---------------------------------------------------------------------------------------
+constexpr uint32_t kClaimChunk = 64;      // electrons a wave takes per claim
+constexpr uint32_t kAbortPoll = 64;       // passes between reads of the overflow counter
+
+// A value the whole wave holds, kept in scalar registers.
+__device__ __forceinline__ int64_t wave_uniform(int64_t x) {
+  const uint64_t u = static_cast<uint64_t>(x);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u >> 32));
+  return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
 template <typename R, bool HB, bool TR, int EXT>
 __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restrict__ desc, int pend_trig,
-                                                    int ch_off, int cum_off) {
+                                                    int ch_off, int cum_off, int64_t first, int64_t count,
+                                                    int flush) {
   using PT = typename Pair<R>::T;
   extern __shared__ __align__(16) unsigned char smem[];
   PT* s_nu = reinterpret_cast<PT*>(smem);
@@ -1898,38 +1916,38 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
   L.state = ST_IDLE;
   L.trace_slot = -1;
   L.n_ev = 0;
-  bool prim_left = true;
-  int64_t slot = -1;
-  uint32_t polls = 0;
   const uint64_t lane_lt = (1ull << __lane_id()) - 1ull;
+  // wave-uniform: the wave's chunk [w_next, w_end), whether the generation is exhausted,
+  // whether the run is stopping after an overflow, and the pass count
+  int64_t w_next = 0, w_end = 0;
+  bool exhausted = false, aborting = flush != 0;
+  uint32_t pass = 0;
   for (;;) {
-    if (L.state == ST_IDLE && prim_left) {
-      const uint64_t e = atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->prim_next), 1ull);
-      if (static_cast<int64_t>(e) < N) {
-        init_primary<R, HB, EXT>(L, C, s_nu, e);
-        L.rec = static_cast<int64_t>(e);
-        L.k_stop = C.n_coll;
-        if constexpr (TR) {
-          L.trace_slot = find_trace<TR>(d, L.id);
-          L.n_ev = 0;
-        }
-        L.state = ST_ACTIVE;
-      } else {
-        prim_left = false;
+    const uint64_t idle = __ballot(L.state == ST_IDLE);
+    if (idle != 0) {
+      if (w_next >= w_end && !exhausted) {
+        const int leader = __ffsll(static_cast<long long>(idle)) - 1;
+        unsigned long long base = 0;
+        if (static_cast<int>(__lane_id()) == leader)
+          base = atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->gen_next),
+                           static_cast<unsigned long long>(kClaimChunk));
+        w_next = wave_uniform(static_cast<int64_t>(__shfl(base, leader)));
+        w_end = min(w_next + static_cast<int64_t>(kClaimChunk), count);
+        exhausted = w_next >= count;
       }
-    }
-    if (L.state == ST_IDLE) {
-      // claim the next queue slot; it is filled when its parent ionises (or never, if the
-      // run ends first)
-      slot = static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->child_head), 1ull));
-      L.state = ST_WAIT;
-    }
-    if (L.state == ST_WAIT) {
-      bool got = false;
-      if (slot < child_cap) {
-        const uint32_t rdy = __hip_atomic_load(&d.child_ready[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (rdy != 0u) {
-          __atomic_thread_fence(__ATOMIC_ACQUIRE);
+      const int64_t avail = max(w_end - w_next, int64_t{0});
+      const int64_t rank = static_cast<int64_t>(__popcll(idle & lane_lt));
+      const int64_t e = w_next + rank;
+      w_next = wave_uniform(min(w_end, w_next + static_cast<int64_t>(__popcll(idle))));
+      if (L.state == ST_IDLE && exhausted && avail == 0) L.state = ST_DONE;
+      if (L.state == ST_IDLE && rank < avail) {
+        if (first < 0) {
+          init_primary<R, HB, EXT>(L, C, s_nu, e);
+          L.rec = static_cast<int64_t>(e);
+          L.k_stop = C.n_coll;
+          L.state = ST_ACTIVE;
+        } else {
+          const int64_t slot = first + static_cast<int64_t>(e);
           const ChildState cs = d.children[slot];
           L.rx = cs.r[0]; L.ry = cs.r[1]; L.rz = cs.r[2];
           L.t = cs.t;
@@ -1944,18 +1962,18 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
           L.rec = N + slot;
           set_anchor<R, HB>(L, C);
           start_trial_frequency<R, EXT>(L, C, s_nu, static_cast<R>(cs.eps_birth));
-          if constexpr (TR) {
-            L.trace_slot = find_trace<TR>(d, L.id);
-            L.n_ev = 0;
-          }
-          got = true;
           // a secondary born at its lineage's last collision has nothing left to do
           L.state = L.k >= L.k_stop ? ST_STOPPED : ST_ACTIVE;
         }
-      }
-      if (!got) {
-        const int64_t live = __hip_atomic_load(&ctr->live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (live == 0) L.state = ST_DONE;
+        // after an overflow, electrons not yet started are recorded as they are (flag 8)
+        if (L.state == ST_ACTIVE && aborting) {
+          L.flags |= 8u;
+          L.state = ST_STOPPED;
+        }
+        if constexpr (TR) {
+          L.trace_slot = find_trace<TR>(d, L.id);
+          L.n_ev = 0;
+        }
       }
     }
     uint64_t ready;
@@ -1976,56 +1994,33 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
       if (sm != 0) {
         const int leader = __ffsll(static_cast<long long>(sm)) - 1;
         unsigned long long base = 0;
-        if (static_cast<int>(__lane_id()) == leader) {
-          const unsigned long long n = __popcll(sm);
-          atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->live), n);
-          base = atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->child_tail), n);
-        }
+        if (static_cast<int>(__lane_id()) == leader)
+          base = atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->child_tail),
+                           static_cast<unsigned long long>(__popcll(sm)));
         base = __shfl(base, leader);
         if (spawn) {
           const int64_t s = static_cast<int64_t>(base + __popcll(sm & lane_lt));
-          if (s < child_cap) {
-            d.children[s] = child;
-            __atomic_thread_fence(__ATOMIC_RELEASE);
-            __hip_atomic_store(&d.child_ready[s], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          } else {
-            atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->dropped), 1ull);
-            atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->live), static_cast<unsigned long long>(-1ll));
-          }
+          if (s < child_cap) d.children[s] = child;
+          else atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->dropped), 1ull);
         }
       }
     }
     // Once the queue has overflowed the run's result is an error: stop every electron at
-    // its current anchor (flag 8) and take no new work, so the launch ends promptly.
-    const bool abort_run = __hip_atomic_load(&ctr->dropped, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-    if (abort_run) {
-      if (L.state == ST_ACTIVE || L.state == ST_PENDING || L.state == ST_READY) {
-        L.flags |= 8u;
-        L.state = ST_STOPPED;
-      } else if (L.state == ST_IDLE || L.state == ST_WAIT) {
-        L.state = ST_DONE;
-        prim_left = false;
-      }
+    // its current anchor (flag 8), so the launch ends promptly.  The electrons this
+    // generation has not started yet are then recorded unstarted.
+    if (!aborting && ++pass % kAbortPoll == 0)
+      aborting = __builtin_amdgcn_readfirstlane(static_cast<int>(
+                     __hip_atomic_load(&ctr->dropped, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) != 0;
+    if (aborting && (L.state == ST_ACTIVE || L.state == ST_PENDING || L.state == ST_READY)) {
+      L.flags |= 8u;
+      L.state = ST_STOPPED;
     }
     if (L.state == ST_STOPPED) {
       if (L.k >= C.n_coll && !(L.flags & 10u)) L.flags |= 1u;   // attached or aborted: not finished
       write_record(d, L);
-      atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->n_done), 1ull);
-      atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->live), static_cast<unsigned long long>(-1ll));
-      L.state = abort_run ? ST_DONE : ST_IDLE;
+      L.state = ST_IDLE;
     }
-    const uint64_t busy = __ballot(L.state == ST_ACTIVE || L.state == ST_PENDING || L.state == ST_READY ||
-                                   L.state == ST_IDLE);
-    if (busy == 0) {
-      if (__ballot(L.state != ST_DONE) == 0) break;
-      __builtin_amdgcn_s_sleep(32);
-      if (++polls > (1u << 27)) {     // bounded wait: report and leave
-        if (__lane_id() == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->poll_overrun), 1ull);
-        break;
-      }
-    } else {
-      polls = 0;
-    }
+    if (__ballot(L.state != ST_DONE) == 0) break;
   }
 }
 
@@ -2338,9 +2333,9 @@ hipError_t launch_swarm_dummy(const InstanceDesc* d_desc, const WorkItem* d_item
 
 hipError_t launch_swarm_real(const InstanceDesc* d_desc, int precision, bool has_b, bool trace,
                              int ext, int block_size, int grid, int pending_trigger, size_t lds_bytes,
-                             int ch_off, int cum_off, hipStream_t s) {
+                             int ch_off, int cum_off, int64_t first, int64_t count, int flush, hipStream_t s) {
   void* fn = pick_kernel(precision, has_b, trace, true, ext);
-  void* args[] = {const_cast<InstanceDesc**>(&d_desc), &pending_trigger, &ch_off, &cum_off};
+  void* args[] = {const_cast<InstanceDesc**>(&d_desc), &pending_trigger, &ch_off, &cum_off, &first, &count, &flush};
   return hipLaunchKernel(fn, dim3(grid), dim3(block_size), args, lds_bytes, s);
 }
 

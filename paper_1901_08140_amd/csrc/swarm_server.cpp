@@ -144,7 +144,6 @@ swarm_status admit(swarm_server* s, const std::shared_ptr<Request>& r) {
   d.records = static_cast<swarm_record*>(h->records.p);
   d.saved = static_cast<SavedState*>(r->saved.p);
   d.children = nullptr;
-  d.child_ready = nullptr;
   d.ctr = c;
   d.trace_ids = nullptr;
   d.n_trace = 0;
