@@ -172,16 +172,18 @@ def serve(sw, args):
                                                   c.n_electrons, c.n_collisions, c.seed))
         sw.swarm_server_drain(srv)
         t_end = sw.swarm_server_now(srv)
-        lat, real = [], 0
+        lat, real, trials = [], 0, 0
         for tk in tickets:
             done, tal, info = sw.swarm_server_poll(srv, tk)
             lat.append(info["done_s"] - info["submit_s"])
             real += tal["n_real"]
+            trials += tal["n_real"] + tal["n_null"] + tal["n_forbidden"] + tal["n_fail"]
         lat = np.array(lat)
         offered = sum(c.n_electrons * c.n_collisions for c in reqs) / args.serve_seconds
         return {"requests": len(tickets), "rate_per_s": args.serve_rate, "arrival_window_s": args.serve_seconds,
                 "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
                 "served_real_per_s": real / (t_end - t0), "offered_real_per_s": offered,
+                "served_trials_per_s": trials / (t_end - t0), "efficiency": real / trials,
                 "makespan_s": t_end - t0}
     finally:
         sw.swarm_server_destroy(srv)
