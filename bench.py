@@ -60,6 +60,8 @@ def parse():
                     help="skip the leg with screened-Coulomb scattering")
     ap.add_argument("--no-real", action="store_true",
                     help="skip the real-secondaries leg (mixture, 1e6 primaries)")
+    ap.add_argument("--real-only", action="store_true",
+                    help="only run the real-secondaries leg (used for its kernel trace)")
     ap.add_argument("--no-batch256", action="store_true",
                     help="skip the 256-instance batch leg")
     ap.add_argument("--serve-rate", type=float, default=5.0)
@@ -375,6 +377,10 @@ def main():
     if args.serve_only:
         import paper_1901_08140_amd as sw
         print(json.dumps({"serving": serve(sw, args)}), flush=True)
+        return
+    if args.real_only:
+        import paper_1901_08140_amd as sw
+        print(json.dumps({"real_secondaries": real_secondaries_leg(sw, args)}), flush=True)
         return
     if args.copy_probe:
         n = args.copy_probe // 4
