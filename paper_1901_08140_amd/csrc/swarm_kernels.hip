@@ -776,7 +776,8 @@ __device__ __forceinline__ R energy_at(const Lane<R>& L, const Consts<R>& C, R T
 // no select on the weight.  Index and weight are exact: the node index comes from the
 // exponent and leading mantissa bits, and w = frac(2 P mant) = frac((2 mant - 1) P) (the
 // product by the power of two 2P is exact).  The raw index (exponent and leading mantissa
-// bits, clamped to [off1, off1 + G]) is returned; the padded index is raw - off1.
+// bits, clamped to [off1, off1 + G]) is returned; the padded index is raw - off1, and the
+// FP32 table is read through a base moved back by off1 entries (one address instruction).
 __device__ __forceinline__ int raw_index(float eps, const Consts<float>& C) {
   return min(max(static_cast<int>(__float_as_uint(eps) >> (23 - C.p)), C.off1), C.off1G);
 }
@@ -788,7 +789,7 @@ __device__ __forceinline__ float lds_rate(const float2* __restrict__ s_nu, float
                                          int* raw_out, float* w_out) {
   const int raw = raw_index(eps, C);
   const float w = __builtin_amdgcn_fractf(__builtin_amdgcn_frexp_mantf(eps) * C.twoPf);
-  const float2 q = s_nu[raw - C.off1];
+  const float2 q = (s_nu - C.off1)[raw];
   *raw_out = raw;
   *w_out = w;
   return fmaf(w, q.y, q.x);
@@ -1096,9 +1097,10 @@ __device__ __forceinline__ bool one_trial(Lane<R>& L, const Consts<R>& C,
                                           const typename Pair<R>::T* __restrict__ s_nu,
                                           uint32_t hf, uint32_t hr, uint32_t lf, uint32_t lr) {
   if constexpr (sizeof(R) == 4) {
-    // u = (hf >> 8) 2^-24: -ln(1-u)/nu' = (24 - log2(2^24 - (hf >> 8))) ln2/nu'
-    const float l2 = __builtin_amdgcn_logf(static_cast<float>(0x1000000u - (hf >> 8)));
-    L.T = fmaf(l2 - 24.0f, -(EXT ? L.cT : C.cT), L.T);
+    // u = (hf >> 8) 2^-24: -ln(1-u)/nu' = -log2(1 - u) ln2/nu', with 1 - u formed exactly
+    // by one FMA (a 24-bit integer times 2^-24 subtracted from 1)
+    const float l2 = __builtin_amdgcn_logf(fmaf(static_cast<float>(hf >> 8), -0x1.0p-24f, 1.0f));
+    L.T = fmaf(l2, -(EXT ? L.cT : C.cT), L.T);
     L.p_x = static_cast<float>(hr >> 8) * (EXT ? L.nup24 : C.nup24);    // = u_r nu' exactly
   } else {
     L.T = L.T + flight(uni(hf, lf, R(0)), EXT ? L.cT : C.cT);
