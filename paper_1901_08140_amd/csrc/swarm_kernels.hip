@@ -1156,12 +1156,10 @@ __device__ __forceinline__ void trial_block(Lane<R>& L, const Consts<R>& C,
   // candidate becomes PENDING and stops writing them until it is served, so they need no
   // copy, and the second trial runs only on the lanes whose first one was null.
   bool hit = one_trial<R, HB, EXT>(L, C, s_nu, h.x, h.y, l.x, l.y);
-  L.p_sub = 0;
-  if (!hit) {
-    hit = one_trial<R, HB, EXT>(L, C, s_nu, h.z, h.w, l.z, l.w);
-    L.p_sub = 1;
-  }
-  if (hit) L.state = ST_PENDING;
+  const bool second = !hit;
+  if (second) hit = one_trial<R, HB, EXT>(L, C, s_nu, h.z, h.w, l.z, l.w);
+  L.p_sub = second ? 1u : 0u;
+  L.state = hit ? ST_PENDING : ST_ACTIVE;
 }
 
 // Outcome of serving a pending candidate.
