@@ -1549,12 +1549,14 @@ __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restr
         }
       }
       // Trial phase: random-number blocks until enough lanes of the wave wait on a
-      // real-collision candidate (or none can go on), then serve them together.
+      // real-collision candidate (or none can go on), then serve them together.  (`drawing`
+      // is carried to the next pass, so the test is made once per pass.)
+      bool drawing = L.state == ST_ACTIVE || L.state == ST_PENDING;
       for (;;) {
-        if (L.state == ST_ACTIVE || L.state == ST_PENDING) trial_block<R, HB, EXT>(L, C, s_nu);
+        if (drawing) trial_block<R, HB, EXT>(L, C, s_nu);
+        drawing = L.state == ST_ACTIVE || L.state == ST_PENDING;
         const uint64_t ready = __ballot(L.state == ST_READY);
-        const uint64_t busy = __ballot(L.state == ST_ACTIVE || L.state == ST_PENDING);
-        if (busy == 0 || __popcll(ready) >= pend_trig) break;
+        if (__ballot(drawing) == 0 || __popcll(ready) >= pend_trig) break;
       }
       if (L.state == ST_READY) {
         bool spawn;
@@ -1977,11 +1979,12 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
       }
     }
     uint64_t ready;
+    bool drawing = L.state == ST_ACTIVE || L.state == ST_PENDING;
     for (;;) {
-      if (L.state == ST_ACTIVE || L.state == ST_PENDING) trial_block<R, HB, EXT>(L, C, s_nu);
+      if (drawing) trial_block<R, HB, EXT>(L, C, s_nu);
+      drawing = L.state == ST_ACTIVE || L.state == ST_PENDING;
       ready = __ballot(L.state == ST_READY);
-      const uint64_t busy = __ballot(L.state == ST_ACTIVE || L.state == ST_PENDING);
-      if (busy == 0 || __popcll(ready) >= pend_trig) break;
+      if (__ballot(drawing) == 0 || __popcll(ready) >= pend_trig) break;
     }
     if (ready != 0) {
       bool spawn = false;
