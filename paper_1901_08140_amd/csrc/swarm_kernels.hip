@@ -112,13 +112,11 @@ __device__ __forceinline__ float uni(uint32_t hi, uint32_t, float) {
   return static_cast<float>(hi >> 8) * 0x1.0p-24f;
 }
 
-// Flight-time increment -ln(1-u)/nu' (eq. random_time).  FP32 uses the hardware log2 with
-// cT = ln2/nu'; FP64 the libm logarithm with cT = 1/nu'.  1-u is exact in both.
-__device__ __forceinline__ float flight(float u, float cT) { return -__builtin_amdgcn_logf(1.0f - u) * cT; }
+// Flight-time increment -ln(1-u)/nu' (eq. random_time) in FP64: the libm logarithm with
+// cT = 1/nu' (1-u is exact).  The FP32 trial forms its own from the 24-bit word (one_trial).
 __device__ __forceinline__ double flight(double u, double cT) { return -log(1.0 - u) * cT; }
 
 __device__ __forceinline__ float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double rsqrt_(double x) { return 1.0 / sqrt(x); }
 __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
 __device__ __forceinline__ float fma_(float a, float b, float c) { return fmaf(a, b, c); }
@@ -314,7 +312,7 @@ __global__ void k_build_constants(InstanceDesc* desc) {
   szero[threadIdx.x] = zero;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
+    if (static_cast<int>(threadIdx.x) < s) {
       smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
       szero[threadIdx.x] |= szero[threadIdx.x + s];
     }
@@ -1556,7 +1554,7 @@ __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restr
         if (drawing) trial_block<R, HB, EXT>(L, C, s_nu);
         drawing = L.state == ST_ACTIVE || L.state == ST_PENDING;
         const uint64_t ready = __ballot(L.state == ST_READY);
-        if (__ballot(drawing) == 0 || __popcll(ready) >= pend_trig) break;
+        if (__ballot(drawing) == 0 || static_cast<int>(__popcll(ready)) >= pend_trig) break;
       }
       if (L.state == ST_READY) {
         bool spawn;
@@ -1780,7 +1778,7 @@ __global__ void __launch_bounds__(512) k_swarm_pooled(const InstanceDesc* __rest
         __syncthreads();
         __syncthreads();
         const int n = min(s_ncand[round & 1], P.cap);
-        if (threadIdx.x == n_trial * 64) {
+        if (static_cast<int>(threadIdx.x) == n_trial * 64) {
           s_ncand[(round + 1) & 1] = 0;
           s_live[(round + 1) % 3] = 0;
         }
@@ -1984,7 +1982,7 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
       if (drawing) trial_block<R, HB, EXT>(L, C, s_nu);
       drawing = L.state == ST_ACTIVE || L.state == ST_PENDING;
       ready = __ballot(L.state == ST_READY);
-      if (__ballot(drawing) == 0 || __popcll(ready) >= pend_trig) break;
+      if (__ballot(drawing) == 0 || static_cast<int>(__popcll(ready)) >= pend_trig) break;
     }
     if (ready != 0) {
       bool spawn = false;
@@ -2037,7 +2035,7 @@ __device__ __forceinline__ void block_sum(double* vals, int nq, double* s_red) {
   for (int q = 0; q < nq; ++q) s_red[q * kTallyThreads + threadIdx.x] = vals[q];
   __syncthreads();
   for (int s = kTallyThreads / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s)
+    if (static_cast<int>(threadIdx.x) < s)
       for (int q = 0; q < nq; ++q)
         s_red[q * kTallyThreads + threadIdx.x] += s_red[q * kTallyThreads + threadIdx.x + s];
     __syncthreads();
