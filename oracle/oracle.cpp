@@ -20,9 +20,10 @@
 // frequency's special cases (cap = constant method, constant rate, no field); anisotropic
 // scattering: quadrature of the sampled cos(theta) against sigma_mt/sigma_el and the
 // screened-Coulomb closed form, rotation geometry, the Maxwell drift eE/(m nu (1-<cos>)).
-// Parity unpinned by a closed form: diffusion magnitudes (sigma, sigma_L, sigma_T) and
-// tallies for the synthetic argon/CO2 tables, and the fail sequences of the variable trial
-// frequency; those rest on GPU-vs-oracle parity.
+// The diffusion magnitudes (sigma, sigma_L, sigma_T) are pinned against an independent
+// random walk of the field-free process and its Gaussian limit.  Parity unpinned by a closed
+// form: tallies for the synthetic argon/CO2 tables at non-trivial fields, and the fail
+// sequences of the variable trial frequency; those rest on GPU-vs-oracle parity.
 
 #include <algorithm>
 #include <atomic>

@@ -94,6 +94,42 @@ def test_diffusion_closed_form_no_field():
     assert abs(T["DT"][2] / T["DT"][0] - 1.0) < 0.08
 
 
+def test_spread_tallies_against_independent_random_walk():
+    # E = 0, very heavy target, constant nu, speed v0: after n real collisions an electron
+    # has made n isotropic, independent steps of length v0 tau, tau ~ Exp(nu) (null
+    # collisions thin a Poisson process and turn nothing).  The spread tallies sigma =
+    # <2|d|>, sigma_L = <2|d_z|>, sigma_T = <2|d_perp|> (section "Determination of swarm
+    # attributes") must equal those of a plain numpy walk of that process, and approach the
+    # Gaussian limits E|d| = sqrt(8 <d^2> / (3 pi)), E|d_z| = sqrt(2 <d_z^2> / pi),
+    # E|d_perp| = sqrt(pi <d_perp^2> / 4) with <d^2> = 2 n (v0/nu)^2.
+    k = synth.tables.MAXWELL_K
+    comp = synth.constant_rate_component(1e9, 1.0, k)
+    m = oracle.OracleModel([comp], 0.0, init_energy_eV=1.0)
+    n, ne = 50, 40000
+    T = tallies(m.run(ne, n, 5).records)
+    nu, v0 = 1e12, math.sqrt(2 * QE / ME)
+    rng = np.random.default_rng(123)
+    nw = 400_000
+    d = np.zeros((nw, 3))
+    for _ in range(n):
+        cz = rng.uniform(-1.0, 1.0, nw)
+        ph = rng.uniform(0.0, 2 * math.pi, nw)
+        sz = np.sqrt(1.0 - cz * cz)
+        step = rng.exponential(v0 / nu, nw)
+        d[:, 0] += step * sz * np.cos(ph)
+        d[:, 1] += step * sz * np.sin(ph)
+        d[:, 2] += step * cz
+    walk = {"sigma": 2 * np.linalg.norm(d, axis=1), "sigmaL": 2 * np.abs(d[:, 2]),
+            "sigmaT": 2 * np.linalg.norm(d[:, :2], axis=1)}
+    for key, x in walk.items():
+        _within(T[key][0], x.mean(), math.hypot(T[key][1], x.std() / math.sqrt(nw)), k=4.0)
+    d2 = 2 * n * (v0 / nu) ** 2
+    gauss = {"sigma": 2 * math.sqrt(8 * d2 / (3 * math.pi)), "sigmaL": 2 * math.sqrt(2 * d2 / (3 * math.pi)),
+             "sigmaT": 2 * math.sqrt(math.pi * (2 * d2 / 3) / 4)}
+    for key, want in gauss.items():
+        assert abs(T[key][0] / want - 1) < 0.03, (key, T[key][0] / want)
+
+
 def _const_rates(k_el, k_ion, k_att):
     return synth.constant_rate_component(4.0, 1.0, k_el, k_ion, k_att)
 
