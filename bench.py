@@ -6,13 +6,13 @@ E/N log-spaced over 1-1000 Td, B = 0, 100,000 electrons x 20,000 real collisions
 seed 0, dummy ionisation (6.4e10 real collisions per step).
 
 A step is one batched launch of all 32 instances in FP32-mixed precision: one persistent
-kernel (launch shape from the autotuner) plus the tally reductions, replayed from a
-hipGraph.  `value` = real collisions per second over the timed steps.  Also measured once:
+kernel (the default launch shape; --autotune runs the autotuner first) plus the tally
+reductions, replayed from a hipGraph.  `value` = real collisions per second over the timed steps.  Also measured once:
 the same workload as 32 plain FP64 single-instance runs, the FP32-vs-FP64 tally agreement,
 a short serving run (p50/p99 request latency), and the FP64 CPU oracle on a bounded sample
 on the host cores.
 
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]   (--help lists the other legs)
 """
 import argparse
 import json
@@ -28,13 +28,15 @@ sys.path.insert(0, ROOT)
 # B = 0 (full-rate VALU instruction = 1 slot; transcendentals log/sqrt/rsqrt/sin/cos = 2, as
 # measured on gfx950; 32x32->64 integer multiply-add = 1, also measured full rate; a
 # three-input xor = 1, gfx950 has it as one instruction).
-# Trial (42): half a Philox4x32-10 call (20 multiply-adds + 20 three-input xors per call),
-# the flight time from the 24-bit uniform (5 + log), x = R nu' (3), |v(T)|^2 m/2e (2 FMA),
-# octave-grid position from the bits (8), interpolated rate and compare (2).  Real collision
+# Trial (40): half a Philox4x32-10 call (20 multiply-adds + 20 three-input xors per call),
+# the flight time from the 24-bit uniform (shift, convert, 1 - u by one FMA, log, FMA: 4 +
+# log), x = R nu' (3), |v(T)|^2 m/2e (2 FMA), octave-grid position from the bits (shift,
+# clamp 2, address 1, mantissa, scale, fraction: 7), interpolated rate and compare (2).  Real
+# collision
 # (113): one Philox call for the scattering block (40), channel search over the running sums
 # (12), onset compare in FP64 (8), isotropic direction (16), cos(theta) (6), energy transfer
 # (3), FP64 energy sums, position and time (16), new velocity (6), next-flight constants (4).
-OPS_PER_TRIAL = 42
+OPS_PER_TRIAL = 40
 OPS_PER_REAL = 113
 PEAK_LANE_OPS = 256 * 64 * 2.4e9      # 256 CUs x 64 FP32 lanes/clock x 2.4 GHz = 3.93e13 /s
 
