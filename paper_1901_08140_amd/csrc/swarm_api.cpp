@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "swarm_api_internal.hpp"
+#include "unit_log.hpp"
 
 using namespace swarm_impl;
 
@@ -407,8 +408,11 @@ swarm_status swarm_create(const swarm_component* comps, int32_t n_comps, const s
   const size_t b_ch = al(nc * sizeof(ChannelDev)), b_th = al(nc * sizeof(ThermalChannel));
   const size_t b_eb = al(entry_bin.size() * 4), b_bf = al(bin_first.size() * 4);
   const size_t b_bn = al(static_cast<size_t>(d.n_bins) * 8), b_bn32 = al(static_cast<size_t>(d.n_bins) * 4);
+  std::vector<double> logtab(kUnitLogStride * kUnitLogEntries);
+  unit_log_table(logtab.data());
+  const size_t b_lt = al(logtab.size() * 8);
   const size_t total = b_e + b_s + 4 * b_i + b_cd + 4 * b_k + b_nodes + b_cm + b_nu64 + b_nu32 + b_c64 + b_c32 + b_ch +
-                       b_th + b_eb + b_bf + b_bn + b_bn32 + al(sizeof(InstanceDesc)) + al(sizeof(RunCounters));
+                       b_th + b_eb + b_bf + b_bn + b_bn32 + b_lt + al(sizeof(InstanceDesc)) + al(sizeof(RunCounters));
   hipError_t e = h->arena.ensure(total);
   if (e != hipSuccess) return hip_fail(e, "allocating instance tables");
   char* base = static_cast<char*>(h->arena.p);
@@ -439,6 +443,8 @@ swarm_status swarm_create(const swarm_component* comps, int32_t n_comps, const s
   d.bin_first = d_bin_first;
   d.bin_nup64 = reinterpret_cast<double*>(take(b_bn));
   d.bin_nup32 = reinterpret_cast<float*>(take(b_bn32));
+  double* d_logtab = reinterpret_cast<double*>(take(b_lt));
+  d.logtab = d_logtab;
   h->d_desc = reinterpret_cast<InstanceDesc*>(take(al(sizeof(InstanceDesc))));
   d.ctr = reinterpret_cast<RunCounters*>(take(al(sizeof(RunCounters))));
   d.raw_e = d_e; d.raw_s = d_s; d.raw_off = d_off; d.raw_n = d_n; d.raw_kind = d_kind;
@@ -449,6 +455,7 @@ swarm_status swarm_create(const swarm_component* comps, int32_t n_comps, const s
   CP(d_e, e_all) CP(d_s, s_all) CP(d_off, off) CP(d_n, npt) CP(d_kind, kind) CP(d_comp, comp)
   CP(d_thr, thr) CP(d_mass, mass) CP(d_frac, frac) CP(d_scat, scat) CP(d_ratio, ratio)
   if (!entry_bin.empty()) { CP(d_entry_bin, entry_bin) CP(d_bin_first, bin_first) }
+  CP(d_logtab, logtab)
 #undef CP
   if ((e = launch_fill_u64(reinterpret_cast<uint64_t*>(d.ctr), 0, sizeof(RunCounters) / 8, s)) != hipSuccess)
     return hip_fail(e, "clearing counters");

@@ -104,6 +104,7 @@ struct InstanceDesc {
   int32_t n_bins;             // binned: number of bins (0 for the other strategies)
   const int32_t* bin_of;      // binned: bin of every entry of the padded rate table (G + 1)
   const int32_t* bin_first;   // binned: first table entry of every bin (n_bins + 1)
+  const double* logtab;       // FP64 flight times: the logarithm table (unit_log.hpp)
   const double* raw_e;        // concatenated raw energies
   const double* raw_s;        // concatenated raw cross-sections
   const int32_t* raw_off;     // per channel: first point

@@ -20,6 +20,7 @@
 #include <math.h>
 
 #include "swarm_internal.hpp"
+#include "unit_log.hpp"
 
 namespace swarm_impl {
 namespace {
@@ -112,9 +113,13 @@ __device__ __forceinline__ float uni(uint32_t hi, uint32_t, float) {
   return static_cast<float>(hi >> 8) * 0x1.0p-24f;
 }
 
-// Flight-time increment -ln(1-u)/nu' (eq. random_time) in FP64: the libm logarithm with
-// cT = 1/nu' (1-u is exact).  The FP32 trial forms its own from the 24-bit word (one_trial).
-__device__ __forceinline__ double flight(double u, double cT) { return -log(1.0 - u) * cT; }
+// Flight-time increment -ln(1-u)/nu' (eq. random_time) in FP64, cT = 1/nu': 1-u is exact,
+// and its logarithm comes from the table-driven unit_log (about 20 instructions where the
+// library logarithm takes about 85), with the table staged in LDS.  The FP32 trial forms
+// its own from the 24-bit word (one_trial).
+__device__ __forceinline__ double flight(double u, double cT, const double* __restrict__ logtab) {
+  return -unit_log(1.0 - u, logtab) * cT;
+}
 
 __device__ __forceinline__ float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
@@ -488,6 +493,7 @@ struct Consts {
   Key key;
   const typename Pair<R>::T* cum;
   const ChannelDev* chan;
+  const double* logtab;    // FP64: the logarithm table of the flight times, in LDS
   const ThermalChannel* chan_th;
   const int32_t* bin_of;   // binned: bin of every padded table entry
   const R* bin_nup;        // binned: nu' of every bin
@@ -1101,7 +1107,7 @@ __device__ __forceinline__ bool one_trial(Lane<R>& L, const Consts<R>& C,
     L.T = fmaf(l2, -(EXT ? L.cT : C.cT), L.T);
     L.p_x = static_cast<float>(hr >> 8) * (EXT ? L.nup24 : C.nup24);    // = u_r nu' exactly
   } else {
-    L.T = L.T + flight(uni(hf, lf, R(0)), EXT ? L.cT : C.cT);
+    L.T = L.T + flight(uni(hf, lf, R(0)), EXT ? L.cT : C.cT, C.logtab);
     L.p_x = uni(hr, lr, R(0)) * (EXT ? L.nup : C.nup);
   }
   L.p_eps = energy_at<R, HB, EXT>(L, C, L.T);
@@ -1491,6 +1497,7 @@ __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restr
   using PT = typename Pair<R>::T;
   extern __shared__ __align__(16) unsigned char smem[];
   PT* s_nu = reinterpret_cast<PT*>(smem);
+  __shared__ double s_logtab[sizeof(R) == 8 ? kUnitLogStride * kUnitLogEntries : 1];
   ChannelDev* s_ch = reinterpret_cast<ChannelDev*>(smem + ch_off);
   __shared__ int s_item;
   __shared__ int s_next;
@@ -1512,6 +1519,8 @@ __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restr
         s_nu[g] = q;
       }
       for (int c = threadIdx.x; c < d.nc; c += blockDim.x) s_ch[c] = d.chan[c];
+      if constexpr (sizeof(R) == 8)
+        for (int j = threadIdx.x; j < kUnitLogStride * kUnitLogEntries; j += blockDim.x) s_logtab[j] = d.logtab[j];
       stage_cum<R>(d, smem, cum_off);
       cur_inst = inst;
     }
@@ -1519,6 +1528,7 @@ __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restr
     __syncthreads();
     Consts<R> C = load_consts<R>(d);
     C.chan = s_ch;
+    C.logtab = s_logtab;
     if (cum_off >= 0) C.cum = reinterpret_cast<const PT*>(smem + cum_off);
     const int64_t count = wi.count;
     Lane<R> L;
@@ -1727,6 +1737,7 @@ __global__ void __launch_bounds__(512) k_swarm_pooled(const InstanceDesc* __rest
   using PT = typename Pair<R>::T;
   extern __shared__ __align__(16) unsigned char smem[];
   PT* s_nu = reinterpret_cast<PT*>(smem);
+  __shared__ double s_logtab[sizeof(R) == 8 ? kUnitLogStride * kUnitLogEntries : 1];
   ChannelDev* s_ch = reinterpret_cast<ChannelDev*>(smem + ch_off);
   __shared__ int s_item;
   __shared__ int s_next;
@@ -1760,6 +1771,8 @@ __global__ void __launch_bounds__(512) k_swarm_pooled(const InstanceDesc* __rest
         s_nu[g] = q;
       }
       for (int c = threadIdx.x; c < d.nc; c += blockDim.x) s_ch[c] = d.chan[c];
+      if constexpr (sizeof(R) == 8)
+        for (int j = threadIdx.x; j < kUnitLogStride * kUnitLogEntries; j += blockDim.x) s_logtab[j] = d.logtab[j];
       stage_cum<R>(d, smem, cum_off);
       cur_inst = inst;
     }
@@ -1771,6 +1784,7 @@ __global__ void __launch_bounds__(512) k_swarm_pooled(const InstanceDesc* __rest
     __syncthreads();
     Consts<R> C = load_consts<R>(d);
     C.chan = s_ch;
+    C.logtab = s_logtab;
     if (cum_off >= 0) C.cum = reinterpret_cast<const PT*>(smem + cum_off);
     if (server) {
       // ---- service waves: the same three barriers per round as the trial waves ----
@@ -1892,6 +1906,7 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
   using PT = typename Pair<R>::T;
   extern __shared__ __align__(16) unsigned char smem[];
   PT* s_nu = reinterpret_cast<PT*>(smem);
+  __shared__ double s_logtab[sizeof(R) == 8 ? kUnitLogStride * kUnitLogEntries : 1];
   ChannelDev* s_ch = reinterpret_cast<ChannelDev*>(smem + ch_off);
   const InstanceDesc& d = *desc;
   {
@@ -1903,11 +1918,14 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
       s_nu[g] = q;
     }
     for (int c = threadIdx.x; c < d.nc; c += blockDim.x) s_ch[c] = d.chan[c];
+    if constexpr (sizeof(R) == 8)
+      for (int j = threadIdx.x; j < kUnitLogStride * kUnitLogEntries; j += blockDim.x) s_logtab[j] = d.logtab[j];
     stage_cum<R>(d, smem, cum_off);
   }
   __syncthreads();
   Consts<R> C = load_consts<R>(d);
   C.chan = s_ch;
+  C.logtab = s_logtab;
   if (cum_off >= 0) C.cum = reinterpret_cast<const PT*>(smem + cum_off);
   RunCounters* ctr = d.ctr;
   const int64_t N = d.n_electrons;
