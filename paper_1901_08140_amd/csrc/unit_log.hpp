@@ -41,16 +41,16 @@ inline void unit_log_table(double* tab) {
 __host__ __device__ inline double unit_log(double x, const double* __restrict__ tab) {
   int e;
   const double mant = frexp(x, &e);          // x = mant 2^e, mant in [0.5, 1)
-  const double m = 2.0 * mant;               // [1, 2), exact
+  // Within 2^-7 of 1, take m = x with exponent 0 and entry 0 (RN(1/c) = 1, no log term):
+  // then r = x - 1 exactly.  Elsewhere m = 2 mant in [1, 2) with exponent e - 1.
+  const bool near1 = x > 0x1.fcp-1;
+  const double m = near1 ? x : 2.0 * mant;
   uint64_t bits;
   memcpy(&bits, &m, sizeof(bits));
-  const int i = static_cast<int>((bits >> 46) & 63u);    // top six fraction bits
-  const bool near1 = x > 0x1.fcp-1;          // x > 1 - 2^-7
-  const double* t = tab + kUnitLogStride * i;
-  const double r = near1 ? x - 1.0 : fma(m, t[0], -1.0);
+  const int i = near1 ? 0 : static_cast<int>((bits >> 46) & 63u);   // top six fraction bits
   const double ed = near1 ? 0.0 : static_cast<double>(e - 1);
-  const double tl_hi = near1 ? 0.0 : t[1];
-  const double tl_lo = near1 ? 0.0 : t[2];
+  const double* t = tab + kUnitLogStride * i;
+  const double r = fma(m, t[0], -1.0);
   double p = 1.0 / 9.0;
   p = fma(p, r, -1.0 / 8.0);
   p = fma(p, r, 1.0 / 7.0);
@@ -60,10 +60,10 @@ __host__ __device__ inline double unit_log(double x, const double* __restrict__ 
   p = fma(p, r, 1.0 / 3.0);
   p = fma(p, r, -0.5);
   const double lp = fma(r * r, p, r);                     // log1p(r)
-  const double ln2_hi = 0x1.62e42fefa3800p-1;             // 43 significant bits: ed ln2_hi exact
+  const double ln2_hi = 0x1.62e42fefa3800p-1;             // 42 significant bits: ed ln2_hi exact
   const double ln2_lo = 0x1.ef35793c76730p-45;
-  const double hi = fma(ed, ln2_hi, tl_hi);     // exact where the two terms cancel
-  const double lo = fma(ed, ln2_lo, tl_lo + lp);
+  const double hi = fma(ed, ln2_hi, t[1]);                // exact where the two terms cancel
+  const double lo = fma(ed, ln2_lo, t[2] + lp);
   return hi + lo;
 }
 
