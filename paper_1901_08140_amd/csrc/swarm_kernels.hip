@@ -127,13 +127,15 @@ __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
 __device__ __forceinline__ float fma_(float a, float b, float c) { return fmaf(a, b, c); }
 __device__ __forceinline__ double fma_(double a, double b, double c) { return fma(a, b, c); }
 
-// sin/cos of 2 pi u for u in [0,1): FP32 through the hardware unit (input in revolutions).
+// sin/cos of 2 pi u for u in [0,1): FP32 through the hardware unit (input in revolutions);
+// FP64 as sin/cos of pi (2u), whose argument reduction is exact, so none of the general
+// large-argument reduction is needed.
 __device__ __forceinline__ void sincos_rev(float u, float* s, float* c) {
   *s = __builtin_amdgcn_sinf(u);
   *c = __builtin_amdgcn_cosf(u);
 }
 __device__ __forceinline__ void sincos_rev(double u, double* s, double* c) {
-  sincos(2.0 * kPi * u, s, c);
+  sincospi(2.0 * u, s, c);
 }
 
 // Anisotropic scattering (section "Theoretical framework", eqs. collision_angle and
@@ -471,7 +473,7 @@ __global__ void k_fill_u64(uint64_t* p, uint64_t v, int64_t n) {
 template <typename R>
 struct Consts {
   R nup, cT, c_eps, c_speed, speed0, az, omega, bx, bz, vDy, apar;
-  R omega_rev;   // FP32 trial phase in revolutions
+  R omega_rev;   // omega / (2 pi): the gyration phase in revolutions
   R aze, apare;  // accelerations in energy units (FP32: times sqrt(m/2e); FP64: plain)
   R nup24;       // FP32: nu' 2^-24 (x = R nu' straight from the 24-bit integer)
   R Pf, twoPf;   // grid points per octave, and twice that, as floating point
@@ -505,7 +507,7 @@ __device__ __forceinline__ Consts<R> load_consts(const InstanceDesc& d) {
   if constexpr (sizeof(R) == 8) {
     c.nup = d.majorant; c.cT = d.inv_majorant; c.c_eps = d.c_eps; c.c_speed = d.c_speed;
     c.speed0 = d.speed0; c.az = d.az; c.omega = d.omega; c.bx = d.bx; c.bz = d.bz; c.vDy = d.vDy;
-    c.apar = d.apar; c.omega_rev = 0.0;
+    c.apar = d.apar; c.omega_rev = d.omega * (0.5 / kPi);
     c.cum = reinterpret_cast<const typename Pair<R>::T*>(d.cum64);
     c.off = (1023 + d.emin) << d.p_log2;
   } else {
@@ -765,7 +767,7 @@ __device__ __forceinline__ R energy_at(const Lane<R>& L, const Consts<R>& C, R T
       s = __builtin_amdgcn_sinf(x);
       c = __builtin_amdgcn_cosf(x);
     } else {
-      sincos(C.omega * T, &s, &c);
+      sincospi(2.0 * C.omega_rev * T, &s, &c);     // omega T = pi (2 omega_rev T)
     }
     const R vp = fma_(C.apare, T, L.e_vpar);
     const R v2 = fma_(vp, vp, fma_(L.e_Bs, s, fma_(L.e_Bc, c, L.e_q0)));
@@ -956,9 +958,9 @@ __device__ __forceinline__ void move_full(const Lane<R>& L, const Consts<R>& C, 
       c = __builtin_amdgcn_cosf(x);
       sh = __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(0.5f * C.omega_rev * T));
     } else {
-      const double wt = C.omega * T;
-      sincos(wt, &s, &c);
-      sh = sin(0.5 * wt);
+      const double ph = 2.0 * C.omega_rev * T;      // omega T / pi
+      sincospi(ph, &s, &c);
+      sh = sinpi(0.5 * ph);
     }
     const R omc = R(2) * sh * sh;   // 1 - cos(wT)
     const R px = C.bx * L.vpar, pz = C.bz * L.vpar;       // v_par0
