@@ -112,13 +112,18 @@ __device__ __forceinline__ double uni(uint32_t hi, uint32_t lo, double) {
 __device__ __forceinline__ float uni(uint32_t hi, uint32_t, float) {
   return static_cast<float>(hi >> 8) * 0x1.0p-24f;
 }
+// 1 - u for the FP64 uniform of (hi, lo), formed directly: 1 - lo' 2^-53 and then minus
+// hi 2^-32 are both exact, so this equals 1 - uni(hi, lo) bit for bit, one step shorter.
+__device__ __forceinline__ double one_minus_uni(uint32_t hi, uint32_t lo) {
+  return fma(static_cast<double>(hi), -0x1.0p-32, fma(static_cast<double>(lo >> 11), -0x1.0p-53, 1.0));
+}
 
 // Flight-time increment -ln(1-u)/nu' (eq. random_time) in FP64, cT = 1/nu': 1-u is exact,
 // and its logarithm comes from the table-driven unit_log (about 20 instructions where the
 // library logarithm takes about 85), with the table staged in LDS.  The FP32 trial forms
 // its own from the 24-bit word (one_trial).
-__device__ __forceinline__ double flight(double u, double cT, const double* __restrict__ logtab) {
-  return -unit_log(1.0 - u, logtab) * cT;
+__device__ __forceinline__ double flight(double one_minus_u, double cT, const double* __restrict__ logtab) {
+  return -unit_log(one_minus_u, logtab) * cT;
 }
 
 __device__ __forceinline__ float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
@@ -783,7 +788,7 @@ __device__ __forceinline__ R energy_at(const Lane<R>& L, const Consts<R>& C, R T
 // exponent and leading mantissa bits, and w = frac(2 P mant) = frac((2 mant - 1) P) (the
 // product by the power of two 2P is exact).  The raw index (exponent and leading mantissa
 // bits, clamped to [off1, off1 + G]) is returned; the padded index is raw - off1, and the
-// FP32 table is read through a base moved back by off1 entries (one address instruction).
+// table is read through a base moved back by off1 entries (one address instruction).
 __device__ __forceinline__ int raw_index(float eps, const Consts<float>& C) {
   return min(max(static_cast<int>(__float_as_uint(eps) >> (23 - C.p)), C.off1), C.off1G);
 }
@@ -804,7 +809,7 @@ __device__ __forceinline__ double lds_rate(const double2* __restrict__ s_nu, dou
                                           int* raw_out, double* w_out) {
   const int raw = raw_index(eps, C);
   const double w = __builtin_amdgcn_fract(__builtin_amdgcn_frexp_mant(eps) * C.twoPf);
-  const double2 q = s_nu[raw - C.off1];
+  const double2 q = (s_nu - C.off1)[raw];
   *raw_out = raw;
   *w_out = w;
   return q.x + w * q.y;
@@ -1109,7 +1114,7 @@ __device__ __forceinline__ bool one_trial(Lane<R>& L, const Consts<R>& C,
     L.T = fmaf(l2, -(EXT ? L.cT : C.cT), L.T);
     L.p_x = static_cast<float>(hr >> 8) * (EXT ? L.nup24 : C.nup24);    // = u_r nu' exactly
   } else {
-    L.T = L.T + flight(uni(hf, lf, R(0)), EXT ? L.cT : C.cT, C.logtab);
+    L.T = L.T + flight(one_minus_uni(hf, lf), EXT ? L.cT : C.cT, C.logtab);
     L.p_x = uni(hr, lr, R(0)) * (EXT ? L.nup : C.nup);
   }
   L.p_eps = energy_at<R, HB, EXT>(L, C, L.T);
