@@ -1309,7 +1309,7 @@ __device__ __forceinline__ int forbidden_pick(const InstanceDesc& d, Lane<R>& L,
 template <typename R, bool HB, bool TR, bool REAL, int EXT>
 __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L, const Consts<R>& C,
                                               const typename Pair<R>::T* __restrict__ s_nu,
-                                              bool* spawn, ChildState* child) {
+                                              bool* spawn) {
   *spawn = false;
   const R eps = L.p_eps;
   const R x = L.p_x;
@@ -1430,17 +1430,11 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
     epsp = epsp * R(0.5);            // equal sharing with the ejected electron
     L.G += 1;
     if constexpr (REAL) {
-      const W4 cw = draw(C.key, L.id, TAG_CHILD, L.k);
-      R sx, sy, sz;
-      iso_dir<R>(uni(h.z, l.z, R(0)), uni(h.w, l.w, R(0)), &sx, &sy, &sz);
-      const R sp = speed_of_energy<R, EXT>(C, epsp);
-      child->r[0] = rx; child->r[1] = ry; child->r[2] = rz;
-      child->t = L.t + static_cast<double>(L.T);
-      child->v[0] = sp * sx; child->v[1] = sp * sy; child->v[2] = sp * sz;
-      child->id = (static_cast<uint64_t>(cw.x) | (static_cast<uint64_t>(cw.y) << 32)) | (1ull << 63);
-      child->k = L.k + 1;
-      child->pad = 0;
-      child->eps_birth = static_cast<double>(epsp);
+      // The secondary is built after this collision from the lane (make_child): it starts at
+      // the collision point and time with the parent's count after it, takes its direction
+      // from words 3 and 4 of the scattering block (still in L.sh, L.sl) and this energy,
+      // which is kept in the candidate field (unused until the next trial).
+      L.p_eps = epsp;
       *spawn = true;
     }
   } else if (ch.kind == SWARM_ATTACHMENT) {
@@ -1473,6 +1467,26 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
   set_anchor<R, HB>(L, C);
   L.state = ST_ACTIVE;
   return RC_CONTINUE;
+}
+
+// The secondary of an ionisation served by real_collision (see there): the lane holds the
+// collision point, time and count after it, the scattering words and the shared energy.
+template <typename R, int EXT>
+__device__ __forceinline__ ChildState make_child(const Lane<R>& L, const Consts<R>& C) {
+  const W4 cw = draw(C.key, L.id, TAG_CHILD, L.k - 1);
+  R sx, sy, sz;
+  iso_dir<R>(uni(L.sh.z, L.sl.z, R(0)), uni(L.sh.w, L.sl.w, R(0)), &sx, &sy, &sz);
+  const R epsp = L.p_eps;
+  const R sp = speed_of_energy<R, EXT>(C, epsp);
+  ChildState child;
+  child.r[0] = L.rx; child.r[1] = L.ry; child.r[2] = L.rz;
+  child.t = L.t;
+  child.v[0] = sp * sx; child.v[1] = sp * sy; child.v[2] = sp * sz;
+  child.id = (static_cast<uint64_t>(cw.x) | (static_cast<uint64_t>(cw.y) << 32)) | (1ull << 63);
+  child.k = L.k;
+  child.pad = 0;
+  child.eps_birth = static_cast<double>(epsp);
+  return child;
 }
 
 // Table layout 1: the instance's running-sum pairs (G x nc, node major) staged in LDS at
@@ -1575,8 +1589,7 @@ __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restr
       }
       if (L.state == ST_READY) {
         bool spawn;
-        ChildState child;
-        if (real_collision<R, HB, TR, false, EXT>(d, L, C, s_nu, &spawn, &child) == RC_STOP) L.state = ST_STOPPED;
+        if (real_collision<R, HB, TR, false, EXT>(d, L, C, s_nu, &spawn) == RC_STOP) L.state = ST_STOPPED;
       }
       // An electron that stopped leaves its final record (budget reached or block cap) or
       // its resumable state (end of the launch's quantum).
@@ -1808,9 +1821,8 @@ __global__ void __launch_bounds__(512) k_swarm_pooled(const InstanceDesc* __rest
           Lane<R> S;
           pool_take<R, HB, EXT>(P, s, S, C);
           bool spawn;
-          ChildState child;
           S.state = ST_ACTIVE;
-          if (real_collision<R, HB, false, false, EXT>(d, S, C, s_nu, &spawn, &child) == RC_STOP)
+          if (real_collision<R, HB, false, false, EXT>(d, S, C, s_nu, &spawn) == RC_STOP)
             S.state = ST_STOPPED;
           pool_give<R, EXT>(P, s, S);
         }
@@ -2011,9 +2023,8 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
     }
     if (ready != 0) {
       bool spawn = false;
-      ChildState child;
       if (L.state == ST_READY) {
-        if (real_collision<R, HB, TR, true, EXT>(d, L, C, s_nu, &spawn, &child) == RC_STOP) L.state = ST_STOPPED;
+        if (real_collision<R, HB, TR, true, EXT>(d, L, C, s_nu, &spawn) == RC_STOP) L.state = ST_STOPPED;
       }
       // append the secondaries of this wave: one reservation, ranks from the lane mask
       const uint64_t sm = __ballot(spawn);
@@ -2026,7 +2037,7 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
         base = __shfl(base, leader);
         if (spawn) {
           const int64_t s = static_cast<int64_t>(base + __popcll(sm & lane_lt));
-          if (s < child_cap) d.children[s] = child;
+          if (s < child_cap) d.children[s] = make_child<R, EXT>(L, C);
           else atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->dropped), 1ull);
         }
       }
