@@ -12,7 +12,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1901_08140_amd", "csrc")
 
-DRIVER = r"""
+HOST_PROGRAM = r"""
 #include <cstdio>
 #include <cstdint>
 #include <cmath>
@@ -65,10 +65,10 @@ int main() {
 
 
 @pytest.fixture(scope="module")
-def driver_output(tmp_path_factory):
+def host_output(tmp_path_factory):
     d = tmp_path_factory.mktemp("unit_log")
     src = d / "drv.cpp"
-    src.write_text(DRIVER)
+    src.write_text(HOST_PROGRAM)
     exe = d / "drv"
     cmd = ["hipcc", "-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-I", CSRC, str(src), "-o", str(exe)]
@@ -79,14 +79,14 @@ def driver_output(tmp_path_factory):
     return {ln.split()[0]: ln.split()[1:] for ln in out.stdout.splitlines()}
 
 
-def test_error_on_kernel_inputs_is_within_two_ulp(driver_output):
-    assert float(driver_output["random"][0]) <= 2.0, driver_output["random"]
+def test_error_on_kernel_inputs_is_within_two_ulp(host_output):
+    assert float(host_output["random"][0]) <= 2.0, host_output["random"]
 
 
-def test_error_on_edge_values_is_within_two_ulp(driver_output):
-    assert float(driver_output["edges"][0]) <= 2.0, driver_output["edges"]
+def test_error_on_edge_values_is_within_two_ulp(host_output):
+    assert float(host_output["edges"][0]) <= 2.0, host_output["edges"]
 
 
-def test_table_and_exact_zero(driver_output):
-    assert [float(v) for v in driver_output["entry0"]] == [1.0, 0.0]     # c_0 = 1: no table term
-    assert float.fromhex(driver_output["zero"][0]) == 0.0                 # ln 1 = 0 exactly
+def test_table_and_exact_zero(host_output):
+    assert [float(v) for v in host_output["entry0"]] == [1.0, 0.0]     # c_0 = 1: no table term
+    assert float.fromhex(host_output["zero"][0]) == 0.0                 # ln 1 = 0 exactly
