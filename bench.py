@@ -44,7 +44,7 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9      # 256 CUs x 64 FP32 lanes/clock x 2.4 GHz 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--electrons", type=int, default=100_000)
     ap.add_argument("--collisions", type=int, default=20_000)
@@ -438,6 +438,9 @@ def main():
         "trials_per_s": trials_per_step * args.steps / wall,
         "efficiency": real_per_step / trials_per_step,
         "device_ms_per_step": avg_ms,
+        "device_ms_median": sorted(dev_ms)[len(dev_ms) // 2] if len(dev_ms) % 2 else
+                            0.5 * (sorted(dev_ms)[len(dev_ms) // 2 - 1] + sorted(dev_ms)[len(dev_ms) // 2]),
+        "device_ms_steps": dev_ms,
         "roofline": {"bound": "alu", "achieved": achieved / 1e9, "peak": PEAK_LANE_OPS / 1e9, "unit": "Gop/s",
                      "frac": achieved / PEAK_LANE_OPS, "traffic": committed_traffic(),
                      "kernel": "k_swarm_dummy<float,false,false,0>",
