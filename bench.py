@@ -68,6 +68,8 @@ def parse():
                     help="skip the 256-instance batch leg")
     ap.add_argument("--serve-rate", type=float, default=5.0)
     ap.add_argument("--serve-seconds", type=float, default=8.0)
+    ap.add_argument("--serve-schedule", type=int, default=0,
+                    help="serving schedule: 0 every admitted request each epoch, 1 shortest remaining work first")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving leg (one JSON line), e.g. for a sweep of --serve-rate")
     ap.add_argument("--autotune", action="store_true",
@@ -165,7 +167,7 @@ def serve(sw, args):
             break
         arrivals.append(t)
     reqs = [synth.cfg5_request(i) for i in range(len(arrivals))]
-    srv = sw.swarm_server_create(200 << 30, sw.SWARM_FP32_MIXED)
+    srv = sw.swarm_server_create(200 << 30, sw.SWARM_FP32_MIXED, schedule=args.serve_schedule)
     try:
         t0 = sw.swarm_server_now(srv)
         tickets = []
@@ -188,6 +190,7 @@ def serve(sw, args):
                 "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
                 "served_real_per_s": real / (t_end - t0), "offered_real_per_s": offered,
                 "served_trials_per_s": trials / (t_end - t0), "efficiency": real / trials,
+                "schedule": "shortest remaining work first" if args.serve_schedule == 1 else "every admitted request",
                 "makespan_s": t_end - t0}
     finally:
         sw.swarm_server_destroy(srv)

@@ -324,6 +324,16 @@ swarm_status swarm_autotune(swarm_t* handles, const swarm_job* jobs, int32_t n,
 
 /* ---- Serving: continuous batching of arriving swarm requests ------------------------ */
 
+/* Which admitted requests an epoch advances. */
+typedef enum {
+  SWARM_SCHEDULE_ALL = 0,             /* every admitted request in every epoch */
+  SWARM_SCHEDULE_SHORTEST_FIRST = 1   /* the least remaining work (electrons x collisions left)
+                                         first, until the epoch holds about 10240 electrons per
+                                         compute unit, plus always the earliest admitted request
+                                         and the one with the most collisions per electron left:
+                                         lower median latency under overload, at some throughput */
+} swarm_schedule;
+
 typedef struct {
   int64_t hbm_budget_bytes;   /* admission limit on device memory held by requests */
   int32_t precision;          /* swarm_precision of every request */
@@ -331,6 +341,7 @@ typedef struct {
   int32_t max_active;         /* instances per epoch (0 = 1024) */
   swarm_launch_opts opts;
   void* stream;               /* hipStream_t or NULL */
+  int32_t schedule;           /* swarm_schedule (0 = every admitted request in every epoch) */
 } swarm_server_params;
 
 typedef struct {
@@ -344,8 +355,9 @@ typedef struct swarm_server* swarm_server_t;
 
 /* A server owns a scheduler thread.  Requests are admitted while the device memory they
  * need fits the budget; admitted requests keep their tables and electron state resident
- * and advance together: each epoch is one persistent launch over all admitted requests in
- * which every unfinished electron makes up to quantum_collisions more real collisions.
+ * and advance together: each epoch is one persistent launch over the admitted requests the
+ * schedule picks, in which every unfinished electron makes up to quantum_collisions more
+ * real collisions.
  * Requests that arrive while an epoch runs join the next one.  Because electrons stop at
  * real-collision boundaries and the random streams are counter based, a request's
  * result does not depend on what it was batched with. */

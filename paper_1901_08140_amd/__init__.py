@@ -25,6 +25,7 @@ SWARM_FP64, SWARM_FP32_MIXED = 0, 1
 SWARM_DUMMY, SWARM_REAL = 0, 1
 SWARM_TRIAL_CONSTANT, SWARM_TRIAL_VARIABLE, SWARM_TRIAL_BINNED = 0, 1, 2
 SWARM_SCATTER_ISOTROPIC, SWARM_SCATTER_SCREENED_COULOMB, SWARM_SCATTER_CONSTANT_XI = 0, 1, 2
+SWARM_SCHEDULE_ALL, SWARM_SCHEDULE_SHORTEST_FIRST = 0, 1
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1901_08140_amd/build.py`")
@@ -81,7 +82,7 @@ class swarm_launch_opts(ctypes.Structure):
 
 class swarm_server_params(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", _i64), ("precision", _i32), ("quantum_collisions", _i64),
-                ("max_active", _i32), ("opts", swarm_launch_opts), ("stream", _vp)]
+                ("max_active", _i32), ("opts", swarm_launch_opts), ("stream", _vp), ("schedule", _i32)]
 
 
 class swarm_request_info(ctypes.Structure):
@@ -359,10 +360,11 @@ def swarm_autotune(handles, jobs, probe_collisions):
 
 # ---- serving -------------------------------------------------------------------------
 def swarm_server_create(hbm_budget_bytes, precision=SWARM_FP32_MIXED, quantum_collisions=0, max_active=0,
-                        opts=None, stream=None):
+                        opts=None, stream=None, schedule=0):
     p = swarm_server_params()
     p.hbm_budget_bytes, p.precision = int(hbm_budget_bytes), int(precision)
     p.quantum_collisions, p.max_active = int(quantum_collisions), int(max_active)
+    p.schedule = int(schedule)
     p.opts = _opts(opts)
     p.stream = _stream_handle(stream)
     s = _vp()

@@ -54,6 +54,7 @@ struct Request {
   int slot = -1;
   int64_t bytes = 0;
   int64_t epochs = 0;
+  int64_t done_coll = 0;    // collisions per electron made so far (the epochs' quanta, capped)
   double submit_s = 0, admit_s = 0, done_s = 0;
   swarm_status status = SWARM_PENDING;
   swarm_tallies_t tallies{};
@@ -197,6 +198,38 @@ void admit_pending(swarm_server* s) {
   }
 }
 
+// Shortest remaining work first: the admitted requests with the fewest electron-collisions
+// left, until the epoch holds about kEpochElectronsPerCu electrons per compute unit (enough
+// to fill the device).  Two more always run: the earliest admitted request, so that no
+// request waits forever behind a stream of small ones, and the one with the most
+// collisions per electron left, the longest chain of sequential work, so that it does not
+// end up running alone on an underfilled device.  Results do not depend on the schedule;
+// only which requests finish first does.
+constexpr int64_t kEpochElectronsPerCu = 10240;
+
+std::vector<std::shared_ptr<Request>> pick_shortest_first(const std::vector<std::shared_ptr<Request>>& active) {
+  const int64_t target = kEpochElectronsPerCu * device_info().n_cu;
+  auto left = [](const std::shared_ptr<Request>& r) { return r->n_e * (r->n_c - r->done_coll); };
+  auto chain = [](const std::shared_ptr<Request>& r) { return r->n_c - r->done_coll; };
+  std::vector<std::shared_ptr<Request>> out{active.front()};
+  const auto longest = std::max_element(active.begin(), active.end(),
+      [&](const std::shared_ptr<Request>& a, const std::shared_ptr<Request>& b) { return chain(a) < chain(b); });
+  if (*longest != active.front()) out.push_back(*longest);
+  int64_t electrons = 0;
+  for (auto& r : out) electrons += r->n_e;
+  std::vector<std::shared_ptr<Request>> rest;
+  for (auto& r : active)
+    if (std::find(out.begin(), out.end(), r) == out.end()) rest.push_back(r);
+  std::stable_sort(rest.begin(), rest.end(),
+                   [&](const std::shared_ptr<Request>& a, const std::shared_ptr<Request>& b) { return left(a) < left(b); });
+  for (auto& r : rest) {
+    if (electrons >= target) break;
+    out.push_back(r);
+    electrons += r->n_e;
+  }
+  return out;
+}
+
 void scheduler(swarm_server* s) {
   std::vector<InstanceDesc> descs;
   std::vector<WorkItem> items;
@@ -216,6 +249,7 @@ void scheduler(swarm_server* s) {
       act = s->active;
     }
     if (act.empty()) continue;
+    if (s->p.schedule == SWARM_SCHEDULE_SHORTEST_FIRST && act.size() > 1) act = pick_shortest_first(act);
     // epoch quantum: fixed, or sized so that an epoch lasts about 50 ms at the measured rate
     int64_t electrons = 0, max_nc = 0;
     for (auto& r : act) { electrons += r->n_e; max_nc = std::max(max_nc, r->n_c); }
@@ -291,6 +325,7 @@ void scheduler(swarm_server* s) {
         fin_desc.push_back(descs[i]);
       }
     }
+    for (auto& r : act) r->done_coll = std::min<int64_t>(r->n_c, r->done_coll + q);
     if (ms > 0) {
       const double r_now = static_cast<double>(work) / (ms * 1e-3);
       s->rate = s->rate > 0 ? 0.5 * s->rate + 0.5 * r_now : r_now;
@@ -329,6 +364,8 @@ swarm_status swarm_server_create(const swarm_server_params* p, swarm_server_t* o
   if (p->hbm_budget_bytes <= 0) return fail(SWARM_ERR_INVALID_ARG, "hbm budget must be > 0");
   if (p->precision != SWARM_FP64 && p->precision != SWARM_FP32_MIXED) return fail(SWARM_ERR_INVALID_ARG, "bad precision");
   if (p->quantum_collisions < 0) return fail(SWARM_ERR_INVALID_ARG, "quantum must be >= 0");
+  if (p->schedule != SWARM_SCHEDULE_ALL && p->schedule != SWARM_SCHEDULE_SHORTEST_FIRST)
+    return fail(SWARM_ERR_INVALID_ARG, "schedule must be SWARM_SCHEDULE_ALL or SWARM_SCHEDULE_SHORTEST_FIRST");
   auto s = std::make_unique<swarm_server>();
   s->p = *p;
   s->t0 = std::chrono::steady_clock::now();

@@ -1,5 +1,6 @@
 """Serving: requests admitted by HBM budget and advanced together in epochs give the same
-bits as the same request run alone."""
+bits as the same request run alone, under either schedule (every admitted request in every
+epoch, or shortest remaining work first)."""
 import time
 
 import numpy as np
@@ -33,8 +34,9 @@ def _wait_all(sw, srv, tickets, timeout=120):
     return out
 
 
+@pytest.mark.parametrize("schedule", [0, 1], ids=["all", "shortest-first"])
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32"])
-def test_alone_equals_in_the_mix(gpu, precision):
+def test_alone_equals_in_the_mix(gpu, precision, schedule):
     sw = gpu
     reqs = [_shrink(c) for c in _requests(8)]
     # alone: each request through its own single run
@@ -44,7 +46,7 @@ def test_alone_equals_in_the_mix(gpu, precision):
         s.run(c.n_electrons, c.n_collisions, c.seed)
         alone.append(s.tallies())
     # in the mix: all submitted together to a server with small epochs
-    srv = sw.swarm_server_create(64 << 30, precision, quantum_collisions=300)
+    srv = sw.swarm_server_create(64 << 30, precision, quantum_collisions=300, schedule=schedule)
     try:
         tickets = [sw.swarm_server_submit(srv, c.components, sw.params_from_config(c, precision),
                                           c.n_electrons, c.n_collisions, c.seed) for c in reqs]
@@ -72,3 +74,9 @@ def test_budget_admission_queues_requests(gpu):
             assert res[t][0]["n_real"] == c.n_electrons * c.n_collisions
     finally:
         sw.swarm_server_destroy(srv)
+
+
+def test_invalid_schedule_refused(gpu):
+    sw = gpu
+    with pytest.raises(sw.SwarmError):
+        sw.swarm_server_create(1 << 30, sw.SWARM_FP32_MIXED, schedule=2)
