@@ -21,9 +21,10 @@
 // scattering: quadrature of the sampled cos(theta) against sigma_mt/sigma_el and the
 // screened-Coulomb closed form, rotation geometry, the Maxwell drift eE/(m nu (1-<cos>)).
 // The diffusion magnitudes (sigma, sigma_L, sigma_T) are pinned against an independent
-// random walk of the field-free process and its Gaussian limit.  Parity unpinned by a closed
-// form: tallies for the synthetic argon/CO2 tables at non-trivial fields, and the fail
-// sequences of the variable trial frequency; those rest on GPU-vs-oracle parity.
+// random walk of the field-free process and its Gaussian limit.  The fail sequences of the
+// variable and binned trial frequencies are pinned by plain-Python runs of the strategies'
+// steps on the oracle's primitives.  Parity unpinned by a closed form: tallies for the
+// synthetic argon/CO2 tables at non-trivial fields; those rest on GPU-vs-oracle parity.
 
 #include <algorithm>
 #include <atomic>
