@@ -8,6 +8,12 @@ positive W).  The completed set F holds the electrons that made all their real c
 Each tally is returned as (value, stat_sigma, spread): `spread` is the sample standard
 deviation of the per-electron quantity (the paper's printed "+-"), `stat_sigma` = spread /
 sqrt(N_F), the statistical uncertainty of the mean.
+
+Pins (tests/test_oracle_swarm.py, tests/test_oracle_estimators.py): W against eE/(m nu) and
+the Drude drift; the mean energies against their closed form; D, D_L, D_T field-free and
+along/across B against closed forms and an independent helical random walk; sigma, sigma_L,
+sigma_T against a random walk; the vector form's removal of a uniform drift, exactly, on
+hand-built records; alpha, eta (per-electron and ratio-of-sums forms) against constant rates.
 """
 from __future__ import annotations
 
