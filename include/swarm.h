@@ -216,6 +216,12 @@ typedef struct {
   int64_t n_real, n_null, n_forbidden, n_fail, n_over;
   int64_t n_electrons, n_finished, n_attached, n_stuck, n_created;
   int64_t n_ionizations, n_attachments, n_dropped;
+  int64_t n_retry_failed;  /* electrons whose binned-strategy retry failed again (flag 16) */
+  int32_t exact;           /* 1: constant trial frequency, the method is exact; 0: the variable
+                              or binned trial frequency ran: its return to the last real
+                              collision after a fail favours flights that gained no energy, so
+                              the tallies carry a bias besides their statistical error */
+  int32_t trial_strategy;  /* swarm_trial_strategy of the run */
 } swarm_tallies_t;
 
 typedef struct swarm* swarm_t;
@@ -237,6 +243,39 @@ swarm_status swarm_create(const swarm_component* comps, int32_t n_comps,
  * started with flag 8 as they were created, and the tallies cover the finished ones.
  * Previous results of the handle are replaced. */
 swarm_status swarm_run(swarm_t h, int64_t n_electrons, int64_t n_collisions, uint64_t seed);
+
+/* The run of swarm_run, started without waiting for it.  DUMMY mode enqueues all its device
+ * work on the handle's stream (work items, the swarm kernel, the tally reductions) and
+ * returns; REAL mode runs its generations on a worker thread the handle owns, since each
+ * generation's launch depends on the counters of the one before.  Errors found before the
+ * work starts (arguments, allocation) are returned here; the run's own status (e.g.
+ * SWARM_ERR_CAPACITY) comes from swarm_wait.  Until swarm_wait returns, every other call on
+ * the handle except swarm_destroy (which waits) returns SWARM_ERR_STATE, and the stream
+ * carries the run: work the caller adds to it afterwards runs after the run's.  The
+ * handle's records and device memory are in use until then; distinct handles on distinct
+ * streams overlap on the device. */
+swarm_status swarm_run_async(swarm_t h, int64_t n_electrons, int64_t n_collisions, uint64_t seed);
+
+/* Wait for the run started by swarm_run_async; returns its status, as swarm_run would have.
+ * Afterwards swarm_tallies, swarm_records and swarm_last_timing give its results.
+ * SWARM_ERR_STATE if no run is in flight. */
+swarm_status swarm_wait(swarm_t h);
+
+/* swarm_create with every device allocation of the handle (tables, records, secondary
+ * queue, work items, tally buffers, trace buffers) taken from one region the caller owns:
+ * `arena` is a device pointer to arena_bytes bytes (e.g. a torch tensor's data_ptr) that
+ * must stay valid until swarm_destroy.  The library sub-allocates it (first fit, 256-byte
+ * blocks) and never frees it.  A run that does not fit returns SWARM_ERR_OUT_OF_MEMORY;
+ * swarm_arena_bytes gives a size that holds the tables and runs of up to n_electrons. */
+swarm_status swarm_create_in_arena(const swarm_component* comps, int32_t n_comps,
+                                   const swarm_params* params, void* arena, int64_t arena_bytes,
+                                   swarm_t* out);
+
+/* Device bytes a handle of these inputs needs for its tables plus one run of n_electrons
+ * primaries (REAL mode: params.capacity electrons, 0 = 64 n_electrons) without tracing.
+ * Validates the inputs like swarm_create; allocates nothing. */
+swarm_status swarm_arena_bytes(const swarm_component* comps, int32_t n_comps, const swarm_params* params,
+                               int64_t n_electrons, int64_t* bytes);
 
 /* Tallies of the last run (computed by deterministic fixed-order device reductions). */
 swarm_status swarm_tallies(swarm_t h, swarm_tallies_t* out);
@@ -353,6 +392,9 @@ typedef struct {
 
 typedef struct swarm_server* swarm_server_t;
 
+/* Tests of the error path only: when the environment variable SWARM_SERVER_FAIL_EPOCH is k
+ * >= 1 at swarm_server_create, the server's k-th epoch reports a device failure without
+ * launching anything, which fails every admitted request with SWARM_ERR_DEVICE. */
 /* A server owns a scheduler thread.  Requests are admitted while the device memory they
  * need fits the budget; admitted requests keep their tables and electron state resident
  * and advance together: each epoch is one persistent launch over the admitted requests the
@@ -362,10 +404,24 @@ typedef struct swarm_server* swarm_server_t;
  * real-collision boundaries and the random streams are counter based, a request's
  * result does not depend on what it was batched with. */
 swarm_status swarm_server_create(const swarm_server_params* p, swarm_server_t* out);
+/* A server whose device memory (every request's tables, electron state and records, and
+ * the epochs' buffers) comes from one region the caller owns (a device pointer to
+ * arena_bytes bytes, valid until swarm_server_destroy returns).  The admission limit is the
+ * smaller of hbm_budget_bytes and the region; a request that fits the budget but not the
+ * region's free blocks waits until an admitted request finishes. */
+swarm_status swarm_server_create_in_arena(const swarm_server_params* p, void* arena, int64_t arena_bytes,
+                                          swarm_server_t* out);
 /* Queue a request (inputs copied); *ticket identifies it.  DUMMY mode only. */
 swarm_status swarm_server_submit(swarm_server_t s, const swarm_component* comps, int32_t n_comps,
                                  const swarm_params* params, int64_t n_electrons,
                                  int64_t n_collisions, uint64_t seed, int64_t* ticket);
+/* swarm_server_submit that also returns the request's per-electron records: records_out is
+ * host memory for n_electrons swarm_record entries (ids 0..n-1 in id order), written before
+ * the request is reported finished; the caller keeps it valid until then. */
+swarm_status swarm_server_submit_records(swarm_server_t s, const swarm_component* comps, int32_t n_comps,
+                                         const swarm_params* params, int64_t n_electrons,
+                                         int64_t n_collisions, uint64_t seed, swarm_record* records_out,
+                                         int64_t* ticket);
 /* SWARM_OK with the tallies once finished, SWARM_PENDING before; info may be NULL. */
 swarm_status swarm_server_poll(swarm_server_t s, int64_t ticket, swarm_tallies_t* out,
                                swarm_request_info* info);
@@ -373,6 +429,9 @@ swarm_status swarm_server_poll(swarm_server_t s, int64_t ticket, swarm_tallies_t
 swarm_status swarm_server_drain(swarm_server_t s);
 /* Seconds on the server clock (the clock of swarm_request_info). */
 double swarm_server_now(swarm_server_t s);
+/* Stop the server: the running epoch ends, every request that has not finished is
+ * cancelled (it would poll SWARM_ERR_STATE) and its memory released, the scheduler thread
+ * is joined.  Call swarm_server_drain first to wait for the results instead. */
 void swarm_server_destroy(swarm_server_t s);
 
 #ifdef __cplusplus

@@ -68,7 +68,8 @@ _COUNT_NAMES = ["n_real", "n_null", "n_forbidden", "n_fail", "n_over", "n_electr
 class swarm_tallies_t(ctypes.Structure):
     _fields_ = ([(n, swarm_stat) for n in _STAT_NAMES] +
                 [("alpha_rate", _d), ("eta_rate", _d), ("efficiency", _d), ("majorant", _d)] +
-                [(n, _i64) for n in _COUNT_NAMES])
+                [(n, _i64) for n in _COUNT_NAMES] +
+                [("n_retry_failed", _i64), ("exact", _i32), ("trial_strategy", _i32)])
 
 
 class swarm_job(ctypes.Structure):
@@ -108,6 +109,10 @@ EVENT_DTYPE = np.dtype({
 _SIGS = {
     "swarm_create": (_i32, [_P(swarm_component), _i32, _P(swarm_params), _P(_vp)]),
     "swarm_run": (_i32, [_vp, _i64, _i64, _u64]),
+    "swarm_run_async": (_i32, [_vp, _i64, _i64, _u64]),
+    "swarm_wait": (_i32, [_vp]),
+    "swarm_create_in_arena": (_i32, [_P(swarm_component), _i32, _P(swarm_params), _vp, _i64, _P(_vp)]),
+    "swarm_arena_bytes": (_i32, [_P(swarm_component), _i32, _P(swarm_params), _i64, _P(_i64)]),
     "swarm_set_launch_opts": (_i32, [_vp, _P(swarm_launch_opts)]),
     "swarm_tallies": (_i32, [_vp, _P(swarm_tallies_t)]),
     "swarm_records": (_i32, [_vp, _vp, _i64, _P(_i64)]),
@@ -126,8 +131,11 @@ _SIGS = {
     "swarm_batch_run": (_i32, [_P(_vp), _P(swarm_job), _i32, _P(swarm_launch_opts)]),
     "swarm_autotune": (_i32, [_P(_vp), _P(swarm_job), _i32, _i64, _P(swarm_launch_opts)]),
     "swarm_server_create": (_i32, [_P(swarm_server_params), _P(_vp)]),
+    "swarm_server_create_in_arena": (_i32, [_P(swarm_server_params), _vp, _i64, _P(_vp)]),
     "swarm_server_submit": (_i32, [_vp, _P(swarm_component), _i32, _P(swarm_params), _i64, _i64, _u64,
                                    _P(_i64)]),
+    "swarm_server_submit_records": (_i32, [_vp, _P(swarm_component), _i32, _P(swarm_params), _i64, _i64, _u64,
+                                           _vp, _P(_i64)]),
     "swarm_server_poll": (_i32, [_vp, _i64, _P(swarm_tallies_t), _P(swarm_request_info)]),
     "swarm_server_drain": (_i32, [_vp]),
     "swarm_server_now": (_d, [_vp]),
@@ -223,6 +231,22 @@ def swarm_create(components, params):
     return h
 
 
+def swarm_create_in_arena(components, params, arena_ptr, arena_bytes):
+    """arena_ptr: device address (int) of arena_bytes bytes the caller keeps alive."""
+    m = _Marshalled(components)
+    h = _vp()
+    _check(_lib.swarm_create_in_arena(m.comps, len(components), ctypes.byref(params), _vp(int(arena_ptr)),
+                                      int(arena_bytes), ctypes.byref(h)))
+    return h
+
+
+def swarm_arena_bytes(components, params, n_electrons):
+    m = _Marshalled(components)
+    n = _i64(0)
+    _check(_lib.swarm_arena_bytes(m.comps, len(components), ctypes.byref(params), int(n_electrons), ctypes.byref(n)))
+    return n.value
+
+
 def swarm_set_launch_opts(h, opts):
     return _check(_lib.swarm_set_launch_opts(h, ctypes.byref(_opts(opts))))
 
@@ -232,11 +256,20 @@ def swarm_run(h, n_electrons, n_collisions, seed):
     return _check(_lib.swarm_run(h, int(n_electrons), int(n_collisions), int(seed)))
 
 
+def swarm_run_async(h, n_electrons, n_collisions, seed):
+    return _check(_lib.swarm_run_async(h, int(n_electrons), int(n_collisions), int(seed)))
+
+
+def swarm_wait(h):
+    """The run's status (raises SwarmError like swarm_run)."""
+    return _check(_lib.swarm_wait(h))
+
+
 def tallies_to_dict(t):
     out = {n: (getattr(t, n).value, getattr(t, n).stat_sigma, getattr(t, n).spread) for n in _STAT_NAMES}
     for n in ("alpha_rate", "eta_rate", "efficiency", "majorant"):
         out[n] = getattr(t, n)
-    for n in _COUNT_NAMES:
+    for n in _COUNT_NAMES + ["n_retry_failed", "exact", "trial_strategy"]:
         out[n] = int(getattr(t, n))
     return out
 
@@ -372,12 +405,36 @@ def swarm_server_create(hbm_budget_bytes, precision=SWARM_FP32_MIXED, quantum_co
     return s
 
 
+def swarm_server_create_in_arena(arena_ptr, arena_bytes, hbm_budget_bytes=None, precision=SWARM_FP32_MIXED,
+                                 quantum_collisions=0, max_active=0, opts=None, stream=None, schedule=0):
+    p = swarm_server_params()
+    p.hbm_budget_bytes = int(hbm_budget_bytes if hbm_budget_bytes is not None else arena_bytes)
+    p.precision = int(precision)
+    p.quantum_collisions, p.max_active = int(quantum_collisions), int(max_active)
+    p.schedule = int(schedule)
+    p.opts = _opts(opts)
+    p.stream = _stream_handle(stream)
+    s = _vp()
+    _check(_lib.swarm_server_create_in_arena(ctypes.byref(p), _vp(int(arena_ptr)), int(arena_bytes), ctypes.byref(s)))
+    return s
+
+
 def swarm_server_submit(s, components, params, n_electrons, n_collisions, seed):
     m = _Marshalled(components)
     t = _i64(0)
     _check(_lib.swarm_server_submit(s, m.comps, len(components), ctypes.byref(params), int(n_electrons),
                                     int(n_collisions), int(seed), ctypes.byref(t)))
     return t.value
+
+
+def swarm_server_submit_records(s, components, params, n_electrons, n_collisions, seed):
+    """(ticket, records array): the array is filled when the request finishes; keep it alive."""
+    m = _Marshalled(components)
+    rec = np.zeros(int(n_electrons), dtype=RECORD_DTYPE)
+    t = _i64(0)
+    _check(_lib.swarm_server_submit_records(s, m.comps, len(components), ctypes.byref(params), int(n_electrons),
+                                            int(n_collisions), int(seed), rec.ctypes.data_as(_vp), ctypes.byref(t)))
+    return t.value, rec
 
 
 def swarm_server_poll(s, ticket):
@@ -408,15 +465,23 @@ def swarm_server_destroy(s):
 class Swarm:
     """Owning wrapper of a swarm handle: Swarm(config, precision).run(n_e, n_c, seed)."""
 
-    def __init__(self, components, params):
-        self.h = swarm_create(components, params)
+    def __init__(self, components, params, arena=None):
+        """arena: optional (device address, bytes) the handle takes all its device memory from."""
+        self.h = swarm_create(components, params) if arena is None else swarm_create_in_arena(components, params,
+                                                                                               *arena)
 
     @classmethod
-    def from_config(cls, cfg, precision=SWARM_FP64, **kw):
-        return cls(cfg.components, params_from_config(cfg, precision, **kw))
+    def from_config(cls, cfg, precision=SWARM_FP64, arena=None, **kw):
+        return cls(cfg.components, params_from_config(cfg, precision, **kw), arena)
 
     def run(self, n_electrons, n_collisions, seed):
         return swarm_run(self.h, n_electrons, n_collisions, seed)
+
+    def run_async(self, n_electrons, n_collisions, seed):
+        return swarm_run_async(self.h, n_electrons, n_collisions, seed)
+
+    def wait(self):
+        return swarm_wait(self.h)
 
     def set_launch_opts(self, opts):
         return swarm_set_launch_opts(self.h, opts)

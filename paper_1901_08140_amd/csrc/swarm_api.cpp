@@ -80,9 +80,66 @@ LdsLayout lds_layout(int precision, int G, int nc, int service_waves, int table_
   return l;
 }
 
+constexpr size_t kArenaAlign = 256;
+
+Arena::Arena(void* base, size_t bytes) {
+  const uintptr_t b = reinterpret_cast<uintptr_t>(base);
+  const uintptr_t a = (b + kArenaAlign - 1) & ~static_cast<uintptr_t>(kArenaAlign - 1);
+  const size_t lost = static_cast<size_t>(a - b);
+  base_ = reinterpret_cast<char*>(a);
+  bytes_ = bytes > lost ? ((bytes - lost) & ~(kArenaAlign - 1)) : 0;
+  if (bytes_ > 0) free_[0] = bytes_;
+}
+
+void* Arena::alloc(size_t n) {
+  const size_t want = std::max(kArenaAlign, (n + kArenaAlign - 1) & ~(kArenaAlign - 1));
+  std::lock_guard<std::mutex> lk(mu_);
+  for (auto it = free_.begin(); it != free_.end(); ++it) {
+    if (it->second < want) continue;
+    const size_t off = it->first, size = it->second;
+    free_.erase(it);
+    if (size > want) free_[off + want] = size - want;
+    used_[off] = want;
+    in_use_ += want;
+    return base_ + off;
+  }
+  return nullptr;
+}
+
+void Arena::release(void* p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(mu_);
+  auto u = used_.find(static_cast<size_t>(static_cast<char*>(p) - base_));
+  if (u == used_.end()) return;
+  size_t off = u->first, size = u->second;
+  used_.erase(u);
+  in_use_ -= size;
+  auto next = free_.lower_bound(off);
+  if (next != free_.end() && off + size == next->first) {   // merge with the block after
+    size += next->second;
+    next = free_.erase(next);
+  }
+  if (next != free_.begin()) {                               // and with the block before
+    auto prev = std::prev(next);
+    if (prev->first + prev->second == off) {
+      prev->second += size;
+      return;
+    }
+  }
+  free_[off] = size;
+}
+
+size_t Arena::in_use() const {
+  std::lock_guard<std::mutex> lk(mu_);
+  return in_use_;
+}
+
 DevBuf::~DevBuf() { reset(); }
 void DevBuf::reset() {
-  if (p) (void)hipFree(p);
+  if (p) {
+    if (arena) arena->release(p);
+    else (void)hipFree(p);
+  }
   p = nullptr;
   bytes = 0;
 }
@@ -90,13 +147,26 @@ hipError_t DevBuf::ensure(size_t n) {
   if (n <= bytes && p) return hipSuccess;
   reset();
   if (n == 0) return hipSuccess;
-  hipError_t e = hipMalloc(&p, n);
-  if (e != hipSuccess) {
-    p = nullptr;
-    return e;
+  if (arena) {
+    p = arena->alloc(n);
+    if (!p) return hipErrorOutOfMemory;
+  } else {
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
   }
   bytes = n;
   return hipSuccess;
+}
+
+size_t tally_bytes(int64_t n_records) {
+  auto blk = [](size_t n) { return std::max(kArenaAlign, (n + kArenaAlign - 1) & ~(kArenaAlign - 1)); };
+  const size_t tiles = static_cast<size_t>(std::max<int64_t>(1, (n_records + kTallyTile - 1) / kTallyTile));
+  return blk(tiles * sizeof(TallyTile)) + blk(sizeof(int32_t)) + blk(sizeof(int64_t)) +
+         blk(tiles * kTally1 * sizeof(double)) + blk(tiles * kTally2 * sizeof(double)) +
+         blk((kTally1 + kTally2) * sizeof(double)) + blk(sizeof(swarm_tallies_t));
 }
 
 }  // namespace swarm_impl
@@ -125,6 +195,10 @@ void decade_bins(int P, int emin, int G, int b, std::vector<int32_t>& entry_bin,
   first.assign(nb + 1, G + 1);
   for (int i = G; i >= 0; --i) first[entry_bin[i]] = i;
   for (int k = nb - 1; k >= 0; --k) first[k] = std::min(first[k], first[k + 1]);
+}
+
+swarm_status busy() {
+  return fail(SWARM_ERR_STATE, "a run started by swarm_run_async is in flight: call swarm_wait first");
 }
 
 swarm_status validate(const swarm_component* comps, int32_t n_comps, const swarm_params* p) {
@@ -321,41 +395,15 @@ swarm_launch_opts resolve_opts(const swarm_launch_opts* o, int precision) {
 // =======================================================================================
 // Single-instance API
 // =======================================================================================
-extern "C" {
+namespace swarm_impl {
 
-const char* swarm_strerror(swarm_status s) {
-  switch (s) {
-    case SWARM_OK: return "ok";
-    case SWARM_ERR_INVALID_ARG: return "invalid argument";
-    case SWARM_ERR_OUT_OF_MEMORY: return "out of memory";
-    case SWARM_ERR_CAPACITY: return "capacity exceeded";
-    case SWARM_ERR_DEVICE: return "device error";
-    case SWARM_ERR_STATE: return "invalid state";
-    case SWARM_PENDING: return "pending";
-  }
-  return "unknown status";
-}
-
-const char* swarm_last_error(void) { return g_last_error.c_str(); }
-
-swarm_status swarm_create(const swarm_component* comps, int32_t n_comps, const swarm_params* params,
-                          swarm_t* out) {
-  if (!out) return fail(SWARM_ERR_INVALID_ARG, "out is NULL");
-  *out = nullptr;
+// Validation, table build and constants of a new handle.  With bytes_only set, only the
+// device bytes the handle's tables need are computed (nothing is allocated or launched).
+static swarm_status build_swarm(swarm* h, const swarm_component* comps, int32_t n_comps,
+                                const swarm_params* params, size_t* bytes_only) {
   swarm_status st = validate(comps, n_comps, params);
   if (st != SWARM_OK) return st;
-  auto h = std::make_unique<swarm>();
   h->params = *params;
-  if (params->stream) {
-    h->stream = static_cast<hipStream_t>(params->stream);
-    h->own_stream = false;
-  } else {
-    hipError_t e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
-    h->own_stream = true;
-  }
-  DeviceInfo& dev = device_info();
-  (void)dev;
   // Flatten the raw tables (argument marshalling only).
   std::vector<double> e_all, s_all, thr, mass, frac, ratio;
   std::vector<int32_t> off, npt, kind, comp, scat;
@@ -413,6 +461,18 @@ swarm_status swarm_create(const swarm_component* comps, int32_t n_comps, const s
   const size_t b_lt = al(logtab.size() * 8);
   const size_t total = b_e + b_s + 4 * b_i + b_cd + 4 * b_k + b_nodes + b_cm + b_nu64 + b_nu32 + b_c64 + b_c32 + b_ch +
                        b_th + b_eb + b_bf + b_bn + b_bn32 + b_lt + al(sizeof(InstanceDesc)) + al(sizeof(RunCounters));
+  if (bytes_only) {
+    *bytes_only = total;
+    return SWARM_OK;
+  }
+  if (params->stream) {
+    h->stream = static_cast<hipStream_t>(params->stream);
+    h->own_stream = false;
+  } else {
+    hipError_t es = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+    if (es != hipSuccess) return hip_fail(es, "hipStreamCreate");
+    h->own_stream = true;
+  }
   hipError_t e = h->arena.ensure(total);
   if (e != hipSuccess) return hip_fail(e, "allocating instance tables");
   char* base = static_cast<char*>(h->arena.p);
@@ -459,7 +519,7 @@ swarm_status swarm_create(const swarm_component* comps, int32_t n_comps, const s
 #undef CP
   if ((e = launch_fill_u64(reinterpret_cast<uint64_t*>(d.ctr), 0, sizeof(RunCounters) / 8, s)) != hipSuccess)
     return hip_fail(e, "clearing counters");
-  if ((e = sync_desc_to_device(h.get())) != hipSuccess) return hip_fail(e, "copying descriptor");
+  if ((e = sync_desc_to_device(h)) != hipSuccess) return hip_fail(e, "copying descriptor");
   if ((e = launch_build(h->d_desc, d, s)) != hipSuccess) return hip_fail(e, "table build launch");
   if ((e = hipMemcpyAsync(&h->desc, h->d_desc, sizeof(InstanceDesc), hipMemcpyDeviceToHost, s)) != hipSuccess)
     return hip_fail(e, "reading descriptor");
@@ -473,12 +533,92 @@ swarm_status swarm_create(const swarm_component* comps, int32_t n_comps, const s
   for (int i = 0; i < 3; ++i)
     if ((e = hipEventCreate(&h->ev[i])) != hipSuccess) return hip_fail(e, "hipEventCreate");
   h->opts = resolve_opts(nullptr, params->precision);
+  return SWARM_OK;
+}
+
+swarm_status create_swarm(const swarm_component* comps, int32_t n_comps, const swarm_params* params,
+                          Arena* mem, swarm_t* out) {
+  if (!out) return fail(SWARM_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  auto h = std::make_unique<swarm>();
+  if (mem) h->bind_arena(mem);
+  const swarm_status st = build_swarm(h.get(), comps, n_comps, params, nullptr);
+  if (st != SWARM_OK) {
+    const std::string msg = g_last_error;
+    swarm_destroy(h.release());
+    g_last_error = msg;
+    return st;
+  }
   *out = h.release();
+  return SWARM_OK;
+}
+
+size_t create_bytes(const swarm_component* comps, int32_t n_comps, const swarm_params* params) {
+  swarm h;
+  size_t bytes = 0;
+  if (build_swarm(&h, comps, n_comps, params, &bytes) != SWARM_OK) return 0;
+  return bytes;
+}
+
+}  // namespace swarm_impl
+
+extern "C" {
+
+const char* swarm_strerror(swarm_status s) {
+  switch (s) {
+    case SWARM_OK: return "ok";
+    case SWARM_ERR_INVALID_ARG: return "invalid argument";
+    case SWARM_ERR_OUT_OF_MEMORY: return "out of memory";
+    case SWARM_ERR_CAPACITY: return "capacity exceeded";
+    case SWARM_ERR_DEVICE: return "device error";
+    case SWARM_ERR_STATE: return "invalid state";
+    case SWARM_PENDING: return "pending";
+  }
+  return "unknown status";
+}
+
+const char* swarm_last_error(void) { return g_last_error.c_str(); }
+
+swarm_status swarm_create(const swarm_component* comps, int32_t n_comps, const swarm_params* params,
+                          swarm_t* out) {
+  return create_swarm(comps, n_comps, params, nullptr, out);
+}
+
+swarm_status swarm_create_in_arena(const swarm_component* comps, int32_t n_comps, const swarm_params* params,
+                                   void* arena, int64_t arena_bytes, swarm_t* out) {
+  if (!out) return fail(SWARM_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!arena || arena_bytes <= 0) return fail(SWARM_ERR_INVALID_ARG, "arena must be a device pointer with bytes > 0");
+  auto mem = std::make_unique<Arena>(arena, static_cast<size_t>(arena_bytes));
+  swarm_t h = nullptr;
+  const swarm_status st = create_swarm(comps, n_comps, params, mem.get(), &h);
+  if (st != SWARM_OK) return st;
+  h->own_mem = std::move(mem);
+  *out = h;
+  return SWARM_OK;
+}
+
+swarm_status swarm_arena_bytes(const swarm_component* comps, int32_t n_comps, const swarm_params* params,
+                               int64_t n_electrons, int64_t* bytes) {
+  if (!bytes) return fail(SWARM_ERR_INVALID_ARG, "bytes is NULL");
+  *bytes = 0;
+  if (n_electrons < 1) return fail(SWARM_ERR_INVALID_ARG, "n_electrons must be >= 1");
+  const size_t tables = create_bytes(comps, n_comps, params);
+  if (tables == 0) return SWARM_ERR_INVALID_ARG;     // validation failed; the message is set
+  auto blk = [](size_t n) { return (n + 2 * 256 - 1) & ~static_cast<size_t>(255); };   // block + alignment
+  const bool real = params->secondaries == SWARM_REAL;
+  const int64_t capacity = real ? (params->capacity ? params->capacity : 64 * n_electrons) : n_electrons;
+  size_t run = blk(static_cast<size_t>(capacity) * sizeof(swarm_record)) + tally_bytes(capacity);
+  if (real && capacity > n_electrons) run += blk(static_cast<size_t>(capacity - n_electrons) * sizeof(ChildState));
+  // dummy-mode work items: at most one per 64 electrons (the smallest work-group), plus the counter
+  if (!real) run += blk(static_cast<size_t>((n_electrons + 63) / 64) * sizeof(WorkItem) + 256);
+  *bytes = static_cast<int64_t>(blk(tables) + run);
   return SWARM_OK;
 }
 
 void swarm_destroy(swarm_t h) {
   if (!h) return;
+  if (h->worker.joinable()) h->worker.join();
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   for (int i = 0; i < 3; ++i)
     if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
@@ -488,6 +628,7 @@ void swarm_destroy(swarm_t h) {
 
 swarm_status swarm_set_trace(swarm_t h, const uint64_t* ids, int32_t n_ids, int32_t max_events) {
   if (!h) return fail(SWARM_ERR_INVALID_ARG, "handle is NULL");
+  if (h->in_flight) return busy();
   if (n_ids < 0 || n_ids > kMaxTraceIds) return fail(SWARM_ERR_INVALID_ARG, "n_ids must be in [0, %d]", kMaxTraceIds);
   if (n_ids > 0 && (!ids || max_events <= 0 || max_events > 4096))
     return fail(SWARM_ERR_INVALID_ARG, "max_events must be in [1, 4096]");
@@ -507,15 +648,27 @@ swarm_status swarm_set_trace(swarm_t h, const uint64_t* ids, int32_t n_ids, int3
 
 swarm_status swarm_set_launch_opts(swarm_t h, const swarm_launch_opts* opts) {
   if (!h) return fail(SWARM_ERR_INVALID_ARG, "NULL handle");
+  if (h->in_flight) return busy();
   h->opts = resolve_opts(opts, h->desc.precision);
   return SWARM_OK;
 }
 
-swarm_status swarm_run(swarm_t h, int64_t n_electrons, int64_t n_collisions, uint64_t seed) {
-  if (!h) return fail(SWARM_ERR_INVALID_ARG, "handle is NULL");
+}  // extern "C"
+
+namespace {
+
+// A run up to the point where everything is on the stream: records, counters, the swarm
+// kernel (dummy mode: one launch; real mode: the generations, which need the host between
+// launches and therefore wait for each), then the tally reductions.  Nothing waits for the
+// dummy-mode work, so swarm_run_async returns while it runs.  A capacity overflow is kept
+// in run_status: its tallies are still reduced.
+swarm_status run_start(swarm_t h, int64_t n_electrons, int64_t n_collisions, uint64_t seed) {
   if (n_electrons < 1) return fail(SWARM_ERR_INVALID_ARG, "n_electrons must be >= 1");
   if (n_collisions < 1 || n_collisions > 0xffffffffLL)
     return fail(SWARM_ERR_INVALID_ARG, "n_collisions must be in [1, 2^32-1]");
+  h->run_status = SWARM_OK;
+  h->run_error.clear();
+  h->noalloc_records = false;
   const bool real = h->desc.secondaries == SWARM_REAL;
   int64_t capacity = n_electrons;
   if (real) {
@@ -612,29 +765,92 @@ swarm_status swarm_run(swarm_t h, int64_t n_electrons, int64_t n_collisions, uin
     }
   }
   if ((e = hipEventRecord(h->ev[1], s)) != hipSuccess) return hip_fail(e, "event");
-  if ((e = hipMemcpyAsync(&hc, d.ctr, sizeof(hc), hipMemcpyDeviceToHost, s)) != hipSuccess) return hip_fail(e, "counters");
-  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "swarm kernel");
+  if (real) {
+    if ((e = hipMemcpyAsync(&hc, d.ctr, sizeof(hc), hipMemcpyDeviceToHost, s)) != hipSuccess) return hip_fail(e, "counters");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "swarm kernel");
+  }
   h->n_records = n_electrons + (real ? std::min<int64_t>(static_cast<int64_t>(hc.child_tail), child_cap) : 0);
   if ((e = h->tally.prepare({h->n_records}, s)) != hipSuccess) return hip_fail(e, "tally plan");
   if ((e = h->tally.launch(h->d_desc, s)) != hipSuccess) return hip_fail(e, "tally launch");
   if ((e = hipEventRecord(h->ev[2], s)) != hipSuccess) return hip_fail(e, "event");
-  if ((e = hipMemcpyAsync(&h->tallies, h->tally.d_out.p, sizeof(swarm_tallies_t), hipMemcpyDeviceToHost, s)) != hipSuccess)
+  h->traced = trace;
+  if (hc.dropped) {
+    h->run_status = fail(SWARM_ERR_CAPACITY, "%llu secondaries did not fit the capacity of %lld electrons",
+                         static_cast<unsigned long long>(hc.dropped), static_cast<long long>(capacity));
+    h->run_error = g_last_error;
+  }
+  return SWARM_OK;
+}
+
+// Wait for the enqueued run, read its tallies and timings back.
+swarm_status run_finish(swarm_t h) {
+  hipError_t e;
+  if ((e = hipEventSynchronize(h->ev[2])) != hipSuccess) return hip_fail(e, "swarm run");
+  if ((e = hipMemcpyAsync(&h->tallies, h->tally.d_out.p, sizeof(swarm_tallies_t), hipMemcpyDeviceToHost,
+                          h->stream)) != hipSuccess ||
+      (e = hipStreamSynchronize(h->stream)) != hipSuccess)
     return hip_fail(e, "tallies");
-  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "tallies");
   float ms = 0.f;
   (void)hipEventElapsedTime(&ms, h->ev[0], h->ev[1]);
   h->kernel_ms = ms;
   (void)hipEventElapsedTime(&ms, h->ev[0], h->ev[2]);
   h->total_ms = ms;
   h->have_run = true;
-  h->traced = trace;
-  if (hc.dropped) return fail(SWARM_ERR_CAPACITY, "%llu secondaries did not fit the capacity of %lld electrons",
-                              static_cast<unsigned long long>(hc.dropped), static_cast<long long>(capacity));
+  if (h->run_status != SWARM_OK) g_last_error = h->run_error;
+  return h->run_status;
+}
+
+}  // namespace
+
+extern "C" {
+
+swarm_status swarm_run(swarm_t h, int64_t n_electrons, int64_t n_collisions, uint64_t seed) {
+  if (!h) return fail(SWARM_ERR_INVALID_ARG, "handle is NULL");
+  if (h->in_flight) return busy();
+  const swarm_status st = run_start(h, n_electrons, n_collisions, seed);
+  if (st != SWARM_OK) return st;
+  return run_finish(h);
+}
+
+swarm_status swarm_run_async(swarm_t h, int64_t n_electrons, int64_t n_collisions, uint64_t seed) {
+  if (!h) return fail(SWARM_ERR_INVALID_ARG, "handle is NULL");
+  if (h->in_flight) return busy();
+  h->have_run = false;
+  if (h->desc.secondaries == SWARM_REAL) {
+    // the generations need the host between launches: they run on a worker thread
+    if (n_electrons < 1 || n_collisions < 1 || n_collisions > 0xffffffffLL)
+      return fail(SWARM_ERR_INVALID_ARG, "n_electrons must be >= 1 and n_collisions in [1, 2^32-1]");
+    h->in_flight = 2;
+    h->worker = std::thread([h, n_electrons, n_collisions, seed] {
+      swarm_status st = run_start(h, n_electrons, n_collisions, seed);
+      if (st == SWARM_OK) st = run_finish(h);
+      h->async_status = st;
+      h->async_error = st != SWARM_OK ? g_last_error : std::string();
+    });
+    return SWARM_OK;
+  }
+  const swarm_status st = run_start(h, n_electrons, n_collisions, seed);
+  if (st != SWARM_OK) return st;
+  h->in_flight = 1;
   return SWARM_OK;
+}
+
+swarm_status swarm_wait(swarm_t h) {
+  if (!h) return fail(SWARM_ERR_INVALID_ARG, "handle is NULL");
+  if (h->in_flight == 0) return fail(SWARM_ERR_STATE, "no run in flight");
+  if (h->in_flight == 2) {
+    h->worker.join();
+    h->in_flight = 0;
+    if (h->async_status != SWARM_OK) g_last_error = h->async_error;
+    return h->async_status;
+  }
+  h->in_flight = 0;
+  return run_finish(h);
 }
 
 swarm_status swarm_tallies(swarm_t h, swarm_tallies_t* out) {
   if (!h || !out) return fail(SWARM_ERR_INVALID_ARG, "NULL argument");
+  if (h->in_flight) return busy();
   if (!h->have_run) return fail(SWARM_ERR_STATE, "no completed run");
   *out = h->tallies;
   return SWARM_OK;
@@ -642,6 +858,8 @@ swarm_status swarm_tallies(swarm_t h, swarm_tallies_t* out) {
 
 swarm_status swarm_records(swarm_t h, swarm_record* out, int64_t max_records, int64_t* n_out) {
   if (!h || !n_out) return fail(SWARM_ERR_INVALID_ARG, "NULL argument");
+  if (h->in_flight) return busy();
+  if (h->noalloc_records) return fail(SWARM_ERR_STATE, "the last run wrote its records to caller memory");
   if (!h->have_run) return fail(SWARM_ERR_STATE, "no completed run");
   // Slots of secondaries that a run stopped early never simulated are empty (id all ones)
   // and are left out: *n_out counts the electrons that have a record.
@@ -664,6 +882,7 @@ swarm_status swarm_records(swarm_t h, swarm_record* out, int64_t max_records, in
 
 swarm_status swarm_trace_events(swarm_t h, swarm_event* out, int32_t* counts) {
   if (!h || !out || !counts) return fail(SWARM_ERR_INVALID_ARG, "NULL argument");
+  if (h->in_flight) return busy();
   if (!h->have_run || !h->traced) return fail(SWARM_ERR_STATE, "no traced run");
   hipError_t e = hipMemcpyAsync(out, h->trace_out.p, static_cast<size_t>(h->n_trace) * h->max_events * sizeof(swarm_event),
                                 hipMemcpyDeviceToHost, h->stream);
@@ -692,6 +911,7 @@ swarm_status swarm_tables(swarm_t h, int32_t* grid_size, int32_t* n_channels, do
 
 swarm_status swarm_last_timing(swarm_t h, double* kernel_ms, double* total_ms) {
   if (!h) return fail(SWARM_ERR_INVALID_ARG, "handle is NULL");
+  if (h->in_flight) return busy();
   if (!h->have_run) return fail(SWARM_ERR_STATE, "no completed run");
   if (kernel_ms) *kernel_ms = h->kernel_ms;
   if (total_ms) *total_ms = h->total_ms;

@@ -12,7 +12,7 @@ namespace swarm_impl {
 constexpr int kMaxTraceIds = 256;
 constexpr int kTallyTile = 2048;          // records per tally work-group (fixed: determinism)
 constexpr int kTallyThreads = 256;
-constexpr int kTally1 = 25;               // pass-1 accumulators
+constexpr int kTally1 = 26;               // pass-1 accumulators
 constexpr int kTally2 = 32;               // pass-2 accumulators
 constexpr uint32_t kMaxBlocks = 0x7fffffffu;   // per-electron cap on trial blocks
 

@@ -552,6 +552,16 @@ __device__ __forceinline__ Consts<R> load_consts(const InstanceDesc& d) {
   return c;
 }
 
+// Real-collision count at which a lane stops in this launch: the budget, or with a quantum
+// (resumable epochs) the count after `quantum` more collisions, summed in 64 bits so that a
+// large quantum cannot wrap around.
+template <typename R>
+__device__ __forceinline__ uint32_t stop_count(uint32_t k, const Consts<R>& C) {
+  if (!C.quantum) return C.n_coll;
+  const uint64_t q = static_cast<uint64_t>(k) + C.quantum;
+  return q < C.n_coll ? static_cast<uint32_t>(q) : C.n_coll;
+}
+
 template <typename R>
 struct Lane {
   double rx, ry, rz, t;     // anchor (state right after the last real collision), FP64
@@ -1566,7 +1576,7 @@ __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restr
             L.rec = ei;
             if (started == 1u) load_state<R, HB, EXT>(d, L, C, ei);
             else init_primary<R, HB, EXT>(L, C, s_nu, static_cast<uint64_t>(ei));
-            L.k_stop = C.quantum ? min(C.n_coll, L.k + C.quantum) : C.n_coll;
+            L.k_stop = stop_count(L.k, C);
             if constexpr (TR) {
               L.trace_slot = find_trace<TR>(d, L.id);
               L.n_ev = L.trace_slot >= 0 ? d.trace_count[L.trace_slot] : 0;
@@ -1859,7 +1869,7 @@ __global__ void __launch_bounds__(512) k_swarm_pooled(const InstanceDesc* __rest
               L.rec = ei;
               if (started == 1u) load_state<R, HB, EXT>(d, L, C, ei);
               else init_primary<R, HB, EXT>(L, C, s_nu, static_cast<uint64_t>(ei));
-              L.k_stop = C.quantum ? min(C.n_coll, L.k + C.quantum) : C.n_coll;
+              L.k_stop = stop_count(L.k, C);
               L.state = ST_ACTIVE;
             }
           } else {
@@ -2082,7 +2092,7 @@ __device__ __forceinline__ void block_sum(double* vals, int nq, double* s_red) {
 enum {
   T1_NF = 0, T1_VX, T1_VY, T1_VZ, T1_AG, T1_AD, T1_ZH, T1_GF, T1_DF,
   T1_KREAL, T1_KNULL, T1_KFORB, T1_KOVER, T1_NATT, T1_NSTUCK, T1_NCREATED, T1_GALL, T1_DALL,
-  T1_SE, T1_SEP, T1_NK, T1_PE, T1_PEP, T1_NREC, T1_KFAIL
+  T1_SE, T1_SEP, T1_NK, T1_PE, T1_PEP, T1_NREC, T1_KFAIL, T1_NRETRY
 };
 // pass-2 accumulator indices
 enum {
@@ -2111,6 +2121,7 @@ __global__ void __launch_bounds__(kTallyThreads) k_tally1(const InstanceDesc* __
     a[T1_KOVER] += static_cast<double>(r.n_over);
     a[T1_NATT] += (r.flags & 2u) ? 1.0 : 0.0;
     a[T1_NSTUCK] += (r.flags & 4u) ? 1.0 : 0.0;
+    a[T1_NRETRY] += (r.flags & 16u) ? 1.0 : 0.0;
     a[T1_NCREATED] += (r.id >> 63) ? 1.0 : 0.0;
     a[T1_GALL] += static_cast<double>(r.G);
     a[T1_DALL] += static_cast<double>(r.D);
@@ -2269,6 +2280,9 @@ __global__ void k_tally_final(const InstanceDesc* __restrict__ descs, const doub
   T.n_ionizations = static_cast<int64_t>(a[T1_GALL]);
   T.n_attachments = static_cast<int64_t>(a[T1_DALL]);
   T.n_dropped = d.ctr ? static_cast<int64_t>(d.ctr->dropped) : 0;
+  T.n_retry_failed = static_cast<int64_t>(a[T1_NRETRY]);
+  T.exact = d.trial_strategy == SWARM_TRIAL_CONSTANT ? 1 : 0;
+  T.trial_strategy = d.trial_strategy;
   out[inst] = T;
 }
 

@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -48,6 +49,8 @@ struct Request {
   swarm_params params{};
   int64_t n_e = 0, n_c = 0;
   uint64_t seed = 0;
+  swarm_record* records_out = nullptr;   // host memory for the records, if the caller asked
+  int64_t need = 0;                        // device bytes it holds while admitted
   // scheduler state
   swarm* h = nullptr;
   DevBuf saved;
@@ -63,6 +66,7 @@ struct Request {
 }  // namespace
 
 struct swarm_server {
+  std::unique_ptr<Arena> mem;   // caller-owned device memory, if any (released last)
   swarm_server_params p{};
   std::chrono::steady_clock::time_point t0;
   hipStream_t compute = nullptr, setup = nullptr;
@@ -74,6 +78,7 @@ struct swarm_server {
   int64_t next_ticket = 1;
   int64_t n_unfinished = 0;
   int64_t used_bytes = 0;
+  int64_t budget = 0;           // admission limit: the HBM budget, or the arena if smaller
   bool stop = false;
   std::thread th;
   // device state of the epochs
@@ -82,6 +87,8 @@ struct swarm_server {
   int max_slots = 0;
   TallyPlan tally;
   double rate = 0.0;   // measured real collisions per second (adaptive quantum)
+  int64_t epoch = 0;   // epochs run so far
+  int64_t fail_epoch = 0;   // tests: epoch number that reports a device failure (0 = none)
 
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -90,8 +97,8 @@ struct swarm_server {
 
 namespace {
 
-// Device memory charged for a request: tables (as allocated by swarm_create) plus records
-// and resumable state of every electron.
+// Estimate of the device memory of a request whose inputs failed validation (it is
+// refused at admission): tables plus records and resumable state of every electron.
 int64_t request_bytes(const Request& r) {
   int64_t nc = 0, pts = 0;
   for (const auto& c : r.comps) {
@@ -122,9 +129,10 @@ swarm_status admit(swarm_server* s, const std::shared_ptr<Request>& r) {
   p.secondaries = SWARM_DUMMY;
   p.stream = s->setup;
   swarm_t h = nullptr;
-  swarm_status st = swarm_create(comps.data(), static_cast<int32_t>(comps.size()), &p, &h);
+  swarm_status st = create_swarm(comps.data(), static_cast<int32_t>(comps.size()), &p, s->mem.get(), &h);
   if (st != SWARM_OK) return st;
   r->h = h;
+  r->saved.arena = s->mem.get();
   hipError_t e;
   if ((e = h->records.ensure(static_cast<size_t>(r->n_e) * sizeof(swarm_record))) != hipSuccess ||
       (e = r->saved.ensure(static_cast<size_t>(r->n_e) * sizeof(SavedState))) != hipSuccess)
@@ -178,8 +186,8 @@ void admit_pending(swarm_server* s) {
     {
       std::lock_guard<std::mutex> lk(s->mu);
       if (s->pending.empty() || s->free_slots.empty()) return;
-      const int64_t need = request_bytes(*s->pending.front());
-      if (s->used_bytes + need > s->p.hbm_budget_bytes && !s->active.empty()) return;
+      const int64_t need = s->pending.front()->need;
+      if (s->used_bytes + need > s->budget && !s->active.empty()) return;
       r = s->pending.front();
       s->pending.pop_front();
       r->slot = s->free_slots.back();
@@ -189,6 +197,22 @@ void admit_pending(swarm_server* s) {
       r->admit_s = s->now();
     }
     const swarm_status st = admit(s, r);
+    if (st == SWARM_ERR_OUT_OF_MEMORY && s->mem) {
+      // The caller's region is fragmented (or the budget overstates it): give the memory
+      // back and retry once an admitted request has finished and released its blocks.
+      std::lock_guard<std::mutex> lk(s->mu);
+      if (!s->active.empty()) {
+        if (r->h) swarm_destroy(r->h);
+        r->h = nullptr;
+        r->saved.reset();
+        s->free_slots.push_back(r->slot);
+        r->slot = -1;
+        s->used_bytes -= r->bytes;
+        r->bytes = 0;
+        s->pending.push_front(r);
+        return;
+      }
+    }
     if (st != SWARM_OK) {
       finish(s, r, st);
       continue;
@@ -240,7 +264,7 @@ void scheduler(swarm_server* s) {
     {
       std::unique_lock<std::mutex> lk(s->mu);
       s->cv.wait(lk, [&] { return s->stop || !s->pending.empty() || !s->active.empty(); });
-      if (s->stop && s->active.empty() && s->pending.empty()) break;
+      if (s->stop) break;
     }
     admit_pending(s);
     std::vector<std::shared_ptr<Request>> act;
@@ -256,8 +280,9 @@ void scheduler(swarm_server* s) {
     int64_t q = s->p.quantum_collisions;
     if (q <= 0) {
       q = s->rate > 0 ? static_cast<int64_t>(0.05 * s->rate / std::max<int64_t>(1, electrons)) : 1000;
-      q = std::max<int64_t>(64, std::min<int64_t>(q, max_nc));
+      q = std::max<int64_t>(64, q);
     }
+    q = std::min<int64_t>(q, max_nc);   // no electron of the epoch needs more
     descs.clear();
     std::vector<int64_t> ne, nc;
     int G = 0, n_ch = 0;
@@ -289,6 +314,11 @@ void scheduler(swarm_server* s) {
                  (e = hipMemcpyAsync(s->items.p, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, s->compute)) == hipSuccess &&
                  (e = launch_fill_u32(reinterpret_cast<uint32_t*>(item_ctr), 0u, 1, s->compute)) == hipSuccess &&
                  (e = hipEventRecord(ev0, s->compute)) == hipSuccess;
+    if (ok && ++s->epoch == s->fail_epoch) {
+      // failure injection (tests of the error path): nothing is launched
+      ok = false;
+      e = hipErrorLaunchFailure;
+    }
     if (ok) {
       const int grid = std::max(1, std::min<int>(static_cast<int>(items.size()), device_info().n_cu * per_cu));
       ok = (e = launch_swarm_dummy(static_cast<const InstanceDesc*>(s->descs.p), static_cast<const WorkItem*>(s->items.p),
@@ -303,10 +333,15 @@ void scheduler(swarm_server* s) {
     if (ok) ok = (e = hipMemcpyAsync(hc.data(), s->ctrs.p, s->max_slots * sizeof(RunCounters), hipMemcpyDeviceToHost, s->compute)) == hipSuccess &&
                  (e = hipStreamSynchronize(s->compute)) == hipSuccess;
     if (!ok) {
+      // The device state of every admitted request is suspect: all of them fail, including
+      // those the schedule left out of this epoch and those admitted while it ran.
       (void)hip_fail(e, "serving epoch");
-      for (auto& r : act) finish(s, r, SWARM_ERR_DEVICE);
-      std::lock_guard<std::mutex> lk(s->mu);
-      s->active.clear();
+      std::vector<std::shared_ptr<Request>> failed;
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        failed.swap(s->active);
+      }
+      for (auto& r : failed) finish(s, r, SWARM_ERR_DEVICE);
       continue;
     }
     float ms = 0.f;
@@ -332,6 +367,7 @@ void scheduler(swarm_server* s) {
     }
     if (!fin.empty()) {
       DevBuf fd;
+      fd.arena = s->mem.get();
       ok = (e = fd.ensure(fin_desc.size() * sizeof(InstanceDesc))) == hipSuccess &&
            (e = hipMemcpyAsync(fd.p, fin_desc.data(), fin_desc.size() * sizeof(InstanceDesc), hipMemcpyHostToDevice, s->compute)) == hipSuccess &&
            (e = s->tally.prepare(fin_n, s->compute)) == hipSuccess &&
@@ -339,6 +375,11 @@ void scheduler(swarm_server* s) {
       std::vector<swarm_tallies_t> out(fin.size());
       if (ok) ok = (e = hipMemcpyAsync(out.data(), s->tally.d_out.p, out.size() * sizeof(swarm_tallies_t), hipMemcpyDeviceToHost, s->compute)) == hipSuccess &&
                    (e = hipStreamSynchronize(s->compute)) == hipSuccess;
+      for (auto& r : fin)
+        if (ok && r->records_out)
+          ok = (e = hipMemcpyAsync(r->records_out, r->h->records.p, static_cast<size_t>(r->n_e) * sizeof(swarm_record),
+                                   hipMemcpyDeviceToHost, s->compute)) == hipSuccess &&
+               (e = hipStreamSynchronize(s->compute)) == hipSuccess;
       {
         std::lock_guard<std::mutex> lk(s->mu);
         for (auto& r : fin) s->active.erase(std::find(s->active.begin(), s->active.end(), r));
@@ -350,15 +391,25 @@ void scheduler(swarm_server* s) {
       }
     }
   }
+  // Stopped (swarm_server_destroy): the running epoch has ended; every request not yet
+  // finished is cancelled and releases its memory.
+  std::vector<std::shared_ptr<Request>> left;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    left.swap(s->active);
+    left.insert(left.end(), s->pending.begin(), s->pending.end());
+    s->pending.clear();
+  }
+  for (auto& r : left) finish(s, r, SWARM_ERR_STATE);
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);
 }
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-swarm_status swarm_server_create(const swarm_server_params* p, swarm_server_t* out) {
+swarm_status server_create(const swarm_server_params* p, void* arena, int64_t arena_bytes, swarm_server_t* out) {
   if (!p || !out) return fail(SWARM_ERR_INVALID_ARG, "NULL argument");
   *out = nullptr;
   if (p->hbm_budget_bytes <= 0) return fail(SWARM_ERR_INVALID_ARG, "hbm budget must be > 0");
@@ -368,7 +419,15 @@ swarm_status swarm_server_create(const swarm_server_params* p, swarm_server_t* o
     return fail(SWARM_ERR_INVALID_ARG, "schedule must be SWARM_SCHEDULE_ALL or SWARM_SCHEDULE_SHORTEST_FIRST");
   auto s = std::make_unique<swarm_server>();
   s->p = *p;
+  s->budget = p->hbm_budget_bytes;
+  if (arena) {
+    s->mem = std::make_unique<Arena>(arena, static_cast<size_t>(arena_bytes));
+    s->budget = std::min<int64_t>(s->budget, static_cast<int64_t>(s->mem->capacity()));
+    for (DevBuf* b : {&s->ctrs, &s->descs, &s->items}) b->arena = s->mem.get();
+    s->tally.bind(s->mem.get());
+  }
   s->t0 = std::chrono::steady_clock::now();
+  if (const char* f = std::getenv("SWARM_SERVER_FAIL_EPOCH")) s->fail_epoch = std::atoll(f);
   s->max_slots = p->max_active > 0 ? p->max_active : 1024;
   hipError_t e;
   if (p->stream) s->compute = static_cast<hipStream_t>(p->stream);
@@ -382,9 +441,29 @@ swarm_status swarm_server_create(const swarm_server_params* p, swarm_server_t* o
   return SWARM_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+swarm_status swarm_server_create(const swarm_server_params* p, swarm_server_t* out) {
+  return server_create(p, nullptr, 0, out);
+}
+
+swarm_status swarm_server_create_in_arena(const swarm_server_params* p, void* arena, int64_t arena_bytes,
+                                          swarm_server_t* out) {
+  if (!arena || arena_bytes <= 0) return fail(SWARM_ERR_INVALID_ARG, "arena must be a device pointer with bytes > 0");
+  return server_create(p, arena, arena_bytes, out);
+}
+
 swarm_status swarm_server_submit(swarm_server_t s, const swarm_component* comps, int32_t n_comps,
                                  const swarm_params* params, int64_t n_electrons, int64_t n_collisions,
                                  uint64_t seed, int64_t* ticket) {
+  return swarm_server_submit_records(s, comps, n_comps, params, n_electrons, n_collisions, seed, nullptr, ticket);
+}
+
+swarm_status swarm_server_submit_records(swarm_server_t s, const swarm_component* comps, int32_t n_comps,
+                                         const swarm_params* params, int64_t n_electrons, int64_t n_collisions,
+                                         uint64_t seed, swarm_record* records_out, int64_t* ticket) {
   if (!s || !comps || !params || !ticket) return fail(SWARM_ERR_INVALID_ARG, "NULL argument");
   if (params->secondaries != SWARM_DUMMY) return fail(SWARM_ERR_INVALID_ARG, "serving takes dummy-secondaries requests");
   if (n_electrons < 1) return fail(SWARM_ERR_INVALID_ARG, "n_electrons must be >= 1");
@@ -414,6 +493,18 @@ swarm_status swarm_server_submit(swarm_server_t s, const swarm_component* comps,
   r->n_e = n_electrons;
   r->n_c = n_collisions;
   r->seed = seed;
+  r->records_out = records_out;
+  {
+    // device memory while admitted: the tables exactly as swarm_create allocates them, then
+    // records and resumable state (256-byte blocks)
+    swarm_params p = *params;
+    p.precision = s->p.precision;
+    p.secondaries = SWARM_DUMMY;
+    const int64_t tables = static_cast<int64_t>(create_bytes(comps, n_comps, &p));
+    r->need = (tables > 0 ? tables + 256 : request_bytes(*r)) +
+              ((r->n_e * static_cast<int64_t>(sizeof(swarm_record)) + 255) & ~int64_t(255)) +
+              ((r->n_e * static_cast<int64_t>(sizeof(SavedState)) + 255) & ~int64_t(255));
+  }
   {
     std::lock_guard<std::mutex> lk(s->mu);
     r->ticket = s->next_ticket++;

@@ -44,7 +44,7 @@ def test_struct_sizes_match_the_oracle_layout():
     import paper_1901_08140_amd as sw
     assert sw.RECORD_DTYPE.itemsize == 104
     assert sw.EVENT_DTYPE.itemsize == 80
-    assert ctypes.sizeof(sw.swarm_tallies_t) == 20 * 24 + 4 * 8 + 13 * 8
+    assert ctypes.sizeof(sw.swarm_tallies_t) == 20 * 24 + 4 * 8 + 14 * 8 + 2 * 4
 
 
 STRUCTS = ["swarm_channel", "swarm_component", "swarm_params", "swarm_stat", "swarm_tallies_t", "swarm_job",

@@ -6,7 +6,10 @@ import time
 import numpy as np
 import pytest
 
+import oracle
 import synth
+from oracle.tallies import tallies as oracle_tallies
+from swarm_testutil import compare_records
 
 pytestmark = pytest.mark.gpu
 
@@ -59,9 +62,19 @@ def test_alone_equals_in_the_mix(gpu, precision, schedule):
         sw.swarm_server_destroy(srv)
 
 
+def _alone(sw, reqs, precision):
+    out = []
+    for c in reqs:
+        s = sw.Swarm.from_config(c, precision)
+        s.run(c.n_electrons, c.n_collisions, c.seed)
+        out.append(s.tallies())
+    return out
+
+
 def test_budget_admission_queues_requests(gpu):
     sw = gpu
     reqs = [_shrink(c, 50000, 500) for c in _requests(6)]
+    alone = _alone(sw, reqs, sw.SWARM_FP32_MIXED)
     srv = sw.swarm_server_create(30 << 20, sw.SWARM_FP32_MIXED, quantum_collisions=0)
     try:
         tickets = [sw.swarm_server_submit(srv, c.components, sw.params_from_config(c, 1), c.n_electrons,
@@ -70,10 +83,120 @@ def test_budget_admission_queues_requests(gpu):
         res = _wait_all(sw, srv, tickets)
         admits = [res[t][1]["admit_s"] for t in tickets]
         assert admits == sorted(admits)
-        for t, c in zip(tickets, reqs):
+        # the budget held some requests back until others had finished
+        assert max(admits) > min(res[t][1]["done_s"] for t in tickets)
+        for t, c, a in zip(tickets, reqs, alone):
             assert res[t][0]["n_real"] == c.n_electrons * c.n_collisions
+            assert res[t][0] == a
     finally:
         sw.swarm_server_destroy(srv)
+
+
+def test_requests_submitted_while_epochs_run(gpu):
+    """Requests that arrive while others are on the device join later epochs and still give
+    the bits of their single runs."""
+    sw = gpu
+    reqs = [_shrink(c, 20000, 2000) for c in _requests(8)]
+    alone = _alone(sw, reqs, sw.SWARM_FP32_MIXED)
+    srv = sw.swarm_server_create(64 << 30, sw.SWARM_FP32_MIXED, quantum_collisions=50)
+    try:
+        first = [sw.swarm_server_submit(srv, c.components, sw.params_from_config(c, 1), c.n_electrons,
+                                        c.n_collisions, c.seed) for c in reqs[:3]]
+        t0 = time.time()
+        while sw.swarm_server_poll(srv, first[0])[2]["admit_s"] == 0.0:
+            assert time.time() - t0 < 60
+            time.sleep(0.001)
+        late = [sw.swarm_server_submit(srv, c.components, sw.params_from_config(c, 1), c.n_electrons,
+                                       c.n_collisions, c.seed) for c in reqs[3:]]
+        res = _wait_all(sw, srv, first + late)
+        first_admit = res[first[0]][1]["admit_s"]
+        for t in late:
+            assert res[t][1]["admit_s"] > first_admit
+        for t, a in zip(first + late, alone):
+            assert res[t][0] == a
+    finally:
+        sw.swarm_server_destroy(srv)
+
+
+def test_served_requests_match_the_oracle(gpu):
+    """Config-5 requests (random mixtures, fields and sizes, shrunk to what the oracle runs in
+    seconds), served in FP64 with small epochs: every request's tallies equal the oracle's
+    (continuous values to 1e-8 relative, counts exactly) and the records of those submitted
+    with a record buffer equal the oracle's (integer fields exactly, continuous to 1e-9)."""
+    sw = gpu
+    reqs = [_shrink(c, 300, 250) for c in _requests(12)]
+    srv = sw.swarm_server_create(8 << 30, sw.SWARM_FP64, quantum_collisions=40)
+    recs = {}
+    try:
+        tickets = []
+        for i, c in enumerate(reqs):
+            p = sw.params_from_config(c, sw.SWARM_FP64)
+            if i % 3 == 0:
+                t, rec = sw.swarm_server_submit_records(srv, c.components, p, c.n_electrons, c.n_collisions, c.seed)
+                recs[t] = rec
+            else:
+                t = sw.swarm_server_submit(srv, c.components, p, c.n_electrons, c.n_collisions, c.seed)
+            tickets.append(t)
+        res = _wait_all(sw, srv, tickets)
+    finally:
+        sw.swarm_server_destroy(srv)
+    for t, c in zip(tickets, reqs):
+        r = oracle.OracleModel.from_config(c).run(c.n_electrons, c.n_collisions, c.seed)
+        O = oracle_tallies(r.records)
+        T = res[t][0]
+        assert res[t][1]["epochs"] >= c.n_collisions // 40
+        for key in ("W", "Wx", "Wy", "Wz", "mean_energy", "mean_energy_after", "D", "DL", "DT", "D_vec",
+                    "DL_vec", "DT_vec", "sigma", "sigma_vec", "alpha", "eta"):
+            for j in range(3):
+                a, b = T[key][j], O[key][j]
+                assert abs(a - b) <= 1e-8 * abs(b) + 1e-300, (c.label, key, j, a, b)
+        for key in ("n_real", "n_null", "n_forbidden", "n_over", "n_electrons", "n_finished", "n_ionizations",
+                    "n_attachments"):
+            assert T[key] == O[key], (c.label, key)
+        if t in recs:
+            compare_records(recs[t], r.records)
+
+
+def test_failed_epoch_fails_every_admitted_request(gpu, monkeypatch):
+    """A device failure in an epoch (forced from the host: the epoch launches nothing) fails
+    every admitted request, including those left out of the epoch and those admitted while it
+    ran; drain returns, and the server goes on serving new requests."""
+    sw = gpu
+    monkeypatch.setenv("SWARM_SERVER_FAIL_EPOCH", "10")
+    reqs = [_shrink(c, 3000, 3000) for c in _requests(6)]
+    srv = sw.swarm_server_create(64 << 30, sw.SWARM_FP32_MIXED, quantum_collisions=20, schedule=1)
+    try:
+        tickets = [sw.swarm_server_submit(srv, c.components, sw.params_from_config(c, 1), c.n_electrons,
+                                          c.n_collisions, c.seed) for c in reqs]
+        sw.swarm_server_drain(srv)
+        failed = 0
+        for t in tickets:
+            try:
+                # a request admitted only after the failed epoch finishes normally
+                assert sw.swarm_server_poll(srv, t)[0]
+            except sw.SwarmError as e:
+                assert e.status == sw.SWARM_ERR_DEVICE
+                failed += 1
+        assert failed >= 1
+        c = _shrink(_requests(7)[6], 2000, 200)
+        t = sw.swarm_server_submit(srv, c.components, sw.params_from_config(c, 1), c.n_electrons, c.n_collisions,
+                                   c.seed)
+        sw.swarm_server_drain(srv)
+        assert sw.swarm_server_poll(srv, t)[0]
+    finally:
+        sw.swarm_server_destroy(srv)
+
+
+def test_destroy_cancels_unfinished_requests(gpu):
+    sw = gpu
+    reqs = [synth.cfg5_request(i).scaled(n_electrons=200000, n_collisions=100000) for i in range(3)]
+    srv = sw.swarm_server_create(64 << 30, sw.SWARM_FP32_MIXED)
+    for c in reqs:
+        sw.swarm_server_submit(srv, c.components, sw.params_from_config(c, 1), c.n_electrons, c.n_collisions, c.seed)
+    time.sleep(0.5)
+    t0 = time.time()
+    sw.swarm_server_destroy(srv)
+    assert time.time() - t0 < 20
 
 
 def test_invalid_schedule_refused(gpu):
