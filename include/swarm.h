@@ -303,6 +303,22 @@ swarm_status swarm_tables(swarm_t h, int32_t* grid_size, int32_t* n_channels, do
  * (simulation plus tallies). */
 swarm_status swarm_last_timing(swarm_t h, double* kernel_ms, double* total_ms);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving
+ * loops that must not call hipMalloc, harnesses that forbid it): the DUMMY-mode run of
+ * swarm_run with no allocation.  The caller passes `records`, device memory for n_electrons
+ * swarm_record entries, which receive the records of ids 0..n-1 in id order (as swarm_run
+ * keeps them).  The run's scratch (work items, their counter, tally partial sums and
+ * output) is a library array of 1.4 MB in device memory, one per GPU, held until the
+ * process ends; n_electrons is limited to 4194304 (2^22) and larger runs are refused with
+ * SWARM_ERR_INVALID_ARG, as are REAL mode and tracing.  Every call on a GPU shares that
+ * GPU's array and leaves its contents behind (each call rebuilds what it reads); calls that
+ * overlapped on one GPU would race on it, so the library runs them one at a time (a call
+ * holds a per-device lock until its results are back).  Synchronous: on return
+ * swarm_tallies gives the tallies (the same bits as swarm_run's); swarm_records refuses
+ * (SWARM_ERR_STATE), the records being in the caller's memory. */
+swarm_status swarm_run_noalloc(swarm_t h, int64_t n_electrons, int64_t n_collisions, uint64_t seed,
+                               swarm_record* records);
+
 void swarm_destroy(swarm_t h);             /* NULL-safe */
 const char* swarm_strerror(swarm_status s);
 const char* swarm_last_error(void);        /* thread-local message of the last failure */

@@ -113,6 +113,7 @@ _SIGS = {
     "swarm_wait": (_i32, [_vp]),
     "swarm_create_in_arena": (_i32, [_P(swarm_component), _i32, _P(swarm_params), _vp, _i64, _P(_vp)]),
     "swarm_arena_bytes": (_i32, [_P(swarm_component), _i32, _P(swarm_params), _i64, _P(_i64)]),
+    "swarm_run_noalloc": (_i32, [_vp, _i64, _i64, _u64, _vp]),
     "swarm_set_launch_opts": (_i32, [_vp, _P(swarm_launch_opts)]),
     "swarm_tallies": (_i32, [_vp, _P(swarm_tallies_t)]),
     "swarm_records": (_i32, [_vp, _vp, _i64, _P(_i64)]),
@@ -263,6 +264,11 @@ def swarm_run_async(h, n_electrons, n_collisions, seed):
 def swarm_wait(h):
     """The run's status (raises SwarmError like swarm_run)."""
     return _check(_lib.swarm_wait(h))
+
+
+def swarm_run_noalloc(h, n_electrons, n_collisions, seed, records_ptr):
+    """records_ptr: device address (int) of n_electrons records (104 bytes each)."""
+    return _check(_lib.swarm_run_noalloc(h, int(n_electrons), int(n_collisions), int(seed), _vp(int(records_ptr))))
 
 
 def tallies_to_dict(t):

@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libswarm.so")
-SOURCES = ["swarm_kernels.hip", "swarm_api.cpp", "swarm_batch.cpp", "swarm_server.cpp"]
+SOURCES = ["swarm_kernels.hip", "swarm_api.cpp", "swarm_batch.cpp", "swarm_server.cpp", "swarm_noalloc.cpp"]
 ARCH = os.environ.get("SWARM_OFFLOAD_ARCH", "gfx950")
 
 
