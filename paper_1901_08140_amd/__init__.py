@@ -29,6 +29,13 @@ SWARM_SCHEDULE_ALL, SWARM_SCHEDULE_SHORTEST_FIRST = 0, 1
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1901_08140_amd/build.py`")
+# torch ships its own HIP and HSA runtimes.  Loading torch first lets the library bind to those
+# (same sonames) instead of a second copy from /opt/rocm, which cannot open the device once
+# torch's copy holds it.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
 _lib = ctypes.CDLL(LIB_PATH)
 
 _d, _i32, _i64, _u64, _vp = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p

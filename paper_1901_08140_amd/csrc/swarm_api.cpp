@@ -380,7 +380,7 @@ swarm_launch_opts resolve_opts(const swarm_launch_opts* o, int precision) {
   swarm_launch_opts r{};
   r.block_size = (o && o->block_size) ? o->block_size : default_block(precision);
   r.chunk = (o && o->chunk) ? o->chunk : r.block_size * 8;
-  r.pending_trigger = (o && o->pending_trigger) ? o->pending_trigger : 24;
+  r.pending_trigger = (o && o->pending_trigger) ? o->pending_trigger : 32;
   r.use_graph = o ? o->use_graph : 0;
   r.block_size = std::max(64, std::min(1024, (r.block_size / 64) * 64));
   r.chunk = std::max(r.block_size, (r.chunk / r.block_size) * r.block_size);

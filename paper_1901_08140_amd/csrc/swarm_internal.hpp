@@ -17,14 +17,12 @@ constexpr int kTally2 = 32;               // pass-2 accumulators
 constexpr uint32_t kMaxBlocks = 0x7fffffffu;   // per-electron cap on trial blocks
 
 // Lane states of the swarm kernels.
-// ACTIVE: drawing trials; PENDING: holds a real-collision candidate and draws its
-// scattering block in the next trial pass; READY: candidate and scattering words ready;
-// IDLE: needs an electron; WAIT: pooled schedule, has its candidate in the work-group
-// pool; CAND: pooled schedule, holds a
-// candidate not yet in the pool; STOPPED: must store its record or state; DONE: no more
-// work.
-enum : int { ST_ACTIVE = 0, ST_PENDING = 1, ST_IDLE = 2, ST_WAIT = 3, ST_DONE = 4, ST_STOPPED = 5,
-             ST_READY = 6, ST_CAND = 7 };
+// ACTIVE: drawing trials; READY: holds a real-collision candidate (served with the wave's
+// other READY lanes, which draw their scattering words then); IDLE: needs an electron; WAIT:
+// pooled schedule, has its candidate in the work-group pool; CAND: pooled schedule, holds a
+// candidate not yet in the pool; STOPPED: must store its record or state; DONE: no more work.
+enum : int { ST_ACTIVE = 0, ST_IDLE = 2, ST_WAIT = 3, ST_DONE = 4, ST_STOPPED = 5, ST_READY = 6,
+             ST_CAND = 7 };
 
 // Per-channel constants built on the device from the raw inputs.
 struct ChannelDev {

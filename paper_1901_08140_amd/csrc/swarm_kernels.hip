@@ -1142,45 +1142,46 @@ __device__ __forceinline__ bool one_trial(Lane<R>& L, const Consts<R>& C,
 // One random-number block = two candidate trials (eq. random_time for the flight time,
 // eq. null_fraction for the real/null test with x = R nu' < nu(eps)).  A non-null
 // outcome of the first trial leaves the second unused.  The total rate comes from the
-// LDS pair table.
-// Lanes that hold a real-collision candidate (PENDING) run the same Philox instructions
-// with the counter of their scattering block (k, SCAT) instead of a trial block: they
-// would be masked off here anyway, so the scattering words cost the wave nothing and the
-// collision phase needs no generator call of its own.  The streams are unchanged.
+// LDS pair table.  A lane that finds a real candidate is READY at once: its scattering
+// words are drawn in the collision phase, where all the wave's waiting lanes draw them in
+// one generator call (drawing them in a trial pass would keep the lane out of trials for a
+// pass).
 template <typename R, bool HB, int EXT>
 __device__ __forceinline__ void trial_block(Lane<R>& L, const Consts<R>& C,
                                             const typename Pair<R>::T* __restrict__ s_nu) {
-  const bool waiting = L.state == ST_PENDING;
-  if (!waiting && L.block >= kMaxBlocks) {
+  if (L.block >= kMaxBlocks) {
     L.flags |= 4u;
     L.state = ST_STOPPED;    // stopped at the cap: recorded and flagged
     return;
   }
-  const uint32_t ctr = waiting ? L.k : L.block;
-  TrialPre ph = L.pre_hi;
-  if (waiting) ph.a ^= (TAG_TRIAL_HI ^ TAG_SCAT_HI);
-  const W4 h = draw_trial(C.key, ph, ctr);
+  const W4 h = draw_trial(C.key, L.pre_hi, L.block);
   W4 l = {0, 0, 0, 0};
-  if constexpr (sizeof(R) == 8) {
-    TrialPre pl = L.pre_lo;
-    if (waiting) pl.a ^= (TAG_TRIAL_LO ^ TAG_SCAT_LO);
-    l = draw_trial(C.key, pl, ctr);
-  }
-  if (waiting) {
-    L.sh = h;
-    L.sl = l;
-    L.state = ST_READY;
-    return;
-  }
+  if constexpr (sizeof(R) == 8) l = draw_trial(C.key, L.pre_lo, L.block);
   L.block += 1;
   // The trial writes the candidate fields of the lane directly: a lane that finds a real
-  // candidate becomes PENDING and stops writing them until it is served, so they need no
-  // copy, and the second trial runs only on the lanes whose first one was null.
+  // candidate stops writing them until it is served, so they need no copy, and the second
+  // trial runs only on the lanes whose first one was null.
   bool hit = one_trial<R, HB, EXT>(L, C, s_nu, h.x, h.y, l.x, l.y);
   const bool second = !hit;
   if (second) hit = one_trial<R, HB, EXT>(L, C, s_nu, h.z, h.w, l.z, l.w);
   L.p_sub = second ? 1u : 0u;
-  L.state = hit ? ST_PENDING : ST_ACTIVE;
+  L.state = hit ? ST_READY : ST_ACTIVE;
+}
+
+// Scattering block k of the lane's electron (SCAT_HI, and SCAT_LO in FP64), through the
+// precomputed first round of its trial stream (the tags differ by a constant in word 1).
+template <typename R>
+__device__ __forceinline__ void draw_scattering(Lane<R>& L, const Consts<R>& C) {
+  TrialPre ph = L.pre_hi;
+  ph.a ^= (TAG_TRIAL_HI ^ TAG_SCAT_HI);
+  L.sh = draw_trial(C.key, ph, L.k);
+  if constexpr (sizeof(R) == 8) {
+    TrialPre pl = L.pre_lo;
+    pl.a ^= (TAG_TRIAL_LO ^ TAG_SCAT_LO);
+    L.sl = draw_trial(C.key, pl, L.k);
+  } else {
+    L.sl = W4{0, 0, 0, 0};
+  }
 }
 
 // Outcome of serving a pending candidate.
@@ -1348,16 +1349,20 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
   const typename Pair<R>::T* row = C.cum + static_cast<int64_t>(g) * C.nc;
   int lo;
   if (C.nc <= kScanChannels) {
-    // few channels: fetch the whole row at once (one memory round trip) and take the
-    // first c with x < C_c(eps) by a backward scan; the last channel needs no test
-    typename Pair<R>::T q[kScanChannels - 1];
-#pragma unroll
-    for (int c = 0; c < kScanChannels - 1; ++c)
-      if (c < C.nc - 1) q[c] = row[c];
+    // few channels: fetch the whole row at once and take the first c with x < C_c(eps) by a
+    // backward scan; the last channel needs no test.  The loads are unconditional (indices
+    // clamped to the row), so that they all issue before the first wait: one memory round
+    // trip.
     lo = C.nc - 1;
+    if (C.nc > 1) {
+      const int last = C.nc - 2;
+      typename Pair<R>::T q[kScanChannels - 1];
 #pragma unroll
-    for (int c = kScanChannels - 2; c >= 0; --c)
-      if (c < C.nc - 1 && x < lerp_pair(q[c], w)) lo = c;
+      for (int c = 0; c < kScanChannels - 1; ++c) q[c] = row[min(c, last)];
+#pragma unroll
+      for (int c = kScanChannels - 2; c >= 0; --c)
+        if (c <= last && x < lerp_pair(q[c], w)) lo = c;
+    }
   } else {
     // many channels: bisection on the running sums, which do not decrease with c
     lo = 0;
@@ -1392,7 +1397,8 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
     if (e64 < ch.onset) return forbidden_pick<R, TR, EXT>(d, L, C, lo, eps, nu_eps);
   }
   if (over) L.nover += 1;
-  const W4 h = L.sh;        // scattering block k, drawn while the candidate waited
+  draw_scattering<R>(L, C);   // scattering block k (kept in the lane for a secondary)
+  const W4 h = L.sh;
   const W4 l = L.sl;
   R nx, ny, nz;
   const R u_c = uni(h.x, l.x, R(0)), u_p = uni(h.y, l.y, R(0));
@@ -1590,10 +1596,10 @@ __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restr
       // Trial phase: random-number blocks until enough lanes of the wave wait on a
       // real-collision candidate (or none can go on), then serve them together.  (`drawing`
       // is carried to the next pass, so the test is made once per pass.)
-      bool drawing = L.state == ST_ACTIVE || L.state == ST_PENDING;
+      bool drawing = L.state == ST_ACTIVE;
       for (;;) {
         if (drawing) trial_block<R, HB, EXT>(L, C, s_nu);
-        drawing = L.state == ST_ACTIVE || L.state == ST_PENDING;
+        drawing = L.state == ST_ACTIVE;
         const uint64_t ready = __ballot(L.state == ST_READY);
         if (__ballot(drawing) == 0 || static_cast<int>(__popcll(ready)) >= pend_trig) break;
       }
@@ -1690,7 +1696,7 @@ __device__ __forceinline__ void pool_take(const Pool<R>& P, int s, Lane<R>& S, c
   S.nfirst = P.U(PU_NFIRST, s); S.nforb = P.U(PU_NFORB, s); S.nover = P.U(PU_NOVER, s);
   S.G = P.U(PU_G, s); S.D = P.U(PU_D, s); S.k = P.U(PU_K, s); S.k_stop = P.U(PU_KSTOP, s);
   S.flags = P.U(PU_FLAGS, s); S.nfail = P.U(PU_NFAIL, s);
-  S.id = static_cast<uint64_t>(P.U(PU_IDLO, s)) | (static_cast<uint64_t>(P.U(PU_IDHI, s)) << 32);
+  set_id(S, C, static_cast<uint64_t>(P.U(PU_IDLO, s)) | (static_cast<uint64_t>(P.U(PU_IDHI, s)) << 32));
   if constexpr (EXT) {
     restore_trial_frequency<R, EXT>(S, C, P.V(PR_NUP, s));
     S.grace = P.U(PU_GRACE, s);
@@ -1698,11 +1704,7 @@ __device__ __forceinline__ void pool_take(const Pool<R>& P, int s, Lane<R>& S, c
   S.trace_slot = -1;
   S.n_ev = 0;
   set_anchor<R, HB>(S, C);
-  // the scattering block k of this electron (the stream the per-wave schedule draws while
-  // the candidate waits)
-  S.sh = draw(C.key, S.id, TAG_SCAT_HI, S.k);
-  if constexpr (sizeof(R) == 8) S.sl = draw(C.key, S.id, TAG_SCAT_LO, S.k);
-  else S.sl = W4{0, 0, 0, 0};
+  // (the collision code draws the scattering block k from the first-round terms set_id made)
 }
 
 // Service lane -> pool: the outcome.
@@ -2024,10 +2026,10 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
       }
     }
     uint64_t ready;
-    bool drawing = L.state == ST_ACTIVE || L.state == ST_PENDING;
+    bool drawing = L.state == ST_ACTIVE;
     for (;;) {
       if (drawing) trial_block<R, HB, EXT>(L, C, s_nu);
-      drawing = L.state == ST_ACTIVE || L.state == ST_PENDING;
+      drawing = L.state == ST_ACTIVE;
       ready = __ballot(L.state == ST_READY);
       if (__ballot(drawing) == 0 || static_cast<int>(__popcll(ready)) >= pend_trig) break;
     }
@@ -2058,7 +2060,7 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
     if (!aborting && ++pass % kAbortPoll == 0)
       aborting = __builtin_amdgcn_readfirstlane(static_cast<int>(
                      __hip_atomic_load(&ctr->dropped, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) != 0;
-    if (aborting && (L.state == ST_ACTIVE || L.state == ST_PENDING || L.state == ST_READY)) {
+    if (aborting && (L.state == ST_ACTIVE || L.state == ST_READY)) {
       L.flags |= 8u;
       L.state = ST_STOPPED;
     }
