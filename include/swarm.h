@@ -404,7 +404,19 @@ typedef struct {
   int64_t n_real;                     /* real collisions of the request */
   int64_t epochs;                     /* scheduling epochs the request took part in */
   int64_t bytes;                      /* device memory charged against the budget */
+  int64_t progress;                   /* real collisions made so far (all its electrons; exact
+                                         at epoch boundaries) */
 } swarm_request_info;
+
+/* A snapshot of the server (swarm_server_stats). */
+typedef struct {
+  double time_s;                      /* server clock */
+  int64_t n_submitted, n_pending, n_active, n_finished, n_failed;   /* requests */
+  int64_t bytes_in_use;               /* device memory charged by admitted requests */
+  int64_t work_left;                  /* real collisions the unfinished requests still need */
+  int64_t work_done;                  /* real collisions made by all requests so far */
+  int64_t epochs;                     /* epochs completed */
+} swarm_server_stats_t;
 
 typedef struct swarm_server* swarm_server_t;
 
@@ -443,6 +455,8 @@ swarm_status swarm_server_poll(swarm_server_t s, int64_t ticket, swarm_tallies_t
                                swarm_request_info* info);
 /* Block until every submitted request has finished. */
 swarm_status swarm_server_drain(swarm_server_t s);
+/* Queue and progress counters (e.g. the backlog against time under overload). */
+swarm_status swarm_server_stats(swarm_server_t s, swarm_server_stats_t* out);
 /* Seconds on the server clock (the clock of swarm_request_info). */
 double swarm_server_now(swarm_server_t s);
 /* Stop the server: the running epoch ends, every request that has not finished is

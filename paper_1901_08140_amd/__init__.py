@@ -95,7 +95,13 @@ class swarm_server_params(ctypes.Structure):
 
 class swarm_request_info(ctypes.Structure):
     _fields_ = [("submit_s", _d), ("admit_s", _d), ("done_s", _d), ("n_real", _i64), ("epochs", _i64),
-                ("bytes", _i64)]
+                ("bytes", _i64), ("progress", _i64)]
+
+
+class swarm_server_stats_t(ctypes.Structure):
+    _fields_ = [("time_s", _d), ("n_submitted", _i64), ("n_pending", _i64), ("n_active", _i64),
+                ("n_finished", _i64), ("n_failed", _i64), ("bytes_in_use", _i64), ("work_left", _i64),
+                ("work_done", _i64), ("epochs", _i64)]
 
 
 RECORD_DTYPE = np.dtype({
@@ -147,6 +153,7 @@ _SIGS = {
     "swarm_server_poll": (_i32, [_vp, _i64, _P(swarm_tallies_t), _P(swarm_request_info)]),
     "swarm_server_drain": (_i32, [_vp]),
     "swarm_server_now": (_d, [_vp]),
+    "swarm_server_stats": (_i32, [_vp, _P(swarm_server_stats_t)]),
     "swarm_server_destroy": (None, [_vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -463,6 +470,12 @@ def swarm_server_poll(s, ticket):
 
 def swarm_server_drain(s):
     return _check(_lib.swarm_server_drain(s))
+
+
+def swarm_server_stats(s):
+    t = swarm_server_stats_t()
+    _check(_lib.swarm_server_stats(s, ctypes.byref(t)))
+    return {k: getattr(t, k) for k, _ in swarm_server_stats_t._fields_}
 
 
 def swarm_server_now(s):

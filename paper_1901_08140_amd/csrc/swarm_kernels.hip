@@ -408,8 +408,31 @@ __global__ void k_build_constants(InstanceDesc* desc) {
       d.rel_p2 = sum > 0.0 ? l2s / sum : 0.5;
       d.rel_K = sum > 0.0 ? l1s * l2s / sum : 0.0;
     }
-    d.c_eps_f = static_cast<float>(d.c_eps);
-    d.c_speed_f = static_cast<float>(d.c_speed);
+    // FP32 velocity <-> energy constants.  A lane's speed after a collision is c_speed
+    // sqrt(eps'), and the next trials read its energy back as c_eps (vx^2 + vy^2) + (sceps vz)^2.
+    // With each constant rounded on its own, that round trip loses 1e-7 of the energy per
+    // collision, which a gas losing little energy per collision (2 m/M) accumulates into a
+    // mean-energy bias of 1e-7 M/(2m).  c_speed is moved by at most 16 units in the last place
+    // so that c_eps c_speed^2 and (sceps c_speed)^2 both equal 1 to about 1e-8.
+    {
+      const float base = static_cast<float>(d.c_speed);
+      float best_cs = base, best_sc = static_cast<float>(sqrt(d.c_eps)), best_ce = static_cast<float>(d.c_eps);
+      double best_r = 1e300;
+      float cs = base;
+      for (int i = 0; i < 16; ++i) cs = nextafterf(cs, 0.0f);
+      for (int i = 0; i <= 32; ++i, cs = nextafterf(cs, 1e30f)) {
+        const double c = static_cast<double>(cs);
+        const float sc = static_cast<float>(1.0 / c);
+        const float ce = static_cast<float>(1.0 / (c * c));
+        const double r1 = fabs(static_cast<double>(ce) * c * c - 1.0);
+        const double r2 = fabs(static_cast<double>(sc) * static_cast<double>(sc) * c * c - 1.0);
+        const double r = fmax(r1, r2);
+        if (r < best_r) { best_r = r; best_cs = cs; best_sc = sc; best_ce = ce; }
+      }
+      d.c_speed_f = best_cs;
+      d.c_eps_f = best_ce;
+      d.sceps_f = best_sc;
+    }
     d.speed0_f = static_cast<float>(d.speed0);
     d.az_f = static_cast<float>(d.az);
     d.omega_rev_f = static_cast<float>(d.omega / (2.0 * kPi));
@@ -417,8 +440,7 @@ __global__ void k_build_constants(InstanceDesc* desc) {
     d.bz_f = static_cast<float>(d.bz);
     d.vDy_f = static_cast<float>(d.vDy);
     d.apar_f = static_cast<float>(d.apar);
-    const double sc = sqrt(d.c_eps);
-    d.sceps_f = static_cast<float>(sc);
+    const double sc = static_cast<double>(d.sceps_f);
     d.aze_f = static_cast<float>(d.az * sc);
     d.apare_f = static_cast<float>(d.apar * sc);
     d.nup24_f = d.majorant_f * 0x1.0p-24f;

@@ -87,7 +87,10 @@ struct swarm_server {
   int max_slots = 0;
   TallyPlan tally;
   double rate = 0.0;   // measured real collisions per second (adaptive quantum)
-  int64_t epoch = 0;   // epochs run so far
+  int64_t epoch = 0;   // epochs started so far (failure injection counts them)
+  int64_t n_epochs = 0;     // epochs completed
+  int64_t work_done = 0;    // real collisions made by all requests so far
+  int64_t n_ok = 0, n_failed = 0;
   int64_t fail_epoch = 0;   // tests: epoch number that reports a device failure (0 = none)
 
   double now() const {
@@ -165,6 +168,8 @@ void finish(swarm_server* s, const std::shared_ptr<Request>& r, swarm_status st)
   std::lock_guard<std::mutex> lk(s->mu);
   r->status = st;
   r->done_s = s->now();
+  if (st == SWARM_OK) ++s->n_ok;
+  else ++s->n_failed;
   if (r->h) {
     swarm_destroy(r->h);
     r->h = nullptr;
@@ -360,7 +365,17 @@ void scheduler(swarm_server* s) {
         fin_desc.push_back(descs[i]);
       }
     }
-    for (auto& r : act) r->done_coll = std::min<int64_t>(r->n_c, r->done_coll + q);
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      for (auto& r : act) {
+        // every unfinished electron of the request made exactly the epoch's quantum (or the
+        // rest of its budget): the progress is exact at epoch boundaries
+        const int64_t nd = std::min<int64_t>(r->n_c, r->done_coll + q);
+        s->work_done += r->n_e * (nd - r->done_coll);
+        r->done_coll = nd;
+      }
+      ++s->n_epochs;
+    }
     if (ms > 0) {
       const double r_now = static_cast<double>(work) / (ms * 1e-3);
       s->rate = s->rate > 0 ? 0.5 * s->rate + 0.5 * r_now : r_now;
@@ -531,6 +546,7 @@ swarm_status swarm_server_poll(swarm_server_t s, int64_t ticket, swarm_tallies_t
     info->n_real = r.status == SWARM_OK ? r.tallies.n_real : 0;
     info->epochs = r.epochs;
     info->bytes = r.bytes;
+    info->progress = r.n_e * r.done_coll;
   }
   if (r.status == SWARM_PENDING) return SWARM_PENDING;
   if (r.status != SWARM_OK) return fail(r.status, "request %lld failed", static_cast<long long>(ticket));
@@ -546,6 +562,25 @@ swarm_status swarm_server_drain(swarm_server_t s) {
 }
 
 double swarm_server_now(swarm_server_t s) { return s ? s->now() : 0.0; }
+
+swarm_status swarm_server_stats(swarm_server_t s, swarm_server_stats_t* out) {
+  if (!s || !out) return fail(SWARM_ERR_INVALID_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  swarm_server_stats_t t{};
+  t.time_s = s->now();
+  t.n_submitted = s->next_ticket - 1;
+  t.n_pending = static_cast<int64_t>(s->pending.size());
+  t.n_active = static_cast<int64_t>(s->active.size());
+  t.n_finished = s->n_ok;
+  t.n_failed = s->n_failed;
+  t.bytes_in_use = s->used_bytes;
+  t.work_done = s->work_done;
+  for (const auto& r : s->pending) t.work_left += r->n_e * r->n_c;
+  for (const auto& r : s->active) t.work_left += r->n_e * (r->n_c - r->done_coll);
+  t.epochs = s->n_epochs;
+  *out = t;
+  return SWARM_OK;
+}
 
 void swarm_server_destroy(swarm_server_t s) {
   if (!s) return;

@@ -63,3 +63,44 @@ def tally_agreement(a, b, keys=PARITY_KEYS, k=3.0, rel=0.005):
         if abs(va - vb) > allowed:
             bad.append((key, va, vb, allowed))
     return bad
+
+
+PAIRED_KEYS = ["W", "mean_energy", "mean_energy_after", "D", "DL", "DT", "alpha"]
+
+
+def per_electron(rec):
+    """Per-electron contributions to the mean-type tallies of the finished electrons (dummy
+    mode: every electron makes the same number of collisions, so the mean energies are means
+    of sum/k too), each with its own run's drift velocity in the displacement."""
+    fin = (rec["flags"] & 1) != 0
+    rec = rec[fin]
+    r, t = rec["r"], rec["t"]
+    k = (rec["k_end"].astype(np.int64) - rec["k_start"]).astype(float)
+    wz = np.mean(r[:, 2] / t)
+    dz = r[:, 2] - t * wz
+    dp2 = r[:, 0] ** 2 + r[:, 1] ** 2
+    return rec["id"], {"W": -r[:, 2] / t, "mean_energy": rec["sum_eps"] / k, "mean_energy_after": rec["sum_epsp"] / k,
+                       "D": (dz ** 2 + dp2) / t, "DL": dz ** 2 / (2 * t), "DT": dp2 / (4 * t),
+                       "alpha": rec["G"] / -r[:, 2]}
+
+
+def paired_bias(rec_a, rec_b, keys=PAIRED_KEYS):
+    """Bias of run a against run b on the same electrons (same ids, same random streams):
+    {key: (mean_a - mean_b, its standard error from the per-electron paired differences,
+    mean_b)}.  Runs that share streams are strongly correlated, so the paired error is far
+    below that of two independent estimates."""
+    a, b = sort_by_id(rec_a), sort_by_id(rec_b)
+    ida, qa = per_electron(a)
+    idb, qb = per_electron(b)
+    assert np.array_equal(ida, idb), "the runs finished different electrons"
+    out = {}
+    for key in keys:
+        d = qa[key] - qb[key]
+        out[key] = (float(np.mean(d)), float(np.std(d, ddof=1) / math.sqrt(len(d))), float(np.mean(qb[key])))
+    return out
+
+
+def paired_bias_failures(pb, k=4.0, floor=2e-5):
+    """Keys whose bias exceeds k paired standard errors plus floor x |value|."""
+    return [(key, bias, sig, ref) for key, (bias, sig, ref) in pb.items()
+            if not abs(bias) <= k * sig + floor * abs(ref)]

@@ -48,7 +48,7 @@ def test_struct_sizes_match_the_oracle_layout():
 
 
 STRUCTS = ["swarm_channel", "swarm_component", "swarm_params", "swarm_stat", "swarm_tallies_t", "swarm_job",
-           "swarm_launch_opts", "swarm_server_params", "swarm_request_info"]
+           "swarm_launch_opts", "swarm_server_params", "swarm_request_info", "swarm_server_stats_t"]
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")

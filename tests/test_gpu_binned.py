@@ -188,3 +188,21 @@ def test_invalid_binned_refused(gpu):
     for bins, grace in ((101, 10), (-1, 10), (10, -3)):
         with pytest.raises(sw.SwarmError):
             sw.Swarm.from_config(_bin(synth.cfg2_argon_sweep()[3], bins, grace), sw.SWARM_FP64)
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32"])
+def test_tallies_flag_inexact_strategies_and_count_failed_retries(gpu, precision):
+    """The tallies say whether the run used the exact constant trial frequency, and count the
+    electrons whose binned retry failed again (record flag 16)."""
+    sw = gpu
+    base = synth.cfg2_argon_sweep()[12]
+    for cfg, strategy in ((base, 0), (base.scaled(trial_strategy=1), 1), (_bin(base, 10, 50), 2)):
+        s = sw.Swarm.from_config(cfg, precision)
+        s.run(4000, 800, 6)
+        T = s.tallies()
+        assert T["trial_strategy"] == strategy
+        assert T["exact"] == (1 if strategy == 0 else 0)
+        n16 = int(((s.records()["flags"] & 16) != 0).sum())
+        assert T["n_retry_failed"] == n16
+        if strategy == 2:
+            assert n16 > 0

@@ -12,7 +12,7 @@ import pytest
 import oracle
 import synth
 from oracle.tallies import tallies as oracle_tallies
-from swarm_testutil import compare_events, compare_records, tally_agreement
+from swarm_testutil import compare_events, compare_records, paired_bias, paired_bias_failures, tally_agreement
 
 pytestmark = pytest.mark.gpu
 
@@ -128,6 +128,9 @@ def test_fp32_real_secondaries_statistics(gpu):
     assert abs(T["n_electrons"] / O["n_electrons"] - 1) < 0.05
 
 
+# systematic FP32 allowance of the paired-bias check (relative; see test_fp32_tallies_within_tolerance)
+FP32_FLOOR = 3e-4
+
 FP32_CASES = [
     ("maxwell", lambda: synth.cfg1_maxwell(), 1000, 10000),
     ("argon-1Td", lambda: synth.cfg2_argon_sweep()[0], 2000, 4000),
@@ -140,14 +143,43 @@ FP32_CASES = [
 
 @pytest.mark.parametrize("name,mk,n_e,n_c", FP32_CASES, ids=[c[0] for c in FP32_CASES])
 def test_fp32_tallies_within_tolerance(gpu, name, mk, n_e, n_c):
+    """FP32-mixed against the FP64 oracle on the same electrons and streams: every tally within
+    the stated tolerance (3 combined sigma + 0.5%), and its FP32 bias within 4 standard errors
+    of the per-electron paired differences plus 3e-4 relative, the systematic error of binary32
+    rounding: about 7e-8 of the energy per collision, accumulated over the 1/(2m/M) collisions
+    a gas needs to relax its energy (the Maxwell gas, M = 4 u: -2e-4 in the mean energy).  The
+    paired errors are far below independent ones where the two precisions keep the same event
+    sequence, and there the same check flags a 0.1% bias planted in the FP32 drift velocity."""
     sw = gpu
     cfg = mk()
     s, _ = _gpu_run(sw, cfg, sw.SWARM_FP32_MIXED, n_e, n_c, 11)
     T = s.tallies()
-    O = oracle_tallies(oracle.OracleModel.from_config(cfg).run(n_e, n_c, 11).records)
+    ref = oracle.OracleModel.from_config(cfg).run(n_e, n_c, 11).records
+    O = oracle_tallies(ref)
     bad = tally_agreement(T, O)
     assert not bad, bad
     assert abs(T["efficiency"] / O["efficiency"] - 1) < 0.01
+    rec = s.records()
+    pb = paired_bias(rec, ref)
+    assert not paired_bias_failures(pb, floor=FP32_FLOOR), paired_bias_failures(pb, floor=FP32_FLOOR)
+    bias, sig, w = pb["W"]
+    if 4 * sig + FP32_FLOOR * abs(w) < 1e-3 * abs(w):
+        planted = rec.copy()
+        planted["r"] = planted["r"] * 1.001        # every z/t, so W, up by 0.1%
+        assert [k for k, *_ in paired_bias_failures(paired_bias(planted, ref, ["W"]), floor=FP32_FLOOR)] == ["W"]
+
+
+def test_fp32_bias_is_resolved_where_streams_stay_in_step(gpu):
+    """Where FP32 and FP64 keep the same event sequence (the Maxwell gas; argon at 1000 Td), the
+    paired error of W is small enough (4 sigma + the FP32 allowance below 0.08%) that a planted 0.1%
+    bias in the FP32 W cannot pass."""
+    sw = gpu
+    for mk, n_e, n_c in ((lambda: synth.cfg1_maxwell(), 1000, 10000), (lambda: synth.cfg2_argon_sweep()[31], 2000, 4000)):
+        cfg = mk()
+        s, _ = _gpu_run(sw, cfg, sw.SWARM_FP32_MIXED, n_e, n_c, 11)
+        pb = paired_bias(s.records(), oracle.OracleModel.from_config(cfg).run(n_e, n_c, 11).records, ["W"])
+        bias, sig, w = pb["W"]
+        assert 4 * sig + FP32_FLOOR * abs(w) < 0.8e-3 * abs(w), (cfg.label, sig / w)
 
 
 def test_fp32_tracks_fp64_streams(gpu):
