@@ -524,6 +524,7 @@ struct Consts {
   const ChannelDev* chan;
   const double* logtab;    // FP64: the logarithm table of the flight times, in LDS
   const ThermalChannel* chan_th;
+  bool cum_lds;            // the running sums are staged in LDS (else: global memory)
   const int32_t* bin_of;   // binned: bin of every padded table entry
   const R* bin_nup;        // binned: nu' of every bin
 };
@@ -569,6 +570,7 @@ __device__ __forceinline__ Consts<R> load_consts(const InstanceDesc& d) {
   c.key = {static_cast<uint32_t>(d.seed), static_cast<uint32_t>(d.seed >> 32)};
   c.chan = d.chan;
   c.chan_th = d.chan_th;
+  c.cum_lds = false;
   c.off1 = c.off - 1;
   c.off1G = c.off1 + c.G;
   return c;
@@ -1378,9 +1380,22 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
     lo = C.nc - 1;
     if (C.nc > 1) {
       const int last = C.nc - 2;
-      typename Pair<R>::T q[kScanChannels - 1];
+      using PT = typename Pair<R>::T;
+      PT q[kScanChannels - 1];
+      if (C.cum_lds) {
 #pragma unroll
-      for (int c = 0; c < kScanChannels - 1; ++c) q[c] = row[min(c, last)];
+        for (int c = 0; c < kScanChannels - 1; ++c) q[c] = row[min(c, last)];
+      } else {
+        // global memory: one address and immediate offsets (the table has kScanChannels
+        // spare pairs after its last row, so entries past the row stay inside the buffer)
+        const __attribute__((address_space(1))) PT* grow =
+            (const __attribute__((address_space(1))) PT*)(row);
+#pragma unroll
+        for (int c = 0; c < kScanChannels - 1; ++c) {
+          q[c].x = grow[c].x;
+          q[c].y = grow[c].y;
+        }
+      }
 #pragma unroll
       for (int c = kScanChannels - 2; c >= 0; --c)
         if (c <= last && x < lerp_pair(q[c], w)) lo = c;
@@ -1588,7 +1603,10 @@ __global__ void __launch_bounds__(512) k_swarm_dummy(const InstanceDesc* __restr
     Consts<R> C = load_consts<R>(d);
     C.chan = s_ch;
     C.logtab = s_logtab;
-    if (cum_off >= 0) C.cum = reinterpret_cast<const PT*>(smem + cum_off);
+    if (cum_off >= 0) {
+      C.cum = reinterpret_cast<const PT*>(smem + cum_off);
+      C.cum_lds = true;
+    }
     const int64_t count = wi.count;
     Lane<R> L;
     L.state = ST_IDLE;
@@ -1839,7 +1857,10 @@ __global__ void __launch_bounds__(512) k_swarm_pooled(const InstanceDesc* __rest
     Consts<R> C = load_consts<R>(d);
     C.chan = s_ch;
     C.logtab = s_logtab;
-    if (cum_off >= 0) C.cum = reinterpret_cast<const PT*>(smem + cum_off);
+    if (cum_off >= 0) {
+      C.cum = reinterpret_cast<const PT*>(smem + cum_off);
+      C.cum_lds = true;
+    }
     if (server) {
       // ---- service waves: the same three barriers per round as the trial waves ----
       for (int round = 0;; ++round) {
@@ -1979,7 +2000,10 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
   Consts<R> C = load_consts<R>(d);
   C.chan = s_ch;
   C.logtab = s_logtab;
-  if (cum_off >= 0) C.cum = reinterpret_cast<const PT*>(smem + cum_off);
+  if (cum_off >= 0) {
+      C.cum = reinterpret_cast<const PT*>(smem + cum_off);
+      C.cum_lds = true;
+    }
   RunCounters* ctr = d.ctr;
   const int64_t N = d.n_electrons;
   const int64_t child_cap = d.capacity - N;
