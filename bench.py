@@ -38,6 +38,18 @@ sys.path.insert(0, ROOT)
 # (3), FP64 energy sums, position and time (16), new velocity (6), next-flight constants (4).
 OPS_PER_TRIAL = 40
 OPS_PER_REAL = 113
+# The FP64 path, counted the same way (FP64 FMA issues at the full lane rate on gfx950, so the
+# same lane-slot peak applies).  Trial (82): a full Philox call for the HI and one for the LO
+# words per block (40 per trial), 1 - u exactly from the 53-bit uniform (5), the table-driven
+# logarithm and the flight-time update (20: exponent and mantissa 2, table index and address 3,
+# reduction 1, series to r^9 9, exponent and table terms 4, scaled add 1), x = R nu' (4), energy
+# (3), grid position (7), interpolation and compare (3).  Real collision (184): the HI and LO
+# scattering calls (80), channel search (12), onset compare (1), isotropic direction with
+# binary64 sqrt and sincospi (42), cos(theta) with its square root and division (21), energy
+# transfer (3), energy sums, position and time (8), new speed and velocity (13), next-flight
+# constants (4).
+OPS_PER_TRIAL_FP64 = 82
+OPS_PER_REAL_FP64 = 184
 PEAK_LANE_OPS = 256 * 64 * 2.4e9      # 256 CUs x 64 FP32 lanes/clock x 2.4 GHz = 3.93e13 /s
 
 
@@ -617,8 +629,14 @@ def main():
         sw.swarm_batch_launch(b64)
         ms64 = sw.swarm_batch_wait(b64)
         sw.swarm_batch_destroy(b64)
+        trials64 = sum(t["n_real"] + t["n_null"] + t["n_forbidden"] + t["n_fail"] for t in tall64)
+        ach64 = (trials64 * OPS_PER_TRIAL_FP64 + real64 * OPS_PER_REAL_FP64) / (ms64 * 1e-3)
         out["fp64_batched"] = {"value": real64 / (ms64 * 1e-3), "unit": "real collisions/s",
-                               "device_ms": ms64}
+                               "device_ms": ms64,
+                               "roofline": {"bound": "alu", "achieved": ach64 / 1e9, "peak": PEAK_LANE_OPS / 1e9,
+                                            "unit": "Gop/s", "frac": ach64 / PEAK_LANE_OPS,
+                                            "kernel": "k_swarm_dummy<double,false,false,0>",
+                                            "ops_per_trial": OPS_PER_TRIAL_FP64, "ops_per_real": OPS_PER_REAL_FP64}}
         del h64
 
     if args.serve_seconds > 0 and args.serve_rate > 0:
