@@ -1210,6 +1210,35 @@ __device__ __forceinline__ void draw_scattering(Lane<R>& L, const Consts<R>& C) 
 
 // Outcome of serving a pending candidate.
 constexpr int kScanChannels = 8;   // up to this many channels, selection scans the whole row
+
+// Few channels (2 <= nc <= N + 1): the first c with x < C_c(eps), or nc - 1 (the last channel
+// needs no test), by a backward scan over the row of running sums fetched at once.  The loads
+// are unconditional so that they all issue before the first wait: one memory round trip.  From
+// global memory they use one address and immediate offsets (the table keeps kScanChannels
+// spare pairs after its last row, so entries past the row stay inside the buffer); from LDS the
+// indices are clamped to the row.
+template <typename R, int N>
+__device__ __forceinline__ int first_channel_below(const Consts<R>& C, const typename Pair<R>::T* row, R x, R w) {
+  using PT = typename Pair<R>::T;
+  const int last = C.nc - 2;
+  PT q[N];
+  if (C.cum_lds) {
+#pragma unroll
+    for (int c = 0; c < N; ++c) q[c] = row[min(c, last)];
+  } else {
+    const __attribute__((address_space(1))) PT* grow = (const __attribute__((address_space(1))) PT*)(row);
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      q[c].x = grow[c].x;
+      q[c].y = grow[c].y;
+    }
+  }
+  int lo = C.nc - 1;
+#pragma unroll
+  for (int c = N - 1; c >= 0; --c)
+    if (c <= last && x < lerp_pair(q[c], w)) lo = c;
+  return lo;
+}
 enum : int { RC_CONTINUE = 0, RC_STOP = 1 };
 
 // Moving targets (section "Effect of gas temperature").  The target velocity of collision k
@@ -1370,36 +1399,14 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
   const bool over = gi >= C.G;
   const int g = min(max(gi - 1, 0), C.G - 1);
   const R w = (gi >= 1 && !over) ? L.p_w : R(0);
-  const typename Pair<R>::T* row = C.cum + static_cast<int64_t>(g) * C.nc;
+  const typename Pair<R>::T* row = C.cum + g * C.nc;    // G nc < 2^31: a 32-bit offset
   int lo;
-  if (C.nc <= kScanChannels) {
-    // few channels: fetch the whole row at once and take the first c with x < C_c(eps) by a
-    // backward scan; the last channel needs no test.  The loads are unconditional (indices
-    // clamped to the row), so that they all issue before the first wait: one memory round
-    // trip.
-    lo = C.nc - 1;
-    if (C.nc > 1) {
-      const int last = C.nc - 2;
-      using PT = typename Pair<R>::T;
-      PT q[kScanChannels - 1];
-      if (C.cum_lds) {
-#pragma unroll
-        for (int c = 0; c < kScanChannels - 1; ++c) q[c] = row[min(c, last)];
-      } else {
-        // global memory: one address and immediate offsets (the table has kScanChannels
-        // spare pairs after its last row, so entries past the row stay inside the buffer)
-        const __attribute__((address_space(1))) PT* grow =
-            (const __attribute__((address_space(1))) PT*)(row);
-#pragma unroll
-        for (int c = 0; c < kScanChannels - 1; ++c) {
-          q[c].x = grow[c].x;
-          q[c].y = grow[c].y;
-        }
-      }
-#pragma unroll
-      for (int c = kScanChannels - 2; c >= 0; --c)
-        if (c <= last && x < lerp_pair(q[c], w)) lo = c;
-    }
+  if (C.nc == 1) {
+    lo = 0;
+  } else if (C.nc <= 5) {
+    lo = first_channel_below<R, 4>(C, row, x, w);     // the argon-like gas: 5 channels
+  } else if (C.nc <= kScanChannels) {
+    lo = first_channel_below<R, kScanChannels - 1>(C, row, x, w);
   } else {
     // many channels: bisection on the running sums, which do not decrease with c
     lo = 0;
