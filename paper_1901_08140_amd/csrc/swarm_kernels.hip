@@ -200,11 +200,13 @@ __device__ __forceinline__ void rotate_dir(R a, R b, R c, R cos_t, R u_phi, R* n
   }
 }
 
-// Isotropic unit vector: cos(Theta) = 1 - 2u, Phi = 2 pi u'.
+// Isotropic unit vector: cos(Theta) = 1 - 2u, Phi = 2 pi u'.  With u a multiple of the
+// precision's 2^-24 or 2^-53 below 1, 1 - 2u, 1 - ct = 2u and 1 + ct are exact and not
+// negative, so one FMA forms ct and sin(Theta) needs no clamp.
 template <typename R>
 __device__ __forceinline__ void iso_dir(R uc, R up, R* nx, R* ny, R* nz) {
-  const R ct = R(1) - R(2) * uc;
-  const R st = sqrt_(fmax((R)0, (R(1) - ct) * (R(1) + ct)));
+  const R ct = fma_(R(-2), uc, R(1));
+  const R st = sqrt_((R(1) - ct) * (R(1) + ct));
   R s, c;
   sincos_rev(up, &s, &c);
   *nx = st * c;
@@ -518,6 +520,8 @@ struct Consts {
   int G, nc, off, p;
   int off1;      // off - 1: raw index of entry 0 of the padded LDS table
   int off1G;     // off1 + G: raw index of its last entry
+  float e_lo, e_hi;   // FP32: the float just below 2^emin, and 2^emax (the clamp of the index;
+                      // e_hi is held in a vector register, see load_consts)
   uint32_t n_coll, quantum;
   Key key;
   const typename Pair<R>::T* cum;
@@ -573,6 +577,12 @@ __device__ __forceinline__ Consts<R> load_consts(const InstanceDesc& d) {
   c.cum_lds = false;
   c.off1 = c.off - 1;
   c.off1G = c.off1 + c.G;
+  c.e_lo = __uint_as_float((static_cast<uint32_t>(127 + d.emin) << 23) - 1u);
+  // The median-of-three of the index clamp can read one scalar operand only; a copy the
+  // compiler cannot rematerialise keeps the other bound in a vector register for the whole
+  // work item instead of a move in every trial.
+  const float e_hi = __uint_as_float(static_cast<uint32_t>(127 + d.emax) << 23);
+  asm("v_mov_b32 %0, %1" : "=v"(c.e_hi) : "s"(e_hi));
   return c;
 }
 
@@ -628,7 +638,8 @@ __device__ __forceinline__ void set_id(Lane<R>& L, const Consts<R>& C, uint64_t 
 template <typename R, bool HB>
 __device__ __forceinline__ void set_anchor(Lane<R>& L, const Consts<R>& C) {
   if (!HB || !C.magnetic) {
-    L.q0 = L.vx * L.vx + L.vy * L.vy;
+    if constexpr (sizeof(R) == 4) L.q0 = fmaf(L.vy, L.vy, L.vx * L.vx);
+    else L.q0 = L.vx * L.vx + L.vy * L.vy;
     if constexpr (sizeof(R) == 4) {
       L.e_q0 = C.c_eps * L.q0;
       L.e_vz = C.sceps * L.vz;
@@ -822,23 +833,35 @@ __device__ __forceinline__ R energy_at(const Lane<R>& L, const Consts<R>& C, R T
 // exponent and leading mantissa bits, and w = frac(2 P mant) = frac((2 mant - 1) P) (the
 // product by the power of two 2P is exact).  The raw index (exponent and leading mantissa
 // bits, clamped to [off1, off1 + G]) is returned; the padded index is raw - off1, and the
-// table is read through a base moved back by off1 entries (one address instruction).
+// table is read through a base moved back by off1 entries (one address instruction).  A
+// negative energy (the rounding of a near-zero one in the expanded magnetic form) takes entry
+// 0, as below the grid.  With MED3 the FP32 trial clamps the energy instead, to [the float
+// below 2^emin, 2^emax], whose indices are off1 and off1 + G: one median-of-three instead of
+// a maximum and a minimum, for a vector register that holds the upper bound (taken where the
+// kernel has one to spare: B = 0 with the constant trial frequency).
+template <bool MED3 = false>
 __device__ __forceinline__ int raw_index(float eps, const Consts<float>& C) {
-  return min(max(static_cast<int>(__float_as_uint(eps) >> (23 - C.p)), C.off1), C.off1G);
+  if constexpr (MED3)
+    return static_cast<int>(__float_as_uint(__builtin_amdgcn_fmed3f(eps, C.e_lo, C.e_hi)) >> (23 - C.p));
+  else
+    return min(max(static_cast<int>(__float_as_uint(eps)) >> (23 - C.p), C.off1), C.off1G);
 }
+template <bool MED3 = false>
 __device__ __forceinline__ int raw_index(double eps, const Consts<double>& C) {
-  const uint32_t hi = static_cast<uint32_t>(static_cast<uint64_t>(__double_as_longlong(eps)) >> 32);
-  return min(max(static_cast<int>(hi >> (20 - C.p)), C.off1), C.off1G);
+  const int32_t hi = static_cast<int32_t>(static_cast<uint64_t>(__double_as_longlong(eps)) >> 32);
+  return min(max(hi >> (20 - C.p), C.off1), C.off1G);    // arithmetic shift: negative -> entry 0
 }
+template <bool MED3 = false>
 __device__ __forceinline__ float lds_rate(const float2* __restrict__ s_nu, float eps, const Consts<float>& C,
                                          int* raw_out, float* w_out) {
-  const int raw = raw_index(eps, C);
+  const int raw = raw_index<MED3>(eps, C);
   const float w = __builtin_amdgcn_fractf(__builtin_amdgcn_frexp_mantf(eps) * C.twoPf);
   const float2 q = (s_nu - C.off1)[raw];
   *raw_out = raw;
   *w_out = w;
   return fmaf(w, q.y, q.x);
 }
+template <bool MED3 = false>
 __device__ __forceinline__ double lds_rate(const double2* __restrict__ s_nu, double eps, const Consts<double>& C,
                                           int* raw_out, double* w_out) {
   const int raw = raw_index(eps, C);
@@ -1152,7 +1175,7 @@ __device__ __forceinline__ bool one_trial(Lane<R>& L, const Consts<R>& C,
     L.p_x = uni(hr, lr, R(0)) * (EXT ? L.nup : C.nup);
   }
   L.p_eps = energy_at<R, HB, EXT>(L, C, L.T);
-  const R nu = lds_rate(s_nu, L.p_eps, C, &L.p_gi, &L.p_w);
+  const R nu = lds_rate<!HB && EXT == 0>(s_nu, L.p_eps, C, &L.p_gi, &L.p_w);
   // Not null when x < nu.  That includes nu > nu' (then x < nu' < nu), a fail of an
   // adaptive strategy, which the collision phase tells apart.
   const bool hit = L.p_x < nu;
@@ -1435,8 +1458,10 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
     if constexpr (sizeof(R) == 8) {
       e64 = eps;
     } else {
+      // the squares of binary32 components are exact in binary64, so the FMAs round as the
+      // plain sum does
       const double dx = vx, dy = vy, dz = vz;
-      e64 = d.c_eps * (dx * dx + dy * dy + dz * dz);
+      e64 = d.c_eps * fma(dz, dz, fma(dy, dy, dx * dx));
     }
     if (e64 < ch.onset) return forbidden_pick<R, TR, EXT>(d, L, C, lo, eps, nu_eps);
   }
@@ -1450,13 +1475,15 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
   if (EXT == 2 && C.thermal) {
     moving_target_outcome<R>(ch, C, eps, u_c, u_p, vx, vy, vz, vcm, g2, &nx, &ny, &nz, &epsp);
   } else {
-    const R v2 = vx * vx + vy * vy + vz * vz;
+    R v2;
+    if constexpr (sizeof(R) == 8) v2 = vx * vx + vy * vy + vz * vz;
+    else v2 = fmaf(vz, vz, fmaf(vy, vy, vx * vx));
     R cos_t;
     if (ch.scat == SWARM_SCATTER_ISOTROPIC || !(v2 > R(0))) {
       // isotropic in the lab frame; theta is the angle to the incoming velocity
       iso_dir<R>(u_c, u_p, &nx, &ny, &nz);
       if constexpr (sizeof(R) == 8) cos_t = v2 > 0.0 ? (nx * vx + ny * vy + nz * vz) / sqrt(v2) : 0.0;
-      else cos_t = v2 > 0.0f ? (nx * vx + ny * vy + nz * vz) * rsqrt_(v2) : 0.0f;
+      else cos_t = v2 > 0.0f ? fmaf(nz, vz, fmaf(ny, vy, nx * vx)) * rsqrt_(v2) : 0.0f;
     } else {
       // anisotropic: theta about the incoming direction, azimuth 2 pi u'
       R xi;
