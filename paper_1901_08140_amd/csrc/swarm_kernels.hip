@@ -171,12 +171,13 @@ __device__ __forceinline__ double scatter_cos(int scat, double xi, double eps, d
   }
   return 1.0 - 2.0 * u * (1.0 - xi) / (1.0 + xi * (1.0 - 2.0 * u));
 }
+// (FP32: the quotient through the hardware reciprocal, within an ulp of the division)
 __device__ __forceinline__ float scatter_cos(int scat, float xi, float eps, float u) {
   if (scat == SWARM_SCATTER_SCREENED_COULOMB) {
     const float e = eps * static_cast<float>(1.0 / kHartreeEV);
-    return 1.0f - 2.0f * u / (1.0f + 8.0f * e * (1.0f - u));
+    return 1.0f - 2.0f * u * __builtin_amdgcn_rcpf(1.0f + 8.0f * e * (1.0f - u));
   }
-  return 1.0f - 2.0f * u * (1.0f - xi) / (1.0f + xi * (1.0f - 2.0f * u));
+  return 1.0f - 2.0f * u * (1.0f - xi) * __builtin_amdgcn_rcpf(1.0f + xi * (1.0f - 2.0f * u));
 }
 
 // The unit vector at polar angle theta (cos given) and azimuth 2 pi u_phi about the unit
@@ -193,6 +194,27 @@ __device__ __forceinline__ void rotate_dir(R a, R b, R c, R cos_t, R u_phi, R* n
     *nx = a * cos_t + sin_t * (a * c * cp - b * sp) / s;
     *ny = b * cos_t + sin_t * (b * c * cp + a * sp) / s;
     *nz = c * cos_t - s * sin_t * cp;
+  } else {
+    *nx = sin_t * cp;
+    *ny = sin_t * sp;
+    *nz = c * cos_t;
+  }
+}
+// FP32: 1/s from the hardware reciprocal square root and s = s^2 (1/s), instead of a square
+// root and two divisions
+template <>
+__device__ __forceinline__ void rotate_dir<float>(float a, float b, float c, float cos_t, float u_phi,
+                                                  float* nx, float* ny, float* nz) {
+  const float sin_t = sqrt_(fmaxf(0.0f, (1.0f - cos_t) * (1.0f + cos_t)));
+  float sp, cp;
+  sincos_rev(u_phi, &sp, &cp);
+  const float s2 = fmaf(b, b, a * a);
+  if (s2 > 0.0f) {
+    const float inv = rsqrt_(s2);
+    const float k = sin_t * inv;
+    *nx = fmaf(a, cos_t, k * (a * c * cp - b * sp));
+    *ny = fmaf(b, cos_t, k * (b * c * cp + a * sp));
+    *nz = fmaf(c, cos_t, -(s2 * inv) * sin_t * cp);
   } else {
     *nx = sin_t * cp;
     *ny = sin_t * sp;
@@ -1322,21 +1344,21 @@ __device__ __forceinline__ void moving_target_outcome(const ChannelDev& ch, cons
                                                       R* nx, R* ny, R* nz, R* epsp) {
   if constexpr (sizeof(R) == 4) {
     const float cx = static_cast<float>(vcm[0]), cy = static_cast<float>(vcm[1]), cz = static_cast<float>(vcm[2]);
+    // (unit vectors through the hardware reciprocal square root)
     const float ux = vx - cx, uy = vy - cy, uz = vz - cz;
-    const float g = sqrt_(ux * ux + uy * uy + uz * uz);
+    const float gg = fmaf(uz, uz, fmaf(uy, uy, ux * ux));
     float hx, hy, hz;
-    if (ch.scat == SWARM_SCATTER_ISOTROPIC || !(g > 0.0f)) {
+    if (ch.scat == SWARM_SCATTER_ISOTROPIC || !(gg > 0.0f)) {
       iso_dir<float>(u_c, u_p, &hx, &hy, &hz);
     } else {
-      const float ig = 1.0f / g;
+      const float ig = rsqrt_(gg);
       rotate_dir<float>(ux * ig, uy * ig, uz * ig, scatter_cos(ch.scat, ch.xi_f, eps, u_c), u_p, &hx, &hy, &hz);
     }
     const float sp = sqrt_(fmaxf(static_cast<float>(g2), 0.0f));
     const float px = cx + hx * sp, py = cy + hy * sp, pz = cz + hz * sp;
-    const float p2 = px * px + py * py + pz * pz;
-    const float s1 = sqrt_(p2);
-    if (s1 > 0.0f) {
-      const float is = 1.0f / s1;
+    const float p2 = fmaf(pz, pz, fmaf(py, py, px * px));
+    if (p2 > 0.0f) {
+      const float is = rsqrt_(p2);
       *nx = px * is; *ny = py * is; *nz = pz * is;
     } else {
       *nx = hx; *ny = hy; *nz = hz;
