@@ -58,7 +58,7 @@ DeviceInfo& device_info() {
 
 // Dynamic LDS of the swarm kernels: the total-rate pairs of the G grid nodes plus one
 // padding entry in front, then (16-byte aligned) the nc channel descriptors, then with table
-// layout 1 the G x nc running-sum pairs (if everything fits the work-group's LDS), then with
+// layout 1 the (G+1) x nc running-sum pairs (if everything fits the work-group's LDS), then with
 // the pooled schedule the candidate pool (64 slots per service wave).
 LdsLayout lds_layout(int precision, int G, int nc, int service_waves, int table_layout) {
   auto al = [](size_t n) { return (n + 15) & ~static_cast<size_t>(15); };
@@ -70,7 +70,7 @@ LdsLayout lds_layout(int precision, int G, int nc, int service_waves, int table_
   l.cum_off = -1;
   l.pool_off = static_cast<int>(after_ch);
   if (table_layout == 1) {
-    const size_t with_cum = al(after_ch + (static_cast<size_t>(G) * static_cast<size_t>(nc) + 8) * pair);
+    const size_t with_cum = al(after_ch + (static_cast<size_t>(G + 1) * static_cast<size_t>(nc) + 8) * pair);
     if (static_cast<int64_t>(with_cum + pool) <= device_info().lds_per_block) {
       l.cum_off = static_cast<int>(after_ch);
       l.pool_off = static_cast<int>(with_cum);
@@ -452,9 +452,9 @@ static swarm_status build_swarm(swarm* h, const swarm_component* comps, int32_t 
   const size_t b_nodes = al(static_cast<size_t>(G) * 8);
   const size_t b_cm = al(static_cast<size_t>(G) * nc * 8);
   const size_t b_nu64 = al(static_cast<size_t>(G) * 16), b_nu32 = al(static_cast<size_t>(G) * 8);
-  // running sums, node major, with spare pairs after the last row (the channel search reads a
-  // whole row of up to 8 pairs at once)
-  const size_t b_c64 = al((static_cast<size_t>(G) * nc + 8) * 16), b_c32 = al((static_cast<size_t>(G) * nc + 8) * 8);
+  // running sums, node major, padded with a row in front (below the grid), with spare pairs
+  // after the last row (the channel search reads a whole row of up to 8 pairs at once)
+  const size_t b_c64 = al((static_cast<size_t>(G + 1) * nc + 8) * 16), b_c32 = al((static_cast<size_t>(G + 1) * nc + 8) * 8);
   const size_t b_ch = al(nc * sizeof(ChannelDev)), b_th = al(nc * sizeof(ThermalChannel));
   const size_t b_eb = al(entry_bin.size() * 4), b_bf = al(bin_first.size() * 4);
   const size_t b_bn = al(static_cast<size_t>(d.n_bins) * 8), b_bn32 = al(static_cast<size_t>(d.n_bins) * 4);

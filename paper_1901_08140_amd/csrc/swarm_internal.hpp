@@ -118,7 +118,7 @@ struct InstanceDesc {
   double* cum_cm;             // nc x G running sums, channel major (FP64)
   double2* nu64;              // G pairs (F, F[g+1]-F[g]) of the total rate
   float2* nu32;
-  double2* cum64;             // G x nc pairs, node major
+  double2* cum64;             // (G+1) x nc pairs, node major (row 0: below the grid), + 8 spare
   float2* cum32;
   ChannelDev* chan;
   ThermalChannel* chan_th;    // moving targets: per-channel constants (nc)

@@ -313,7 +313,10 @@ __global__ void k_build_rates(InstanceDesc* desc) {
   d.nodes[g] = eps;
 }
 
-// Pairs (F[g], F[g+1]-F[g]) of every running sum (node major) and of the total rate.
+// Pairs (F[g], F[g+1]-F[g]) of every running sum (node major) and of the total rate.  The
+// running sums are padded like the LDS table of the total rate: row 0 holds (F[0], 0) for
+// energies below the grid, row g+1 node g, and row G (the top node, difference zero) serves
+// energies at or above the top, so the padded index of a trial selects the row directly.
 __global__ void k_build_pairs(InstanceDesc* desc) {
   const InstanceDesc& d = *desc;
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -322,8 +325,12 @@ __global__ void k_build_pairs(InstanceDesc* desc) {
   const double* F = d.cum_cm + static_cast<size_t>(c) * d.G;
   const double f0 = F[g];
   const double df = g + 1 < d.G ? F[g + 1] - f0 : 0.0;
-  d.cum64[idx] = make_double2(f0, df);
-  d.cum32[idx] = make_float2(static_cast<float>(f0), static_cast<float>(df));
+  d.cum64[idx + d.nc] = make_double2(f0, df);
+  d.cum32[idx + d.nc] = make_float2(static_cast<float>(f0), static_cast<float>(df));
+  if (g == 0) {
+    d.cum64[c] = make_double2(f0, 0.0);
+    d.cum32[c] = make_float2(static_cast<float>(f0), 0.0f);
+  }
   if (c == d.nc - 1) {
     d.nu64[g] = make_double2(f0, df);
     d.nu32[g] = make_float2(static_cast<float>(f0), static_cast<float>(df));
@@ -1438,13 +1445,14 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
       return RC_CONTINUE;
     }
   }
-  // node and weight of the candidate (entry 0 of the padded index is below the grid, entry
-  // G at or above its top; both use a constant value there)
+  // row and weight of the candidate: the running sums are padded as the total rate is (row 0
+  // below the grid, row G at or above its top, both with zero differences), so the trial's
+  // padded index and weight select them without clamps (the weight is zeroed above the grid
+  // only because that keeps the magnetic adaptive kernels at 128 registers)
   const int gi = L.p_gi - C.off1;
   const bool over = gi >= C.G;
-  const int g = min(max(gi - 1, 0), C.G - 1);
-  const R w = (gi >= 1 && !over) ? L.p_w : R(0);
-  const typename Pair<R>::T* row = C.cum + g * C.nc;    // G nc < 2^31: a 32-bit offset
+  const R w = over ? R(0) : L.p_w;
+  const typename Pair<R>::T* row = C.cum + gi * C.nc;   // (G+1) nc < 2^31: a 32-bit offset
   int lo;
   if (C.nc == 1) {
     lo = 0;
@@ -1607,7 +1615,7 @@ __device__ __forceinline__ void stage_cum(const InstanceDesc& d, unsigned char* 
   const PT* src = reinterpret_cast<const PT*>(sizeof(R) == 8 ? static_cast<const void*>(d.cum64)
                                                              : static_cast<const void*>(d.cum32));
   PT* dst = reinterpret_cast<PT*>(smem + cum_off);
-  const int n = d.G * d.nc;
+  const int n = (d.G + 1) * d.nc;
   for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
 }
 
