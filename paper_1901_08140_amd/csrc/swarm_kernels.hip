@@ -317,6 +317,9 @@ __global__ void k_build_rates(InstanceDesc* desc) {
 // running sums are padded like the LDS table of the total rate: row 0 holds (F[0], 0) for
 // energies below the grid, row g+1 node g, and row G (the top node, difference zero) serves
 // energies at or above the top, so the padded index of a trial selects the row directly.
+// The FP32 differences are stored times 2^-(23-p), because the FP32 weight is taken as the
+// integer of the low 23-p mantissa bits (see lds_rate): an exact power-of-two scale, so every
+// product w (F[g+1]-F[g]) keeps its value to the bit.
 __global__ void k_build_pairs(InstanceDesc* desc) {
   const InstanceDesc& d = *desc;
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -325,15 +328,16 @@ __global__ void k_build_pairs(InstanceDesc* desc) {
   const double* F = d.cum_cm + static_cast<size_t>(c) * d.G;
   const double f0 = F[g];
   const double df = g + 1 < d.G ? F[g + 1] - f0 : 0.0;
+  const float df32 = static_cast<float>(df) * ldexpf(1.0f, d.p_log2 - 23);
   d.cum64[idx + d.nc] = make_double2(f0, df);
-  d.cum32[idx + d.nc] = make_float2(static_cast<float>(f0), static_cast<float>(df));
+  d.cum32[idx + d.nc] = make_float2(static_cast<float>(f0), df32);
   if (g == 0) {
     d.cum64[c] = make_double2(f0, 0.0);
     d.cum32[c] = make_float2(static_cast<float>(f0), 0.0f);
   }
   if (c == d.nc - 1) {
     d.nu64[g] = make_double2(f0, df);
-    d.nu32[g] = make_float2(static_cast<float>(f0), static_cast<float>(df));
+    d.nu32[g] = make_float2(static_cast<float>(f0), df32);
   }
 }
 
@@ -551,6 +555,7 @@ struct Consts {
   int off1G;     // off1 + G: raw index of its last entry
   float e_lo, e_hi;   // FP32: the float just below 2^emin, and 2^emax (the clamp of the index;
                       // e_hi is held in a vector register, see load_consts)
+  uint32_t wmask;     // FP32: the low 23-p mantissa bits (the interpolation weight, unscaled)
   uint32_t n_coll, quantum;
   Key key;
   const typename Pair<R>::T* cum;
@@ -606,6 +611,7 @@ __device__ __forceinline__ Consts<R> load_consts(const InstanceDesc& d) {
   c.cum_lds = false;
   c.off1 = c.off - 1;
   c.off1G = c.off1 + c.G;
+  c.wmask = (1u << (23 - d.p_log2)) - 1u;
   c.e_lo = __uint_as_float((static_cast<uint32_t>(127 + d.emin) << 23) - 1u);
   // The median-of-three of the index clamp can read one scalar operand only; a copy the
   // compiler cannot rematerialise keeps the other bound in a vector register for the whole
@@ -860,7 +866,9 @@ __device__ __forceinline__ R energy_at(const Lane<R>& L, const Consts<R>& C, R T
 // node, whose difference is zero) energies at or above 2^emax, so the clamped index needs
 // no select on the weight.  Index and weight are exact: the node index comes from the
 // exponent and leading mantissa bits, and w = frac(2 P mant) = frac((2 mant - 1) P) (the
-// product by the power of two 2P is exact).  The raw index (exponent and leading mantissa
+// product by the power of two 2P is exact).  FP32 takes the weight as the integer of the low
+// 23-p mantissa bits, w 2^(23-p), against differences stored times 2^-(23-p): the same
+// products, one instruction fewer.  The raw index (exponent and leading mantissa
 // bits, clamped to [off1, off1 + G]) is returned; the padded index is raw - off1, and the
 // table is read through a base moved back by off1 entries (one address instruction).  A
 // negative energy (the rounding of a near-zero one in the expanded magnetic form) takes entry
@@ -884,7 +892,7 @@ template <bool MED3 = false>
 __device__ __forceinline__ float lds_rate(const float2* __restrict__ s_nu, float eps, const Consts<float>& C,
                                          int* raw_out, float* w_out) {
   const int raw = raw_index<MED3>(eps, C);
-  const float w = __builtin_amdgcn_fractf(__builtin_amdgcn_frexp_mantf(eps) * C.twoPf);
+  const float w = static_cast<float>(__float_as_uint(eps) & C.wmask);
   const float2 q = (s_nu - C.off1)[raw];
   *raw_out = raw;
   *w_out = w;
