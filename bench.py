@@ -28,15 +28,16 @@ sys.path.insert(0, ROOT)
 # B = 0 (full-rate VALU instruction = 1 slot; transcendentals log/sqrt/rsqrt/sin/cos = 2, as
 # measured on gfx950; 32x32->64 integer multiply-add = 1, also measured full rate; a
 # three-input xor = 1, gfx950 has it as one instruction).
-# Trial (40): half a Philox4x32-10 call (20 multiply-adds + 20 three-input xors per call),
+# Trial (38): half a Philox4x32-10 call (20 multiply-adds + 20 three-input xors per call),
 # the flight time from the 24-bit uniform (shift, convert, 1 - u by one FMA, log, FMA: 4 +
-# log), x = R nu' (3), |v(T)|^2 m/2e (2 FMA), octave-grid position from the bits (shift,
-# clamp 2, address 1, mantissa, scale, fraction: 7), interpolated rate and compare (2).  Real
-# collision
-# (113): one Philox call for the scattering block (40), channel search over the running sums
+# log), x = R nu' (3), |v(T)|^2 m/2e (2 FMA), octave-grid position from the bits (clamp of
+# the energy by one median-of-three, shift, address, and the weight as the masked low
+# mantissa bits converted: 5), interpolated rate and compare (2).  (Until the kernel found the
+# median-of-three clamp and the integer weight, the grid position counted 7 and the trial 40.)
+# Real collision (113): one Philox call for the scattering block (40), channel search over the running sums
 # (12), onset compare in FP64 (8), isotropic direction (16), cos(theta) (6), energy transfer
 # (3), FP64 energy sums, position and time (16), new velocity (6), next-flight constants (4).
-OPS_PER_TRIAL = 40
+OPS_PER_TRIAL = 38
 OPS_PER_REAL = 113
 # The FP64 path, counted the same way (FP64 FMA issues at the full lane rate on gfx950, so the
 # same lane-slot peak applies).  Trial (82): a full Philox call for the HI and one for the LO
