@@ -236,6 +236,18 @@ __device__ __forceinline__ void iso_dir(R uc, R up, R* nx, R* ny, R* nz) {
   *nz = ct;
 }
 
+// The same from the scattering word in FP32: 1 - 2u = 1 - (w >> 8) 2^-23 by one FMA, exact
+// as above, so the result equals iso_dir's to the bit.
+__device__ __forceinline__ void iso_dir_u24(uint32_t w, float up, float* nx, float* ny, float* nz) {
+  const float ct = fmaf(static_cast<float>(w >> 8), -0x1.0p-23f, 1.0f);
+  const float st = sqrt_((1.0f - ct) * (1.0f + ct));
+  float s, c;
+  sincos_rev(up, &s, &c);
+  *nx = st * c;
+  *ny = st * s;
+  *nz = ct;
+}
+
 template <typename R> struct Pair;
 template <> struct Pair<float> { using T = float2; };
 template <> struct Pair<double> { using T = double2; };
@@ -536,6 +548,7 @@ template <typename R>
 struct Consts {
   R nup, cT, c_eps, c_speed, speed0, az, omega, bx, bz, vDy, apar;
   R omega_rev;   // omega / (2 pi): the gyration phase in revolutions
+  R inv_omega;   // 1 / omega (B > 0), divided once per work item instead of per collision
   R aze, apare;  // accelerations in energy units (FP32: times sqrt(m/2e); FP64: plain)
   R nup24;       // FP32: nu' 2^-24 (x = R nu' straight from the 24-bit integer)
   R Pf, twoPf;   // grid points per octave, and twice that, as floating point
@@ -591,6 +604,7 @@ __device__ __forceinline__ Consts<R> load_consts(const InstanceDesc& d) {
     c.Pf = d.Pf_f; c.twoPf = d.twoPf_f;
   }
   c.magnetic = d.B > 0.0;
+  c.inv_omega = c.magnetic ? R(1) / c.omega : R(0);
   c.variable = d.trial_strategy != SWARM_TRIAL_CONSTANT;
   c.binned = d.trial_strategy == SWARM_TRIAL_BINNED;
   c.thermal = d.thermal_targets != 0;
@@ -1068,7 +1082,7 @@ __device__ __forceinline__ void move_full(const Lane<R>& L, const Consts<R>& C, 
     *vy = ((R(0) + R(0) * T) + C.vDy) + (L.u0y * c + L.w0y * s);
     *vz = ((pz + az * T) + R(0)) + (L.u0z * c + L.w0z * s);
     const R hT2 = R(0.5) * T * T;
-    const R inv_w = R(1) / C.omega;
+    const R inv_w = C.inv_omega;
     const R dx = ((px + R(0)) * T + ax * hT2) + (L.u0x * s + L.w0x * omc) * inv_w;
     const R dy = ((R(0) + C.vDy) * T + R(0) * hT2) + (L.u0y * s + L.w0y * omc) * inv_w;
     const R dz = ((pz + R(0)) * T + az * hT2) + (L.u0z * s + L.w0z * omc) * inv_w;
@@ -1519,7 +1533,8 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
     R cos_t;
     if (ch.scat == SWARM_SCATTER_ISOTROPIC || !(v2 > R(0))) {
       // isotropic in the lab frame; theta is the angle to the incoming velocity
-      iso_dir<R>(u_c, u_p, &nx, &ny, &nz);
+      if constexpr (sizeof(R) == 4) iso_dir_u24(h.x, u_p, &nx, &ny, &nz);
+      else iso_dir<R>(u_c, u_p, &nx, &ny, &nz);
       if constexpr (sizeof(R) == 8) cos_t = v2 > 0.0 ? (nx * vx + ny * vy + nz * vz) / sqrt(v2) : 0.0;
       else cos_t = v2 > 0.0f ? fmaf(nz, vz, fmaf(ny, vy, nx * vx)) * rsqrt_(v2) : 0.0f;
     } else {
