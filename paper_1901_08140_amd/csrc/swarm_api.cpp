@@ -379,7 +379,7 @@ int default_block(int) { return 128; }
 swarm_launch_opts resolve_opts(const swarm_launch_opts* o, int precision) {
   swarm_launch_opts r{};
   r.block_size = (o && o->block_size) ? o->block_size : default_block(precision);
-  r.chunk = (o && o->chunk) ? o->chunk : r.block_size * 8;
+  r.chunk = (o && o->chunk) ? o->chunk : r.block_size * 3;   // three electrons per lane per item
   r.pending_trigger = (o && o->pending_trigger) ? o->pending_trigger : 32;
   r.use_graph = o ? o->use_graph : 0;
   r.block_size = std::max(64, std::min(1024, (r.block_size / 64) * 64));

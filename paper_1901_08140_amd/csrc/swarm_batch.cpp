@@ -256,7 +256,7 @@ swarm_status swarm_autotune(swarm_t* handles, const swarm_job* jobs, int32_t n, 
   for (int bs : {128, 256, 512}) {
     swarm_launch_opts o = cur;
     o.block_size = bs;
-    o.chunk = bs * 8;
+    o.chunk = bs * 3;
     if ((st = time_it(o, &t)) != SWARM_OK) return st;
     if (t < best_t) { best_t = t; cur = o; }
   }
@@ -268,7 +268,7 @@ swarm_status swarm_autotune(swarm_t* handles, const swarm_job* jobs, int32_t n, 
     if (t < best_t) { best_t = t; cur = o; }
   }
   const swarm_launch_opts base2 = cur;
-  for (int mult : {4, 8, 16, 32}) {
+  for (int mult : {2, 3, 4, 8}) {
     swarm_launch_opts o = base2;
     o.chunk = base2.block_size * mult;
     if ((st = time_it(o, &t)) != SWARM_OK) return st;
