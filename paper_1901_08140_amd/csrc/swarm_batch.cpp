@@ -253,10 +253,11 @@ swarm_status swarm_autotune(swarm_t* handles, const swarm_job* jobs, int32_t n, 
   swarm_status st = time_it(cur, &t);   // warm-up
   if (st != SWARM_OK) return st;
   double best_t = 1e300;
+  const int per_lane = cur.chunk / cur.block_size;   // the precision's default
   for (int bs : {128, 256, 512}) {
     swarm_launch_opts o = cur;
     o.block_size = bs;
-    o.chunk = bs * 3;
+    o.chunk = bs * per_lane;
     if ((st = time_it(o, &t)) != SWARM_OK) return st;
     if (t < best_t) { best_t = t; cur = o; }
   }
