@@ -530,7 +530,9 @@ def main():
     handles = [h.h for h in h32]
     opts = {"use_graph": 1}
     if args.autotune:
-        best = sw.swarm_autotune(handles, jobs, 300)
+        # probe budgets of a fifth of the run's: short probes misjudge the end of the launch
+        # (the tail of the last work items), which the work-item size is about
+        best = sw.swarm_autotune(handles, jobs, max(300, args.collisions // 5))
         opts.update(best)
         opts["use_graph"] = 1
         log(args, "autotuned launch options", opts)

@@ -389,16 +389,19 @@ void make_items(const std::vector<int64_t>& n_e, const std::vector<int64_t>& n_c
   }
 }
 
-// Default launch shape (the autotuner's usual pick on MI355X for the argon-like sweep).
-int default_block(int) { return 128; }
+// Default launch shape (the autotuner's pick on MI355X for the argon-like sweep, probed with
+// a fifth of the collision budget): work-groups of 256, items of 4 electrons per lane in FP32
+// and 8 in FP64.  Against 128 lanes and 3 per lane the FP32 step went 833 -> 789 ms, and FP64
+// with 8 per lane 2409 -> 2131 ms (32 x 1e5 x 2e4).
+int default_block(int) { return 256; }
 
 swarm_launch_opts resolve_opts(const swarm_launch_opts* o, int precision) {
   swarm_launch_opts r{};
   r.block_size = (o && o->block_size) ? o->block_size : default_block(precision);
-  // electrons per lane and work item: FP32 3, FP64 8 (measured on the argon sweep, the
+  // electrons per lane and work item: FP32 4, FP64 8 (measured on the argon sweep, the
   // 256-instance batch and serving: small items balance uneven work; the slower FP64 lanes
   // lose more to the wait for the slowest lane at every item boundary)
-  r.chunk = (o && o->chunk) ? o->chunk : r.block_size * (precision == SWARM_FP64 ? 8 : 3);
+  r.chunk = (o && o->chunk) ? o->chunk : r.block_size * (precision == SWARM_FP64 ? 8 : 4);
   r.pending_trigger = (o && o->pending_trigger) ? o->pending_trigger : 32;
   r.use_graph = o ? o->use_graph : 0;
   r.block_size = std::max(64, std::min(1024, (r.block_size / 64) * 64));
@@ -553,7 +556,12 @@ static swarm_status build_swarm(swarm* h, const swarm_component* comps, int32_t 
   if (h->desc.built_ok != 1) return fail(SWARM_ERR_DEVICE, "table build did not complete");
   for (int i = 0; i < 3; ++i)
     if ((e = hipEventCreate(&h->ev[i])) != hipSuccess) return hip_fail(e, "hipEventCreate");
-  h->opts = resolve_opts(nullptr, params->precision);
+  // Single runs default to work-groups of 128: a run of one swarm often holds fewer electrons
+  // than the GPU has lanes, and the smaller groups spread it over more CUs (32 single FP64
+  // runs of the argon sweep, 1e5 electrons each: 1.21e10 real/s with 128, 1.07e10 with 256).
+  swarm_launch_opts single{};
+  single.block_size = 128;
+  h->opts = resolve_opts(&single, params->precision);
   return SWARM_OK;
 }
 
