@@ -80,7 +80,7 @@ def parse():
     ap.add_argument("--no-batch256", action="store_true",
                     help="skip the 256-instance batch leg")
     ap.add_argument("--serve-rate", type=float, default=50.0,
-                    help="requests per second of the serving leg (the config-5 stream is 50/s)")
+                    help="requests per second of the serving leg (the random-mixture request stream is stated at 50/s)")
     ap.add_argument("--serve-seconds", type=float, default=40.0,
                     help="arrival window of the serving leg; measured at its end")
     ap.add_argument("--serve-schedule", type=int, default=1,
@@ -184,23 +184,23 @@ def cpu_baseline(sw, args):
     """The oracle as it stands, on the host cores (one thread per core of the process's
     affinity), on three bounded samples of the workloads, each beside the GPU's FP64 and
     FP32-mixed single runs of the same electrons:
-      config 1 in full: Maxwell gas, 1000 electrons x 10,000 collisions, 10 Td;
-      config-2 subset: electrons 0..999 at E/N indices 0, 10, 21, 31 of the argon sweep
+      the Maxwell gas in full: 1000 electrons x 10,000 collisions, 10 Td;
+      an argon-sweep subset: electrons 0..999 at E/N indices 0, 10, 21, 31 of the sweep
         (1, 9.3, 108, 1000 Td), 20,000 collisions each;
-      config-3 subset: primaries 0..999 of the argon:CO2 mixture (100 Td, 1 T at 45 deg) with
+      a mixture subset: primaries 0..999 of the argon:CO2 mixture (100 Td, 1 T at 45 deg) with
         real secondaries, lineage-complete at a 2000-collision budget.
-    `value` is the config-2 subset (the bench workload's gas)."""
+    `value` is the argon-sweep subset (the bench workload's gas)."""
     import oracle
     import synth
     import torch
     threads = max(1, len(os.sched_getaffinity(0)))
     sweep = synth.cfg2_argon_sweep()
     samples = [
-        ("config 1 in full: Maxwell gas, 1000 e x 10000 collisions, 10 Td, dummy",
+        ("Maxwell gas in full: 1000 e x 10000 collisions, 10 Td, dummy",
          [synth.cfg1_maxwell()], 1000, 10_000),
-        ("config-2 subset: ids 0..999 x 20000 collisions at 1, 9.3, 108, 1000 Td of the argon sweep, dummy",
+        ("argon-sweep subset: ids 0..999 x 20000 collisions at 1, 9.3, 108, 1000 Td, dummy",
          [sweep[i] for i in (0, 10, 21, 31)], 1000, 20_000),
-        ("config-3 subset: primaries 0..999 of the argon:CO2 mixture, 100 Td, 1 T at 45 deg, real "
+        ("mixture subset: primaries 0..999 of the argon:CO2 mixture, 100 Td, 1 T at 45 deg, real "
          "secondaries, lineage-complete at 2000 collisions",
          [synth.cfg3_mixture_real(n_electrons=1000, n_collisions=2000)], 1000, 2000),
     ]
@@ -247,7 +247,7 @@ def cpu_baseline(sw, args):
 
 
 def serve(sw, args):
-    """The config-5 request stream (random mixtures of 1-6 components, E/N 1-1000 Td, |B| 0-2 T,
+    """The random-mixture request stream (random mixtures of 1-6 components, E/N 1-1000 Td, |B| 0-2 T,
     1e3-1e6 electrons x 1e3-1e5 collisions) arriving as a Poisson process at --serve-rate over an
     arrival window of --serve-seconds into the continuous-batching server (HBM budget 200 GB,
     FP32-mixed).  Measured at the end of the window: the requests completed in it and their

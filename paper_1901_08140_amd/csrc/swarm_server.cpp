@@ -279,12 +279,14 @@ void scheduler(swarm_server* s) {
     }
     if (act.empty()) continue;
     if (s->p.schedule == SWARM_SCHEDULE_SHORTEST_FIRST && act.size() > 1) act = pick_shortest_first(act);
-    // epoch quantum: fixed, or sized so that an epoch lasts about 50 ms at the measured rate
+    // epoch quantum: fixed, or sized so that an epoch lasts about 100 ms at the measured rate
+    // (a stream of random-mixture requests at 50 req/s over 40 s: 1.22e10 real/s served with 50 ms epochs, 1.30e10
+    // with 100 ms, 1.32e10 with 200 ms; p50 1.27-1.31 s for all three, p99 20.9/19.3/19.0 s)
     int64_t electrons = 0, max_nc = 0;
     for (auto& r : act) { electrons += r->n_e; max_nc = std::max(max_nc, r->n_c); }
     int64_t q = s->p.quantum_collisions;
     if (q <= 0) {
-      q = s->rate > 0 ? static_cast<int64_t>(0.05 * s->rate / std::max<int64_t>(1, electrons)) : 1000;
+      q = s->rate > 0 ? static_cast<int64_t>(0.1 * s->rate / std::max<int64_t>(1, electrons)) : 1000;
       q = std::max<int64_t>(64, q);
     }
     q = std::min<int64_t>(q, max_nc);   // no electron of the epoch needs more
