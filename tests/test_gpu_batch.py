@@ -40,8 +40,11 @@ def test_batch_equals_single_runs(gpu, precision):
         s.run(ne, nc, seed)
         singles.append((s.records(), s.tallies()))
     hs = [sw.Swarm.from_config(c, precision) for c in cfgs]
+    # the default shape, one electron per lane and item, large items, and items of 8 per lane
+    # whose last share is cut into items of 2 per lane
     variants = [dict(), dict(block_size=128, chunk=128, pending_trigger=1),
-                dict(block_size=512, chunk=512 * 16, pending_trigger=64, use_graph=1)]
+                dict(block_size=512, chunk=512 * 16, pending_trigger=64, use_graph=1),
+                dict(block_size=256, chunk=256 * 8, pending_trigger=40)]
     for opts in variants:
         sw.swarm_batch_run([h.h for h in hs], jobs, opts)
         for h, (rec, tal) in zip(hs, singles):
