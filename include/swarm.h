@@ -382,17 +382,20 @@ swarm_status swarm_autotune(swarm_t* handles, const swarm_job* jobs, int32_t n,
 /* Which admitted requests an epoch advances. */
 typedef enum {
   SWARM_SCHEDULE_ALL = 0,             /* every admitted request in every epoch */
-  SWARM_SCHEDULE_SHORTEST_FIRST = 1   /* the least remaining work (electrons x collisions left)
+  SWARM_SCHEDULE_SHORTEST_FIRST = 1   /* the least remaining device work (electrons x
+                                         collisions left x the measured work per collision)
                                          first, until the epoch holds about 10240 electrons per
                                          compute unit, plus always the earliest admitted request
-                                         and the one with the most collisions per electron left:
+                                         and the one with the most work per electron left:
                                          lower median latency under overload, at some throughput */
 } swarm_schedule;
 
 typedef struct {
   int64_t hbm_budget_bytes;   /* admission limit on device memory held by requests */
   int32_t precision;          /* swarm_precision of every request */
-  int64_t quantum_collisions; /* real collisions per electron per scheduling epoch */
+  int64_t quantum_collisions; /* real collisions per electron per scheduling epoch; 0 = per
+                                 request, sized so that an epoch lasts about 100 ms and every
+                                 electron does about the same device work in it */
   int32_t max_active;         /* instances per epoch (0 = 1024) */
   swarm_launch_opts opts;
   void* stream;               /* hipStream_t or NULL */
@@ -426,8 +429,9 @@ typedef struct swarm_server* swarm_server_t;
 /* A server owns a scheduler thread.  Requests are admitted while the device memory they
  * need fits the budget; admitted requests keep their tables and electron state resident
  * and advance together: each epoch is one persistent launch over the admitted requests the
- * schedule picks, in which every unfinished electron makes up to quantum_collisions more
- * real collisions.
+ * schedule picks, in which every unfinished electron makes up to its request's quantum of
+ * real collisions (quantum_collisions, or with 0 a per-request quantum: fewer collisions
+ * for a request whose gas draws more null trials per real collision).
  * Requests that arrive while an epoch runs join the next one.  Because electrons stop at
  * real-collision boundaries and the random streams are counter based, a request's
  * result does not depend on what it was batched with. */

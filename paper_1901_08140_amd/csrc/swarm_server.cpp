@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstdlib>
 #include <cstring>
@@ -58,6 +59,10 @@ struct Request {
   int64_t bytes = 0;
   int64_t epochs = 0;
   int64_t done_coll = 0;    // collisions per electron made so far (the epochs' quanta, capped)
+  int64_t quantum = 0;      // this epoch's collisions per electron
+  double cost = 0.0;        // device work per real collision in trial blocks, measured (0: no epoch yet)
+  uint64_t blocks_seen = 0; // trial blocks its electrons had drawn at its last measurement
+  int64_t coll_seen = 0;    // and its collisions per electron then
   double submit_s = 0, admit_s = 0, done_s = 0;
   swarm_status status = SWARM_PENDING;
   swarm_tallies_t tallies{};
@@ -83,10 +88,12 @@ struct swarm_server {
   std::thread th;
   // device state of the epochs
   DevBuf ctrs, descs, items;
+  DevBuf mdescs, mparts;    // the requests measured after an epoch and their block sums
   std::vector<int> free_slots;
   int max_slots = 0;
   TallyPlan tally;
-  double rate = 0.0;   // measured real collisions per second (adaptive quantum)
+  double rate = 0.0;   // measured real collisions per second (quantum before any cost is known)
+  double block_rate = 0.0;  // measured device work per second, in trial blocks (adaptive quanta)
   int64_t epoch = 0;   // epochs started so far (failure injection counts them)
   int64_t n_epochs = 0;     // epochs completed
   int64_t work_done = 0;    // real collisions made by all requests so far
@@ -227,19 +234,64 @@ void admit_pending(swarm_server* s) {
   }
 }
 
-// Shortest remaining work first: the admitted requests with the fewest electron-collisions
-// left, until the epoch holds about kEpochElectronsPerCu electrons per compute unit (enough
-// to fill the device).  Two more always run: the earliest admitted request, so that no
-// request waits forever behind a stream of small ones, and the one with the most
-// collisions per electron left, the longest chain of sequential work, so that it does not
-// end up running alone on an underfilled device.  Results do not depend on the schedule;
-// only which requests finish first does.
+// Shortest remaining work first: the admitted requests with the least device work left
+// (electron-collisions left times the measured work per collision), until the epoch holds
+// about kEpochElectronsPerCu electrons per compute unit (enough to fill the device).  Two
+// more always run: the earliest admitted request, so that no request waits forever behind a
+// stream of small ones, and the one with the most work per electron left, the longest chain
+// of sequential work, so that it does not end up running alone on an underfilled device.
+// Results do not depend on the schedule; only which requests finish first does.
 constexpr int64_t kEpochElectronsPerCu = 10240;
+
+// Serving accounting, one work-group of 256 per (part, request): the trial blocks drawn so far
+// by the electrons of request blockIdx.y (the block index in the resumable state of an
+// electron that has run and not finished, the record's count of one that has finished), as
+// kEpochBlocksParts partial sums that the host adds up.  Differences between measurements
+// give a request's blocks per real collision, from which its quantum is sized.
+constexpr int kEpochBlocksParts = 32;
+
+__global__ void __launch_bounds__(256) k_epoch_blocks(const InstanceDesc* __restrict__ descs,
+                                                      unsigned long long* __restrict__ out) {
+  __shared__ unsigned long long s_part[4];
+  const InstanceDesc& d = descs[blockIdx.y];
+  unsigned long long acc = 0ull;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; e < d.n_electrons;
+       e += static_cast<int64_t>(gridDim.x) * 256) {
+    const uint32_t st = d.saved[e].started;
+    acc += st == 1u ? d.saved[e].block : st == 2u ? d.records[e].blocks : 0ull;
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off);
+  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    out[static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x] = s_part[0] + s_part[1] + s_part[2] + s_part[3];
+}
+
+hipError_t launch_epoch_blocks(const InstanceDesc* descs, int n, unsigned long long* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_epoch_blocks, dim3(kEpochBlocksParts, static_cast<unsigned>(n)), dim3(256), 0, s, descs, out);
+  return hipGetLastError();
+}
+
+// Device work of a real collision in units of trial blocks: a collision pass serves about
+// two thirds of a wave and runs about 1.5 times the instructions of a trial block.
+constexpr double kCollisionBlocks = 1.5;
 
 std::vector<std::shared_ptr<Request>> pick_shortest_first(const std::vector<std::shared_ptr<Request>>& active) {
   const int64_t target = kEpochElectronsPerCu * device_info().n_cu;
-  auto left = [](const std::shared_ptr<Request>& r) { return r->n_e * (r->n_c - r->done_coll); };
-  auto chain = [](const std::shared_ptr<Request>& r) { return r->n_c - r->done_coll; };
+  // remaining device work: electron-collisions left times the measured work per collision
+  // (the mean over the measured requests for one without a measurement)
+  double mean = 0.0;
+  int n_mean = 0;
+  for (auto& r : active)
+    if (r->cost > 0) { mean += r->cost; ++n_mean; }
+  mean = n_mean > 0 ? mean / n_mean : 1.0;
+  auto left = [mean](const std::shared_ptr<Request>& r) {
+    return static_cast<double>(r->n_e * (r->n_c - r->done_coll)) * (r->cost > 0 ? r->cost : mean);
+  };
+  auto chain = [mean](const std::shared_ptr<Request>& r) {
+    return static_cast<double>(r->n_c - r->done_coll) * (r->cost > 0 ? r->cost : mean);
+  };
   std::vector<std::shared_ptr<Request>> out{active.front()};
   const auto longest = std::max_element(active.begin(), active.end(),
       [&](const std::shared_ptr<Request>& a, const std::shared_ptr<Request>& b) { return chain(a) < chain(b); });
@@ -279,17 +331,29 @@ void scheduler(swarm_server* s) {
     }
     if (act.empty()) continue;
     if (s->p.schedule == SWARM_SCHEDULE_SHORTEST_FIRST && act.size() > 1) act = pick_shortest_first(act);
-    // epoch quantum: fixed, or sized so that an epoch lasts about 100 ms at the measured rate
-    // (a stream of random-mixture requests at 50 req/s over 40 s: 1.22e10 real/s served with 50 ms epochs, 1.30e10
-    // with 100 ms, 1.32e10 with 200 ms; p50 1.27-1.31 s for all three, p99 20.9/19.3/19.0 s)
-    int64_t electrons = 0, max_nc = 0;
-    for (auto& r : act) { electrons += r->n_e; max_nc = std::max(max_nc, r->n_c); }
-    int64_t q = s->p.quantum_collisions;
-    if (q <= 0) {
-      q = s->rate > 0 ? static_cast<int64_t>(0.1 * s->rate / std::max<int64_t>(1, electrons)) : 1000;
-      q = std::max<int64_t>(64, q);
+    // epoch quanta: fixed, or sized so that an epoch lasts about 100 ms (a stream of
+    // random-mixture requests at 50 req/s over 40 s: 1.22e10 real/s served with 50 ms epochs,
+    // 1.30e10 with 100 ms, 1.32e10 with 200 ms; p50 1.27-1.31 s for all three).  Once trial
+    // blocks per real collision have been measured, every electron of the epoch gets about the
+    // same number of trial blocks: a request whose gas makes many null trials per real
+    // collision gets fewer real collisions, so that its electrons do not keep the device
+    // running for the others' tail.  A request without a measurement yet is given the largest
+    // cost measured, which bounds the tail its first epoch can make.
+    int64_t electrons = 0;
+    double worst = 0.0;
+    for (auto& r : act) { electrons += r->n_e; worst = std::max(worst, r->cost); }
+    const int64_t q_fixed = s->p.quantum_collisions;
+    const double blocks_per_electron = s->block_rate > 0 && worst > 0
+        ? 0.1 * s->block_rate / static_cast<double>(std::max<int64_t>(1, electrons)) : 0.0;
+    const int64_t q_rate = s->rate > 0 ? static_cast<int64_t>(0.1 * s->rate / std::max<int64_t>(1, electrons)) : 1000;
+    for (auto& r : act) {
+      int64_t q;
+      if (q_fixed > 0) q = q_fixed;
+      else if (blocks_per_electron > 0) q = static_cast<int64_t>(blocks_per_electron / (r->cost > 0 ? r->cost : worst));
+      else q = q_rate;
+      if (q_fixed <= 0) q = std::max<int64_t>(64, q);
+      r->quantum = std::max<int64_t>(1, std::min<int64_t>(q, r->n_c - r->done_coll));   // no electron needs more
     }
-    q = std::min<int64_t>(q, max_nc);   // no electron of the epoch needs more
     descs.clear();
     std::vector<int64_t> ne, nc;
     int G = 0, n_ch = 0;
@@ -297,10 +361,14 @@ void scheduler(swarm_server* s) {
     int extended = 0;
     for (auto& r : act) {
       InstanceDesc d = r->h->desc;
-      d.quantum = static_cast<uint32_t>(std::min<int64_t>(q, 0xffffffffLL));
+      d.quantum = static_cast<uint32_t>(std::min<int64_t>(r->quantum, 0xffffffffLL));
       descs.push_back(d);
       ne.push_back(r->n_e);
-      nc.push_back(std::min<int64_t>(q, r->n_c));   // this epoch's collisions per electron at most
+      // the items' order and sizes follow the expected device work per electron (longest
+      // first), not the collision count: with per-request quanta the requests with the
+      // fewest collisions per epoch are the slowest ones
+      const double c_r = r->cost > 0 ? r->cost : worst > 0 ? worst : 1.0;
+      nc.push_back(std::max<int64_t>(1, std::llround(16.0 * c_r * static_cast<double>(r->quantum))));
       G = std::max(G, d.G);
       n_ch = std::max(n_ch, d.nc);
       magnetic |= r->h->has_b;
@@ -336,6 +404,22 @@ void scheduler(swarm_server* s) {
     }
     // while the epoch runs, prepare the requests that arrived meanwhile
     if (ok) admit_pending(s);
+    // Requests measured after this epoch: on their epochs 1, 2, 4, 8, ... (their cost settles
+    // as their electrons relax from the initial energy), by one reduction over their state.
+    std::vector<size_t> meas;
+    for (size_t i = 0; i < act.size(); ++i)
+      if ((act[i]->epochs & (act[i]->epochs - 1)) == 0) meas.push_back(i);
+    std::vector<unsigned long long> parts(meas.size() * kEpochBlocksParts);
+    if (ok && !meas.empty()) {
+      std::vector<InstanceDesc> md;
+      for (size_t i : meas) md.push_back(descs[i]);
+      ok = (e = s->mdescs.ensure(md.size() * sizeof(InstanceDesc))) == hipSuccess &&
+           (e = s->mparts.ensure(parts.size() * sizeof(unsigned long long))) == hipSuccess &&
+           (e = hipMemcpyAsync(s->mdescs.p, md.data(), md.size() * sizeof(InstanceDesc), hipMemcpyHostToDevice, s->compute)) == hipSuccess &&
+           (e = launch_epoch_blocks(static_cast<const InstanceDesc*>(s->mdescs.p), static_cast<int>(md.size()),
+                                    static_cast<unsigned long long*>(s->mparts.p), s->compute)) == hipSuccess &&
+           (e = hipMemcpyAsync(parts.data(), s->mparts.p, parts.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s->compute)) == hipSuccess;
+    }
     std::vector<RunCounters> hc(s->max_slots);
     if (ok) ok = (e = hipMemcpyAsync(hc.data(), s->ctrs.p, s->max_slots * sizeof(RunCounters), hipMemcpyDeviceToHost, s->compute)) == hipSuccess &&
                  (e = hipStreamSynchronize(s->compute)) == hipSuccess;
@@ -360,7 +444,7 @@ void scheduler(swarm_server* s) {
     int64_t work = 0;
     for (size_t i = 0; i < act.size(); ++i) {
       const int64_t done_now = static_cast<int64_t>(hc[act[i]->slot].n_done);
-      work += std::min<int64_t>(q, act[i]->n_c) * act[i]->n_e;
+      work += act[i]->quantum * act[i]->n_e;
       if (done_now >= act[i]->n_e) {
         fin.push_back(act[i]);
         fin_n.push_back(act[i]->n_e);
@@ -372,15 +456,34 @@ void scheduler(swarm_server* s) {
       for (auto& r : act) {
         // every unfinished electron of the request made exactly the epoch's quantum (or the
         // rest of its budget): the progress is exact at epoch boundaries
-        const int64_t nd = std::min<int64_t>(r->n_c, r->done_coll + q);
+        const int64_t nd = std::min<int64_t>(r->n_c, r->done_coll + r->quantum);
         s->work_done += r->n_e * (nd - r->done_coll);
         r->done_coll = nd;
       }
       ++s->n_epochs;
     }
+    // the measured requests' cost: blocks drawn per real collision since their last
+    // measurement, plus the collision's own work
+    for (size_t j = 0; j < meas.size(); ++j) {
+      Request& r = *act[meas[j]];
+      unsigned long long total = 0;
+      for (int k = 0; k < kEpochBlocksParts; ++k) total += parts[j * kEpochBlocksParts + k];
+      const double db = static_cast<double>(total - r.blocks_seen);
+      const double made = static_cast<double>(r.n_e) * static_cast<double>(r.done_coll - r.coll_seen);
+      if (made > 0 && total > r.blocks_seen) r.cost = db / made + kCollisionBlocks;
+      r.blocks_seen = total;
+      r.coll_seen = r.done_coll;
+    }
     if (ms > 0) {
       const double r_now = static_cast<double>(work) / (ms * 1e-3);
       s->rate = s->rate > 0 ? 0.5 * s->rate + 0.5 * r_now : r_now;
+      // device work of the epoch in trial blocks, from the requests' costs as now measured
+      double units = 0.0, worst_now = 0.0;
+      for (auto& r : act) worst_now = std::max(worst_now, r->cost);
+      for (auto& r : act)
+        units += static_cast<double>(r->quantum) * static_cast<double>(r->n_e) * (r->cost > 0 ? r->cost : worst_now);
+      const double b_now = units / (ms * 1e-3);
+      if (b_now > 0) s->block_rate = s->block_rate > 0 ? 0.5 * s->block_rate + 0.5 * b_now : b_now;
     }
     if (!fin.empty()) {
       DevBuf fd;
@@ -440,7 +543,7 @@ swarm_status server_create(const swarm_server_params* p, void* arena, int64_t ar
   if (arena) {
     s->mem = std::make_unique<Arena>(arena, static_cast<size_t>(arena_bytes));
     s->budget = std::min<int64_t>(s->budget, static_cast<int64_t>(s->mem->capacity()));
-    for (DevBuf* b : {&s->ctrs, &s->descs, &s->items}) b->arena = s->mem.get();
+    for (DevBuf* b : {&s->ctrs, &s->descs, &s->items, &s->mdescs, &s->mparts}) b->arena = s->mem.get();
     s->tally.bind(s->mem.get());
   }
   s->t0 = std::chrono::steady_clock::now();

@@ -62,6 +62,28 @@ def test_alone_equals_in_the_mix(gpu, precision, schedule):
         sw.swarm_server_destroy(srv)
 
 
+@pytest.mark.parametrize("schedule", [0, 1], ids=["all", "shortest-first"])
+def test_per_request_quanta_give_the_single_run_bits(gpu, schedule):
+    """Quanta sized per request (quantum_collisions = 0: fewer real collisions per epoch for a
+    gas that draws more null trials per real collision, once that has been measured): requests
+    of the argon-like sweep from 1 to 1000 Td, served together over several epochs, give the
+    bits of their single runs."""
+    sw = gpu
+    sweep = synth.cfg2_argon_sweep(n_electrons=100_000, n_collisions=20_000)
+    reqs = [sweep[i] for i in (0, 10, 21, 31)]
+    alone = _alone(sw, reqs, sw.SWARM_FP32_MIXED)
+    srv = sw.swarm_server_create(64 << 30, sw.SWARM_FP32_MIXED, quantum_collisions=0, schedule=schedule)
+    try:
+        tickets = [sw.swarm_server_submit(srv, c.components, sw.params_from_config(c, 1), c.n_electrons,
+                                          c.n_collisions, c.seed) for c in reqs]
+        res = _wait_all(sw, srv, tickets)
+        for t, a in zip(tickets, alone):
+            assert res[t][0] == a
+        assert max(res[t][1]["epochs"] for t in tickets) >= 3
+    finally:
+        sw.swarm_server_destroy(srv)
+
+
 def _alone(sw, reqs, precision):
     out = []
     for c in reqs:
