@@ -409,6 +409,9 @@ typedef struct {
   int64_t bytes;                      /* device memory charged against the budget */
   int64_t progress;                   /* real collisions made so far (all its electrons; exact
                                          at epoch boundaries) */
+  double blocks_per_real;             /* trial blocks per real collision, as the server last
+                                         measured them to size the request's quantum (after
+                                         its epochs 1, 2, 4, 8, ...; 0 before the first) */
 } swarm_request_info;
 
 /* A snapshot of the server (swarm_server_stats). */

@@ -95,7 +95,7 @@ class swarm_server_params(ctypes.Structure):
 
 class swarm_request_info(ctypes.Structure):
     _fields_ = [("submit_s", _d), ("admit_s", _d), ("done_s", _d), ("n_real", _i64), ("epochs", _i64),
-                ("bytes", _i64), ("progress", _i64)]
+                ("bytes", _i64), ("progress", _i64), ("blocks_per_real", _d)]
 
 
 class swarm_server_stats_t(ctypes.Structure):

@@ -373,7 +373,10 @@ void scheduler(swarm_server* s) {
       n_ch = std::max(n_ch, d.nc);
       magnetic |= r->h->has_b;
       extended = std::max(extended, d.thermal_targets || d.relativistic ? 2 : d.trial_strategy != SWARM_TRIAL_CONSTANT ? 1 : 0);
-      r->epochs += 1;
+    }
+    {
+      std::lock_guard<std::mutex> lk(s->mu);   // swarm_server_poll reads the count
+      for (auto& r : act) r->epochs += 1;
     }
     const swarm_launch_opts o = resolve_opts(&s->p.opts, s->p.precision);
     const LdsLayout ll = lds_layout(s->p.precision, G, n_ch, o.service_waves, o.table_layout);
@@ -461,18 +464,18 @@ void scheduler(swarm_server* s) {
         r->done_coll = nd;
       }
       ++s->n_epochs;
-    }
-    // the measured requests' cost: blocks drawn per real collision since their last
-    // measurement, plus the collision's own work
-    for (size_t j = 0; j < meas.size(); ++j) {
-      Request& r = *act[meas[j]];
-      unsigned long long total = 0;
-      for (int k = 0; k < kEpochBlocksParts; ++k) total += parts[j * kEpochBlocksParts + k];
-      const double db = static_cast<double>(total - r.blocks_seen);
-      const double made = static_cast<double>(r.n_e) * static_cast<double>(r.done_coll - r.coll_seen);
-      if (made > 0 && total > r.blocks_seen) r.cost = db / made + kCollisionBlocks;
-      r.blocks_seen = total;
-      r.coll_seen = r.done_coll;
+      // the measured requests' cost: blocks drawn per real collision since their last
+      // measurement, plus the collision's own work
+      for (size_t j = 0; j < meas.size(); ++j) {
+        Request& r = *act[meas[j]];
+        unsigned long long total = 0;
+        for (int k = 0; k < kEpochBlocksParts; ++k) total += parts[j * kEpochBlocksParts + k];
+        const double db = static_cast<double>(total - r.blocks_seen);
+        const double made = static_cast<double>(r.n_e) * static_cast<double>(r.done_coll - r.coll_seen);
+        if (made > 0 && total > r.blocks_seen) r.cost = db / made + kCollisionBlocks;
+        r.blocks_seen = total;
+        r.coll_seen = r.done_coll;
+      }
     }
     if (ms > 0) {
       const double r_now = static_cast<double>(work) / (ms * 1e-3);
@@ -652,6 +655,7 @@ swarm_status swarm_server_poll(swarm_server_t s, int64_t ticket, swarm_tallies_t
     info->epochs = r.epochs;
     info->bytes = r.bytes;
     info->progress = r.n_e * r.done_coll;
+    info->blocks_per_real = r.cost > 0 ? r.cost - kCollisionBlocks : 0.0;
   }
   if (r.status == SWARM_PENDING) return SWARM_PENDING;
   if (r.status != SWARM_OK) return fail(r.status, "request %lld failed", static_cast<long long>(ticket));

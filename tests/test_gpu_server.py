@@ -84,6 +84,32 @@ def test_per_request_quanta_give_the_single_run_bits(gpu, schedule):
         sw.swarm_server_destroy(srv)
 
 
+def test_measured_blocks_per_real_match_the_records(gpu):
+    """The server measures a request's trial blocks per real collision by a reduction over its
+    electrons' state after the request's first epoch: for requests that finish in that epoch it
+    is the records' block counts summed over the request's real collisions."""
+    sw = gpu
+    reqs = [_shrink(c, 20000, 800) for c in _requests(4)]
+    srv = sw.swarm_server_create(64 << 30, sw.SWARM_FP32_MIXED, quantum_collisions=1000)
+    recs = {}
+    try:
+        tickets = []
+        for c in reqs:
+            t, rec = sw.swarm_server_submit_records(srv, c.components, sw.params_from_config(c, 1), c.n_electrons,
+                                                    c.n_collisions, c.seed)
+            tickets.append(t)
+            recs[t] = rec
+        res = _wait_all(sw, srv, tickets)
+    finally:
+        sw.swarm_server_destroy(srv)
+    for t in tickets:
+        tal, info = res[t]
+        assert info["epochs"] == 1
+        blocks = float(recs[t]["blocks"].astype(np.float64).sum())
+        assert blocks >= tal["n_real"]       # a block serves at most one real collision
+        assert info["blocks_per_real"] == pytest.approx(blocks / tal["n_real"], rel=1e-12)
+
+
 def _alone(sw, reqs, precision):
     out = []
     for c in reqs:
