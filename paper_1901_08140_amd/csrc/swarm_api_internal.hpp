@@ -105,6 +105,7 @@ struct swarm {
   swarm_impl::InstanceDesc* d_desc = nullptr;
   swarm_impl::DevBuf arena;                 // raw inputs, tables, descriptor, counters
   swarm_impl::DevBuf records, children, items;
+  swarm_impl::DevBuf parked;                 // real mode: electrons parked between launches (two buffers)
   std::vector<swarm_impl::WorkItem> h_items;
   swarm_impl::DevBuf trace_ids, trace_out, trace_count;
   int32_t n_trace = 0, max_events = 0;
@@ -128,7 +129,7 @@ struct swarm {
 
   void bind_arena(swarm_impl::Arena* a) {
     mem = a;
-    for (swarm_impl::DevBuf* b : {&arena, &records, &children, &items, &trace_ids, &trace_out, &trace_count})
+    for (swarm_impl::DevBuf* b : {&arena, &records, &children, &items, &parked, &trace_ids, &trace_out, &trace_count})
       b->arena = a;
     tally.bind(a);
   }

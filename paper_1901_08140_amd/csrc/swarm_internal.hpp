@@ -60,6 +60,19 @@ struct SavedState {
   uint32_t grace, n_fail;     // trials left before its next update; fails so far
 };
 
+// Real-secondaries runs: an electron a launch parked at a real-collision boundary (its
+// resumable state and its record slot), to be resumed by the next launch together with the
+// secondaries the launch created.
+struct ParkedState {
+  SavedState s;
+  int64_t rec;
+};
+
+// A wave parks only when at most kParkLanes of its 64 lanes still run, and at most once per
+// launch, so a launch of `threads` threads writes at most parked_capacity(threads) states.
+constexpr int kParkLanes = 32;
+constexpr int64_t parked_capacity(int64_t threads) { return threads / 64 * kParkLanes + 64; }
+
 // Secondary electron in the real-secondaries queue, written by the generation that
 // created it and run by the next one.
 struct ChildState {
@@ -80,7 +93,8 @@ struct RunCounters {
   uint64_t pad1[15];
   uint64_t dropped;       // secondaries that did not fit the capacity
   uint64_t n_done;        // dummy mode: electrons that reached their final collision or stopped
-  uint64_t pad2[14];
+  uint64_t parked;        // real mode: electrons the running launch parked for the next one
+  uint64_t pad2[13];
 };
 
 // One swarm instance as seen by the kernels.  Fields in the first group are written by
@@ -185,9 +199,17 @@ hipError_t launch_swarm_dummy(const InstanceDesc* d_desc, const WorkItem* d_item
                               int ext, int service_waves, int block_size, int grid, int pending_trigger,
                               size_t lds_bytes, int ch_off, int pool_off, int cum_off, hipStream_t s);
 size_t swarm_pool_slot_bytes(int precision);
+// One real-secondaries launch: the n_park_in electrons in park_in (parked by the launch
+// before), then `count` electrons from `first` (the primaries if first < 0, else queued
+// secondaries).  Once every electron is claimed, a wave left with few running lanes parks
+// them in park_out (at their next real-collision boundary) and ends, provided this launch has
+// created at least park_min secondaries (the queue started at tail0): the next launch runs
+// them together.  park_min <= 0 parks nothing.
 hipError_t launch_swarm_real(const InstanceDesc* d_desc, int precision, bool has_b, bool trace,
                              int ext, int block_size, int grid, int pending_trigger, size_t lds_bytes,
-                             int ch_off, int cum_off, int64_t first, int64_t count, int flush, hipStream_t s);
+                             int ch_off, int cum_off, int64_t first, int64_t count, int flush,
+                             const ParkedState* park_in, int64_t n_park_in, ParkedState* park_out,
+                             int64_t park_min, int64_t tail0, hipStream_t s);
 hipError_t launch_tallies(const InstanceDesc* d_desc, const TallyTile* d_tiles, int32_t n_tiles,
                           const int32_t* d_tile_base, const int64_t* d_nrec, int32_t n_inst,
                           double* d_part1, double* d_part2, double* d_tot1,

@@ -1139,9 +1139,10 @@ __device__ __forceinline__ void write_record(const InstanceDesc& d, const Lane<R
   d.records[L.rec] = r;
 }
 
+// Resumable state of a lane at a real-collision boundary (the anchor, T = 0): written at the
+// end of a serving epoch, or when a real-secondaries launch parks an electron for the next.
 template <typename R, int EXT>
-__device__ __forceinline__ void save_state(const InstanceDesc& d, const Lane<R>& L, const Consts<R>& C,
-                                           int64_t e) {
+__device__ __forceinline__ SavedState saved_of(const Lane<R>& L, const Consts<R>& C) {
   SavedState s;
   s.r[0] = L.rx; s.r[1] = L.ry; s.r[2] = L.rz;
   s.t = L.t;
@@ -1155,12 +1156,17 @@ __device__ __forceinline__ void save_state(const InstanceDesc& d, const Lane<R>&
   s.nup = static_cast<double>(EXT ? lane_nup(L) : C.nup);
   s.grace = EXT ? L.grace : 0u;
   s.n_fail = L.nfail;
-  d.saved[e] = s;
+  return s;
+}
+
+template <typename R, int EXT>
+__device__ __forceinline__ void save_state(const InstanceDesc& d, const Lane<R>& L, const Consts<R>& C,
+                                           int64_t e) {
+  d.saved[e] = saved_of<R, EXT>(L, C);
 }
 
 template <typename R, bool HB, int EXT>
-__device__ __forceinline__ void load_state(const InstanceDesc& d, Lane<R>& L, const Consts<R>& C, int64_t e) {
-  const SavedState s = d.saved[e];
+__device__ __forceinline__ void load_saved(const SavedState& s, Lane<R>& L, const Consts<R>& C) {
   L.rx = s.r[0]; L.ry = s.r[1]; L.rz = s.r[2];
   L.t = s.t;
   L.vx = static_cast<R>(s.v[0]); L.vy = static_cast<R>(s.v[1]); L.vz = static_cast<R>(s.v[2]);
@@ -1178,6 +1184,12 @@ __device__ __forceinline__ void load_state(const InstanceDesc& d, Lane<R>& L, co
   }
   L.nfail = s.n_fail;
   set_anchor<R, HB>(L, C);
+}
+
+template <typename R, bool HB, int EXT>
+__device__ __forceinline__ void load_state(const InstanceDesc& d, Lane<R>& L, const Consts<R>& C, int64_t e) {
+  const SavedState s = d.saved[e];
+  load_saved<R, HB, EXT>(s, L, C);
 }
 
 template <bool TR>
@@ -2048,9 +2060,17 @@ __global__ void __launch_bounds__(512) k_swarm_pooled(const InstanceDesc* __rest
 // atomic and hands them to its idle lanes by ballot rank, and it reads the overflow
 // counter once every 64 passes, so no pass waits on device-coherent memory.  With `flush`
 // set (the launch after an overflow) every electron is recorded as it was created.
+// A launch also resumes the electrons the launch before it parked (park_in, taken first).
+// Once all of its electrons are claimed, a wave that is down to a few running lanes, in a
+// launch that has created at least park_min secondaries so far, parks them: each lane
+// stops at its next real collision and writes its resumable state to park_out, and the
+// next launch runs them together with those secondaries instead of this launch idling
+// through their tail.  Parking moves no electron to another stream position, so the
+// results do not depend on it.
 // ---------------------------------------------------------------------------------------
 constexpr uint32_t kClaimChunk = 64;      // electrons a wave takes per claim
 constexpr uint32_t kAbortPoll = 64;       // passes between reads of the overflow counter
+constexpr uint32_t kParkPoll = 8;         // passes between a parking candidate's reads of the queue tail
 
 // A value the whole wave holds, kept in scalar registers.
 __device__ __forceinline__ int64_t wave_uniform(int64_t x) {
@@ -2063,7 +2083,9 @@ __device__ __forceinline__ int64_t wave_uniform(int64_t x) {
 template <typename R, bool HB, bool TR, int EXT>
 __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restrict__ desc, int pend_trig,
                                                     int ch_off, int cum_off, int64_t first, int64_t count,
-                                                    int flush) {
+                                                    int flush, const ParkedState* __restrict__ park_in,
+                                                    int64_t n_park_in, ParkedState* __restrict__ park_out,
+                                                    int64_t park_min, int64_t tail0) {
   using PT = typename Pair<R>::T;
   extern __shared__ __align__(16) unsigned char smem[];
   PT* s_nu = reinterpret_cast<PT*>(smem);
@@ -2101,8 +2123,9 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
   const uint64_t lane_lt = (1ull << __lane_id()) - 1ull;
   // wave-uniform: the wave's chunk [w_next, w_end), whether the generation is exhausted,
   // whether the run is stopping after an overflow, and the pass count
+  const int64_t total = n_park_in + count;   // parked electrons first, then the generation's
   int64_t w_next = 0, w_end = 0;
-  bool exhausted = false, aborting = flush != 0;
+  bool exhausted = false, aborting = flush != 0, parking = false;
   uint32_t pass = 0;
   for (;;) {
     const uint64_t idle = __ballot(L.state == ST_IDLE);
@@ -2114,8 +2137,8 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
           base = atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->gen_next),
                            static_cast<unsigned long long>(kClaimChunk));
         w_next = wave_uniform(static_cast<int64_t>(__shfl(base, leader)));
-        w_end = min(w_next + static_cast<int64_t>(kClaimChunk), count);
-        exhausted = w_next >= count;
+        w_end = min(w_next + static_cast<int64_t>(kClaimChunk), total);
+        exhausted = w_next >= total;
       }
       const int64_t avail = max(w_end - w_next, int64_t{0});
       const int64_t rank = static_cast<int64_t>(__popcll(idle & lane_lt));
@@ -2123,13 +2146,20 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
       w_next = wave_uniform(min(w_end, w_next + static_cast<int64_t>(__popcll(idle))));
       if (L.state == ST_IDLE && exhausted && avail == 0) L.state = ST_DONE;
       if (L.state == ST_IDLE && rank < avail) {
-        if (first < 0) {
-          init_primary<R, HB, EXT>(L, C, s_nu, e);
-          L.rec = static_cast<int64_t>(e);
+        if (e < n_park_in) {
+          // parked by the launch before, at a real-collision boundary
+          const ParkedState ps = park_in[e];
+          load_saved<R, HB, EXT>(ps.s, L, C);
+          L.rec = ps.rec;
+          L.k_stop = C.n_coll;
+          L.state = ST_ACTIVE;
+        } else if (first < 0) {
+          init_primary<R, HB, EXT>(L, C, s_nu, e - n_park_in);
+          L.rec = static_cast<int64_t>(e - n_park_in);
           L.k_stop = C.n_coll;
           L.state = ST_ACTIVE;
         } else {
-          const int64_t slot = first + static_cast<int64_t>(e);
+          const int64_t slot = first + static_cast<int64_t>(e - n_park_in);
           const ChildState cs = d.children[slot];
           L.rx = cs.r[0]; L.ry = cs.r[1]; L.rz = cs.r[2];
           L.t = cs.t;
@@ -2153,8 +2183,23 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
           L.state = ST_STOPPED;
         }
         if constexpr (TR) {
+          // a resumed electron goes on with the events it recorded before it was parked
           L.trace_slot = find_trace<TR>(d, L.id);
-          L.n_ev = 0;
+          L.n_ev = L.trace_slot >= 0 ? d.trace_count[L.trace_slot] : 0;
+        }
+      }
+    }
+    // Parking: all of the launch's electrons are claimed, few lanes of the wave still run,
+    // and this launch has created enough secondaries for the next one.  The running lanes
+    // stop at their next real collision (a ready lane at the one it is about to make).
+    if (park_min > 0 && exhausted && !parking && !aborting && pass % kParkPoll == 0) {
+      const int running = static_cast<int>(__popcll(__ballot(L.state == ST_ACTIVE || L.state == ST_READY)));
+      if (running > 0 && running <= kParkLanes) {
+        const int64_t made = wave_uniform(static_cast<int64_t>(__hip_atomic_load(
+                                              &ctr->child_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) - tail0;
+        if (made >= park_min) {
+          parking = true;
+          if (L.state == ST_ACTIVE || L.state == ST_READY) L.k_stop = min(L.k_stop, L.k + 1u);
         }
       }
     }
@@ -2198,9 +2243,27 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
       L.state = ST_STOPPED;
     }
     if (L.state == ST_STOPPED) {
-      if (L.k >= C.n_coll && !(L.flags & 10u)) L.flags |= 1u;   // attached or aborted: not finished
-      write_record(d, L);
-      L.state = ST_IDLE;
+      if (parking && L.k < C.n_coll && !(L.flags & 14u)) {
+        // parked (not attached, capped or aborted): resumed by the next launch.  The slots
+        // stay below parked_capacity of the launch's threads, which the host's buffers hold;
+        // past that a lane would run on.
+        const uint64_t ps = atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->parked), 1ull);
+        if (ps < static_cast<uint64_t>(parked_capacity(static_cast<int64_t>(gridDim.x) * blockDim.x))) {
+          ParkedState p;
+          p.s = saved_of<R, EXT>(L, C);
+          p.rec = L.rec;
+          park_out[ps] = p;
+          L.state = ST_DONE;
+        } else {
+          L.k_stop = C.n_coll;
+          set_anchor<R, HB>(L, C);
+          L.state = ST_ACTIVE;
+        }
+      } else {
+        if (L.k >= C.n_coll && !(L.flags & 10u)) L.flags |= 1u;   // attached or aborted: not finished
+        write_record(d, L);
+        L.state = ST_IDLE;
+      }
     }
     if (__ballot(L.state != ST_DONE) == 0) break;
   }
@@ -2519,9 +2582,12 @@ hipError_t launch_swarm_dummy(const InstanceDesc* d_desc, const WorkItem* d_item
 
 hipError_t launch_swarm_real(const InstanceDesc* d_desc, int precision, bool has_b, bool trace,
                              int ext, int block_size, int grid, int pending_trigger, size_t lds_bytes,
-                             int ch_off, int cum_off, int64_t first, int64_t count, int flush, hipStream_t s) {
+                             int ch_off, int cum_off, int64_t first, int64_t count, int flush,
+                             const ParkedState* park_in, int64_t n_park_in, ParkedState* park_out,
+                             int64_t park_min, int64_t tail0, hipStream_t s) {
   void* fn = pick_kernel(precision, has_b, trace, true, ext);
-  void* args[] = {const_cast<InstanceDesc**>(&d_desc), &pending_trigger, &ch_off, &cum_off, &first, &count, &flush};
+  void* args[] = {const_cast<InstanceDesc**>(&d_desc), &pending_trigger, &ch_off, &cum_off, &first, &count, &flush,
+                  const_cast<ParkedState**>(&park_in), &n_park_in, &park_out, &park_min, &tail0};
   return hipLaunchKernel(fn, dim3(grid), dim3(block_size), args, lds_bytes, s);
 }
 
