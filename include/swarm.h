@@ -303,6 +303,12 @@ swarm_status swarm_tables(swarm_t h, int32_t* grid_size, int32_t* n_channels, do
  * (simulation plus tallies). */
 swarm_status swarm_last_timing(swarm_t h, double* kernel_ms, double* total_ms);
 
+/* Launches of the last run's simulation kernel (one in DUMMY mode; in REAL mode one per
+ * generation, and more where the stragglers of a launch were parked for the next one, see
+ * swarm_launch_opts.park_lanes) and the electrons parked between them in all.  Either pointer
+ * may be NULL.  SWARM_ERR_STATE before the first completed run. */
+swarm_status swarm_last_launches(swarm_t h, int64_t* launches, int64_t* parked);
+
 /* For callers that cannot allocate device memory (code under HIP graph capture, serving
  * loops that must not call hipMalloc, harnesses that forbid it): the DUMMY-mode run of
  * swarm_run with no allocation.  The caller passes `records`, device memory for n_electrons
@@ -346,6 +352,11 @@ typedef struct {
                               descriptors (running sums read through L2); 1 also the running
                               sums of every channel, when they fit the work-group's LDS
                               (otherwise 0) */
+  int32_t park_lanes;      /* real secondaries: once all electrons of a launch are claimed, a
+                              wave with at most this many running lanes parks them (each at its
+                              next real collision) for the next launch, if the launch has
+                              created secondaries for an eighth of the device; 0: 32, -1: never,
+                              at most 64 */
 } swarm_launch_opts;
 
 /* Launch shape of the handle's own runs (swarm_run); zero fields take the defaults.  Like

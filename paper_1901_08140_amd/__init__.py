@@ -85,7 +85,7 @@ class swarm_job(ctypes.Structure):
 
 class swarm_launch_opts(ctypes.Structure):
     _fields_ = [("block_size", _i32), ("chunk", _i32), ("pending_trigger", _i32), ("use_graph", _i32),
-                ("service_waves", _i32), ("table_layout", _i32)]
+                ("service_waves", _i32), ("table_layout", _i32), ("park_lanes", _i32)]
 
 
 class swarm_server_params(ctypes.Structure):
@@ -134,6 +134,7 @@ _SIGS = {
     "swarm_trace_events": (_i32, [_vp, _vp, _P(_i32)]),
     "swarm_tables": (_i32, [_vp, _P(_i32), _P(_i32), _P(_d), _P(_d), _P(_d)]),
     "swarm_last_timing": (_i32, [_vp, _P(_d), _P(_d)]),
+    "swarm_last_launches": (_i32, [_vp, _P(_i64), _P(_i64)]),
     "swarm_destroy": (None, [_vp]),
     "swarm_strerror": (ctypes.c_char_p, [_i32]),
     "swarm_last_error": (ctypes.c_char_p, []),
@@ -336,6 +337,13 @@ def swarm_last_timing(h):
     return k.value, t.value
 
 
+def swarm_last_launches(h):
+    """(simulation launches, electrons parked between them) of the last run."""
+    n, p = _i64(0), _i64(0)
+    _check(_lib.swarm_last_launches(h, ctypes.byref(n), ctypes.byref(p)))
+    return n.value, p.value
+
+
 def swarm_destroy(h):
     if h:
         _lib.swarm_destroy(h)
@@ -523,6 +531,9 @@ class Swarm:
 
     def timing(self):
         return swarm_last_timing(self.h)
+
+    def launches(self):
+        return swarm_last_launches(self.h)
 
     def set_trace(self, ids, max_events):
         self._trace = swarm_set_trace(self.h, ids, max_events)

@@ -409,6 +409,7 @@ swarm_launch_opts resolve_opts(const swarm_launch_opts* o, int precision) {
   r.pending_trigger = std::max(1, std::min(64, r.pending_trigger));
   r.service_waves = o ? std::max(0, std::min(r.block_size / 64 - 1, o->service_waves)) : 0;
   r.table_layout = (o && o->table_layout == 1) ? 1 : 0;
+  r.park_lanes = (o && o->park_lanes) ? std::max(-1, std::min(64, o->park_lanes)) : kParkLanes;
   return r;
 }
 
@@ -640,7 +641,7 @@ swarm_status swarm_arena_bytes(const swarm_component* comps, int32_t n_comps, co
   size_t run = blk(static_cast<size_t>(capacity) * sizeof(swarm_record)) + tally_bytes(capacity);
   if (real && capacity > n_electrons) run += blk(static_cast<size_t>(capacity - n_electrons) * sizeof(ChildState));
   // real mode: the two buffers of parked electrons, for the most lanes a device can hold
-  if (real) run += blk(2 * static_cast<size_t>(parked_capacity(static_cast<int64_t>(device_info().n_cu) * 2048)) * sizeof(ParkedState));
+  if (real) run += blk(2 * static_cast<size_t>(parked_capacity(static_cast<int64_t>(device_info().n_cu) * 2048, 64)) * sizeof(ParkedState));
   // dummy-mode work items: at most one per 64 electrons (the smallest work-group), plus the counter
   if (!real) run += blk(static_cast<size_t>((n_electrons + 63) / 64) * sizeof(WorkItem) + 256);
   *bytes = static_cast<int64_t>(blk(tables) + run);
@@ -770,6 +771,8 @@ swarm_status run_start(swarm_t h, int64_t n_electrons, int64_t n_collisions, uin
                                 d_ctr, d.precision, h->has_b, trace, ext, svc, o.block_size, grid, o.pending_trigger, lds, ch_off,
                                 ll.pool_off, ll.cum_off, s)) != hipSuccess)
       return hip_fail(e, "swarm kernel launch");
+    h->n_launches = 1;
+    h->n_parked = 0;
   }
   RunCounters hc{};
   if (real) {
@@ -783,22 +786,26 @@ swarm_status run_start(swarm_t h, int64_t n_electrons, int64_t n_collisions, uin
     // argon:CO2 mixture at 1 T: FP32 399 -> 372 ms, FP64 1004 -> 966 ms; waves of at most 16
     // running lanes parking after half a device of secondaries: 379 and 988 ms).
     const int64_t lanes = static_cast<int64_t>(dev.n_cu) * per_cu * o.block_size;
-    const int64_t park_cap = parked_capacity(lanes);
+    const int park_lanes = std::max(0, o.park_lanes);   // -1: never
+    const int64_t park_cap = parked_capacity(lanes, park_lanes);
     if ((e = h->parked.ensure(2 * static_cast<size_t>(park_cap) * sizeof(ParkedState))) != hipSuccess)
       return hip_fail(e, "allocating parked electrons");
     ParkedState* park_in = static_cast<ParkedState*>(h->parked.p);
     ParkedState* park_out = park_in + park_cap;
     int64_t first = -1, count = n_electrons, queued = 0, n_parked = 0;
+    h->n_launches = 0;
+    h->n_parked = 0;
     for (;;) {
       if ((e = launch_fill_u64(&d.ctr->gen_next, 0ull, 1, s)) != hipSuccess) return hip_fail(e, "generation counter");
       if ((e = launch_fill_u64(&d.ctr->parked, 0ull, 1, s)) != hipSuccess) return hip_fail(e, "park counter");
       const int64_t want = (n_parked + count + o.block_size - 1) / o.block_size;
       const int grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want * 4, static_cast<int64_t>(dev.n_cu) * per_cu)));
-      const int64_t park_min = hc.dropped != 0 ? 0 : std::max<int64_t>(1, lanes / 8);
+      const int64_t park_min = hc.dropped != 0 || park_lanes == 0 ? 0 : std::max<int64_t>(1, lanes / 8);
       if ((e = launch_swarm_real(h->d_desc, d.precision, h->has_b, trace, ext, o.block_size, grid, o.pending_trigger, lds,
                                  ch_off, ll.cum_off, first, count, hc.dropped != 0 ? 1 : 0, park_in, n_parked, park_out,
-                                 park_min, queued, s)) != hipSuccess)
+                                 park_min, park_lanes, queued, s)) != hipSuccess)
         return hip_fail(e, "swarm kernel launch");
+      h->n_launches += 1;
       if ((e = hipMemcpyAsync(&hc, d.ctr, sizeof(hc), hipMemcpyDeviceToHost, s)) != hipSuccess) return hip_fail(e, "counters");
       if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "swarm kernel");
       const int64_t tail = std::min<int64_t>(static_cast<int64_t>(hc.child_tail), child_cap);
@@ -806,7 +813,9 @@ swarm_status run_start(swarm_t h, int64_t n_electrons, int64_t n_collisions, uin
       first = queued;
       count = tail - queued;
       queued = tail;
-      n_parked = std::min<int64_t>(static_cast<int64_t>(hc.parked), parked_capacity(static_cast<int64_t>(grid) * o.block_size));
+      n_parked = std::min<int64_t>(static_cast<int64_t>(hc.parked),
+                                   parked_capacity(static_cast<int64_t>(grid) * o.block_size, park_lanes));
+      h->n_parked += n_parked;
       std::swap(park_in, park_out);
     }
   }
@@ -961,6 +970,15 @@ swarm_status swarm_last_timing(swarm_t h, double* kernel_ms, double* total_ms) {
   if (!h->have_run) return fail(SWARM_ERR_STATE, "no completed run");
   if (kernel_ms) *kernel_ms = h->kernel_ms;
   if (total_ms) *total_ms = h->total_ms;
+  return SWARM_OK;
+}
+
+swarm_status swarm_last_launches(swarm_t h, int64_t* launches, int64_t* parked) {
+  if (!h) return fail(SWARM_ERR_INVALID_ARG, "handle is NULL");
+  if (h->in_flight) return busy();
+  if (!h->have_run) return fail(SWARM_ERR_STATE, "no completed run");
+  if (launches) *launches = h->n_launches;
+  if (parked) *parked = h->n_parked;
   return SWARM_OK;
 }
 

@@ -116,6 +116,7 @@ struct swarm {
   bool have_run = false;
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
   double kernel_ms = 0.0, total_ms = 0.0;
+  int64_t n_launches = 0, n_parked = 0;     // the last run's simulation launches, parked electrons
   swarm_launch_opts opts{};
   // a run started by swarm_run_async: 1 enqueued on the stream (dummy mode), 2 running on
   // `worker` (real mode, whose generations need the host between launches)

@@ -68,10 +68,11 @@ struct ParkedState {
   int64_t rec;
 };
 
-// A wave parks only when at most kParkLanes of its 64 lanes still run, and at most once per
-// launch, so a launch of `threads` threads writes at most parked_capacity(threads) states.
+// A wave parks only when at most park_lanes of its 64 lanes still run (by default
+// kParkLanes), and at most once per launch, so a launch of `threads` threads writes at most
+// parked_capacity(threads, park_lanes) states.
 constexpr int kParkLanes = 32;
-constexpr int64_t parked_capacity(int64_t threads) { return threads / 64 * kParkLanes + 64; }
+constexpr int64_t parked_capacity(int64_t threads, int park_lanes) { return threads / 64 * park_lanes + 64; }
 
 // Secondary electron in the real-secondaries queue, written by the generation that
 // created it and run by the next one.
@@ -204,12 +205,13 @@ size_t swarm_pool_slot_bytes(int precision);
 // secondaries).  Once every electron is claimed, a wave left with few running lanes parks
 // them in park_out (at their next real-collision boundary) and ends, provided this launch has
 // created at least park_min secondaries (the queue started at tail0): the next launch runs
-// them together.  park_min <= 0 parks nothing.
+// them together; park_lanes is the most running lanes a parking wave may have.  park_min <= 0
+// parks nothing.
 hipError_t launch_swarm_real(const InstanceDesc* d_desc, int precision, bool has_b, bool trace,
                              int ext, int block_size, int grid, int pending_trigger, size_t lds_bytes,
                              int ch_off, int cum_off, int64_t first, int64_t count, int flush,
                              const ParkedState* park_in, int64_t n_park_in, ParkedState* park_out,
-                             int64_t park_min, int64_t tail0, hipStream_t s);
+                             int64_t park_min, int park_lanes, int64_t tail0, hipStream_t s);
 hipError_t launch_tallies(const InstanceDesc* d_desc, const TallyTile* d_tiles, int32_t n_tiles,
                           const int32_t* d_tile_base, const int64_t* d_nrec, int32_t n_inst,
                           double* d_part1, double* d_part2, double* d_tot1,

@@ -2061,8 +2061,8 @@ __global__ void __launch_bounds__(512) k_swarm_pooled(const InstanceDesc* __rest
 // counter once every 64 passes, so no pass waits on device-coherent memory.  With `flush`
 // set (the launch after an overflow) every electron is recorded as it was created.
 // A launch also resumes the electrons the launch before it parked (park_in, taken first).
-// Once all of its electrons are claimed, a wave that is down to a few running lanes, in a
-// launch that has created at least park_min secondaries so far, parks them: each lane
+// Once all of its electrons are claimed, a wave that is down to park_lanes running lanes or
+// fewer, in a launch that has created at least park_min secondaries so far, parks them: each lane
 // stops at its next real collision and writes its resumable state to park_out, and the
 // next launch runs them together with those secondaries instead of this launch idling
 // through their tail.  Parking moves no electron to another stream position, so the
@@ -2085,7 +2085,7 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
                                                     int ch_off, int cum_off, int64_t first, int64_t count,
                                                     int flush, const ParkedState* __restrict__ park_in,
                                                     int64_t n_park_in, ParkedState* __restrict__ park_out,
-                                                    int64_t park_min, int64_t tail0) {
+                                                    int64_t park_min, int park_lanes, int64_t tail0) {
   using PT = typename Pair<R>::T;
   extern __shared__ __align__(16) unsigned char smem[];
   PT* s_nu = reinterpret_cast<PT*>(smem);
@@ -2194,7 +2194,7 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
     // stop at their next real collision (a ready lane at the one it is about to make).
     if (park_min > 0 && exhausted && !parking && !aborting && pass % kParkPoll == 0) {
       const int running = static_cast<int>(__popcll(__ballot(L.state == ST_ACTIVE || L.state == ST_READY)));
-      if (running > 0 && running <= kParkLanes) {
+      if (running > 0 && running <= park_lanes) {
         const int64_t made = wave_uniform(static_cast<int64_t>(__hip_atomic_load(
                                               &ctr->child_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) - tail0;
         if (made >= park_min) {
@@ -2248,7 +2248,7 @@ __global__ void __launch_bounds__(512) k_swarm_real(const InstanceDesc* __restri
         // stay below parked_capacity of the launch's threads, which the host's buffers hold;
         // past that a lane would run on.
         const uint64_t ps = atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->parked), 1ull);
-        if (ps < static_cast<uint64_t>(parked_capacity(static_cast<int64_t>(gridDim.x) * blockDim.x))) {
+        if (ps < static_cast<uint64_t>(parked_capacity(static_cast<int64_t>(gridDim.x) * blockDim.x, park_lanes))) {
           ParkedState p;
           p.s = saved_of<R, EXT>(L, C);
           p.rec = L.rec;
@@ -2584,10 +2584,10 @@ hipError_t launch_swarm_real(const InstanceDesc* d_desc, int precision, bool has
                              int ext, int block_size, int grid, int pending_trigger, size_t lds_bytes,
                              int ch_off, int cum_off, int64_t first, int64_t count, int flush,
                              const ParkedState* park_in, int64_t n_park_in, ParkedState* park_out,
-                             int64_t park_min, int64_t tail0, hipStream_t s) {
+                             int64_t park_min, int park_lanes, int64_t tail0, hipStream_t s) {
   void* fn = pick_kernel(precision, has_b, trace, true, ext);
   void* args[] = {const_cast<InstanceDesc**>(&d_desc), &pending_trigger, &ch_off, &cum_off, &first, &count, &flush,
-                  const_cast<ParkedState**>(&park_in), &n_park_in, &park_out, &park_min, &tail0};
+                  const_cast<ParkedState**>(&park_in), &n_park_in, &park_out, &park_min, &park_lanes, &tail0};
   return hipLaunchKernel(fn, dim3(grid), dim3(block_size), args, lds_bytes, s);
 }
 
