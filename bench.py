@@ -443,9 +443,10 @@ def anisotropic_leg(sw, args, cfgs, jobs, opts, tall_const, ms_const):
 def real_secondaries_leg(sw, args, n_electrons=1_000_000, n_collisions=2000):
     """The real-secondaries kernel on the 90:10 argon-like:CO2-like mixture at 100 Td, B = 1 T at
     45 degrees: 1e6 primaries, with the largest collision budget whose lineage growth fits the
-    default capacity.  FP32-mixed and FP64 single runs (one launch of the persistent kernel
-    each, after a small warm-up run): throughput, electrons created and attached, and how the
-    FP32 tallies agree with the FP64 ones."""
+    default capacity.  FP32-mixed and FP64 single runs (a launch per generation, with the
+    stragglers parked for the next, after a small warm-up run): throughput, launches and
+    electrons parked, electrons created and attached, and how the FP32 tallies agree with the
+    FP64 ones."""
     import torch
     import synth
     cfg = synth.cfg3_mixture_real(n_electrons=n_electrons, n_collisions=n_collisions)
@@ -461,12 +462,14 @@ def real_secondaries_leg(sw, args, n_electrons=1_000_000, n_collisions=2000):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         kernel_ms, total_ms = s.timing()
+        launches, parked = s.launches()
         t = s.tallies()
         tall[name] = t
         out[name] = {"value": t["n_real"] / wall, "unit": "real collisions/s", "seconds": wall,
                      "kernel_ms": kernel_ms, "device_ms": total_ms, "n_real": t["n_real"],
                      "efficiency": t["efficiency"], "n_electrons": t["n_electrons"],
-                     "n_created": t["n_created"], "n_attached": t["n_attached"], "n_dropped": t["n_dropped"]}
+                     "n_created": t["n_created"], "n_attached": t["n_attached"], "n_dropped": t["n_dropped"],
+                     "launches": launches, "parked": parked}
         s.close()
     keys = ["W", "Wx", "Wy", "mean_energy", "D_vec", "alpha"]
     out["fp32_vs_fp64_within_tolerance"] = f"{agreement(tall['fp32'], tall['fp64'], keys)}/{len(keys)}"
