@@ -331,9 +331,10 @@ void scheduler(swarm_server* s) {
     }
     if (act.empty()) continue;
     if (s->p.schedule == SWARM_SCHEDULE_SHORTEST_FIRST && act.size() > 1) act = pick_shortest_first(act);
-    // epoch quanta: fixed, or sized so that an epoch lasts about 100 ms (a stream of
-    // random-mixture requests at 50 req/s over 40 s: 1.22e10 real/s served with 50 ms epochs,
-    // 1.30e10 with 100 ms, 1.32e10 with 200 ms; p50 1.27-1.31 s for all three).  Once trial
+    // epoch quanta: fixed, or sized so that an epoch lasts about 100 ms (with one quantum for
+    // every request, a stream of random-mixture requests at 50 req/s over 40 s served 1.22e10
+    // real/s with 50 ms epochs, 1.30e10 with 100 ms, 1.32e10 with 200 ms; p50 1.27-1.31 s for
+    // all three).  Once trial
     // blocks per real collision have been measured, every electron of the epoch gets about the
     // same number of trial blocks: a request whose gas makes many null trials per real
     // collision gets fewer real collisions, so that its electrons do not keep the device
