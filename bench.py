@@ -58,7 +58,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--electrons", type=int, default=100_000)
     ap.add_argument("--collisions", type=int, default=20_000)
     ap.add_argument("--no-fp64", action="store_true")
