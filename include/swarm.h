@@ -368,7 +368,11 @@ typedef struct swarm_batch* swarm_batch_t;
 /* A batch of instances (all DUMMY mode, all the same precision) with one job each.  The
  * batch keeps the per-instance results on the device; swarm_batch_launch runs every job
  * in one persistent kernel (work items of `chunk` electrons, instance tables staged in
- * LDS), followed by the tally kernels, captured once in a hipGraph when use_graph != 0. */
+ * LDS), followed by the tally kernels, captured in a hipGraph when use_graph != 0.  The
+ * first launch hands out the instances' items heaviest collision budget first, then in the
+ * order given; swarm_batch_wait of the first launch orders them again by each instance's
+ * measured work per electron (trials per real collision), longest first, for the launches
+ * after it.  The order changes no result. */
 swarm_status swarm_batch_create(swarm_t* handles, const swarm_job* jobs, int32_t n,
                                 const swarm_launch_opts* opts, swarm_batch_t* out);
 swarm_status swarm_batch_launch(swarm_batch_t b);                  /* asynchronous */

@@ -340,19 +340,19 @@ hipError_t TallyPlan::launch(const InstanceDesc* d_descs, hipStream_t s) {
                         static_cast<double*>(d_tot.p), static_cast<swarm_tallies_t*>(d_out.p), s);
 }
 
-// Work items of `chunk` electrons per instance, heaviest collision budgets first so that
-// the long items start early and the persistent grid drains evenly.
-// Work items: instances with the largest collision budgets first.  An item holds up to
-// `chunk` electrons; when `slots` (resident work-groups) is given, an instance's items are
-// cut smaller, down to one electron per lane (`block`), so that no item holds much more
-// than 1/slots of the launch's work (electrons x collisions) and a small launch still
-// spreads over the whole GPU.
+// Work items: instances with the largest collision budgets first (or the largest `rank`, the
+// expected device work per electron, where the caller measured it), so that the long items
+// start early and the persistent grid drains evenly.  An item holds up to `chunk` electrons;
+// when `slots` (resident work-groups) is given, an instance's items are cut smaller, down to
+// one electron per lane (`block`), so that no item holds much more than 1/slots of the
+// launch's work (electrons x collisions) and a small launch still spreads over the whole GPU.
 void make_items(const std::vector<int64_t>& n_e, const std::vector<int64_t>& n_c, int64_t chunk,
-                std::vector<WorkItem>& items, int64_t slots, int64_t block) {
+                std::vector<WorkItem>& items, int64_t slots, int64_t block, const std::vector<double>* rank) {
   items.clear();
   std::vector<int> order(n_e.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = static_cast<int>(i);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n_c[a] > n_c[b]; });
+  if (rank) std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return (*rank)[a] > (*rank)[b]; });
+  else std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n_c[a] > n_c[b]; });
   double total = 0.0;
   for (size_t i = 0; i < n_e.size(); ++i) total += static_cast<double>(n_e[i]) * static_cast<double>(n_c[i]);
   // Guided sizes: the last part of the work (about one item of two electrons per lane for

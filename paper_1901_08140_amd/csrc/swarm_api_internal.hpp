@@ -80,8 +80,12 @@ struct LdsLayout {
   int cum_off;     // running sums staged at this offset, or -1 (read from global memory)
 };
 LdsLayout lds_layout(int precision, int G, int nc, int service_waves, int table_layout);
+// Work items of `chunk` electrons (fewer towards the end of the launch), instance by instance:
+// the heaviest collision budget first, or the largest `rank` first where one is given (the
+// expected device work per electron); instances of equal rank in the caller's order.
 void make_items(const std::vector<int64_t>& n_e, const std::vector<int64_t>& n_c, int64_t chunk,
-                std::vector<WorkItem>& items, int64_t slots, int64_t block);
+                std::vector<WorkItem>& items, int64_t slots, int64_t block,
+                const std::vector<double>* rank = nullptr);
 swarm_launch_opts resolve_opts(const swarm_launch_opts* o, int precision);
 // Builds a swarm handle (validation, tables); with `mem` every device allocation of the
 // handle comes from that caller-owned region.

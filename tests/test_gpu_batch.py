@@ -101,3 +101,24 @@ def test_batch_rejects_real_mode_and_mixed_precision(gpu):
     c = sw.Swarm.from_config(synth.cfg3_mixture_real(), sw.SWARM_FP64)
     with pytest.raises(sw.SwarmError):
         sw.swarm_batch_run([c.h], [(10, 10, 0)])
+
+
+def test_reordered_launches_give_the_same_bits(gpu):
+    """After its first launch a batch orders its items by each instance's measured work per
+    electron; the launches after it, in that order, give the bits of the first (instances
+    listed fast ones first, so the order does change)."""
+    sw = gpu
+    cfgs = list(reversed(synth.cfg2_argon_sweep()))[::4]
+    jobs = [(20000, 500, 3 + i) for i in range(len(cfgs))]
+    hs = [sw.Swarm.from_config(c, sw.SWARM_FP32_MIXED) for c in cfgs]
+    b = sw.swarm_batch_create([h.h for h in hs], jobs, {"use_graph": 1})
+    try:
+        sw.swarm_batch_launch(b)
+        sw.swarm_batch_wait(b)
+        first = [h.records().tobytes() for h in hs]
+        for _ in range(2):
+            sw.swarm_batch_launch(b)
+            sw.swarm_batch_wait(b)
+            assert [h.records().tobytes() for h in hs] == first
+    finally:
+        sw.swarm_batch_destroy(b)
