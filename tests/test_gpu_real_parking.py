@@ -32,6 +32,25 @@ def test_parking_changes_no_record(gpu, precision):
         assert out[park][0].tobytes() == out[-1][0].tobytes(), park
 
 
+def test_parking_changes_no_traced_event(gpu):
+    """The traced kernel parks too: the event sequences of primaries claimed first and last
+    (the last ones run in the waves that park) are the same with eager parking as without."""
+    sw = gpu
+    cfg = synth.cfg3_mixture_real(n_electrons=200_000, n_collisions=1000)
+    ids = [0, 1, 100_000] + list(range(199_990, 200_000))
+    out = {}
+    for park in (-1, 64):
+        s = sw.Swarm.from_config(cfg, sw.SWARM_FP64)
+        s.set_launch_opts({"park_lanes": park})
+        s.set_trace(ids, 2048)
+        s.run(cfg.n_electrons, cfg.n_collisions, 3)
+        ev, counts = s.trace_events()
+        out[park] = (ev.tobytes(), counts.tolist(), s.launches()[1])
+    assert out[64][2] > 0
+    assert out[64][1] == out[-1][1]
+    assert out[64][0] == out[-1][0]
+
+
 def test_parked_lineages_equal_the_oracle(gpu):
     """Eager parking on a run of 50,000 primaries: the whole lineages of sampled primaries
     equal the oracle's records, each lineage computed on its own."""
