@@ -181,6 +181,8 @@ swarm_status swarm_run_noalloc(swarm_t h, int64_t n_electrons, int64_t n_collisi
   h->n_records = n_electrons;
   h->noalloc_records = true;
   h->traced = false;
+  h->n_launches = 1;
+  h->n_parked = 0;
   h->have_run = true;
   return SWARM_OK;
 }
