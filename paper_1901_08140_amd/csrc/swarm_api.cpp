@@ -784,7 +784,8 @@ swarm_status run_start(swarm_t h, int64_t n_electrons, int64_t n_collisions, uin
     // created secondaries for at least an eighth of the device's lanes lets its last few
     // running electrons park, and the next launch resumes them first (1e6 primaries of the
     // argon:CO2 mixture at 1 T: FP32 399 -> 372 ms, FP64 1004 -> 966 ms; waves of at most 16
-    // running lanes parking after half a device of secondaries: 379 and 988 ms).
+    // running lanes parking after half a device of secondaries: 379 and 988 ms; 48 lanes after
+    // a sixteenth: 384 and 960 ms).
     const int64_t lanes = static_cast<int64_t>(dev.n_cu) * per_cu * o.block_size;
     const int park_lanes = std::max(0, o.park_lanes);   // -1: never
     const int64_t park_cap = parked_capacity(lanes, park_lanes);
