@@ -1563,15 +1563,13 @@ __device__ __forceinline__ int real_collision(const InstanceDesc& d, Lane<R>& L,
     R c_ela, c_M, c_mM, thr;
     if constexpr (sizeof(R) == 8) { c_ela = ch.c_ela; c_M = ch.c_M; c_mM = ch.c_mM; thr = ch.thr; }
     else { c_ela = ch.c_ela_f; c_M = ch.c_M_f; c_mM = ch.c_mM_f; thr = ch.thr_f; }
-    if constexpr (sizeof(R) == 4 && EXT == 0) {
-      // FP32 with the constant trial frequency: one branch-free evaluation for every kind.
-      // With the threshold taken as 0 for an elastic channel, ratio = 0 and root = 1 make eq.
-      // delta_energy_ine round exactly as eq. delta_energy_ela (1 + c (cos - 1) is
-      // 1 - c (1 - cos) negated twice); attachment (plastic) selects 0.  Mixed-kind passes then
-      // run no divergent branches: 788 -> 781 ms per argon-sweep step, identical records.  The
-      // adaptive kernels keep the branches (the branch-free form made their steps 1.6-2.2%
-      // slower: their collision passes are a larger share, and all-elastic ones then evaluate
-      // the inelastic terms too).
+    if constexpr (sizeof(R) == 4) {
+      // FP32: one branch-free evaluation for every kind.  With the threshold taken as 0 for
+      // an elastic channel, ratio = 0 and root = 1 make eq. delta_energy_ine round exactly as
+      // eq. delta_energy_ela (1 + c (cos - 1) is 1 - c (1 - cos) negated twice); attachment
+      // (plastic) selects 0.  Mixed-kind passes then run no divergent branches.  Same box,
+      // interleaved, identical records: argon-sweep step 784-785 against 787-788 ms; variable
+      // trial frequency 611 against 617 ms, binned 636-637 against 632-633 ms.
       const float th = ch.kind == SWARM_ELASTIC ? 0.0f : thr;
       const float ratio = th * __builtin_amdgcn_rcpf(eps);
       const float root = sqrt_(fmaxf(0.0f, 1.0f - c_mM * ratio));
